@@ -1,0 +1,875 @@
+/*
+ * Plain FP64 CPU oracle of per-column multi-level accelerated
+ * Lambda-iteration (MALI).  TEST INFRASTRUCTURE ONLY: only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.  It shares
+ * no code with the GPU library; parity between the two is the point.
+ *
+ * What it follows.  The paper (Sec. 2.1) names the method: MALI in the
+ * Rybicki & Hummer (1992) formalism with a local (diagonal) approximate
+ * Psi operator, preconditioned rate equations and overlapping transitions;
+ * it writes none of the equations.  The steps below are the standard
+ * published forms of those methods, in this order per iteration:
+ *   1. opacity and emissivity of every ray from the current populations;
+ *   2. formal solution along every (wavelength, angle, direction) ray with
+ *      linear short characteristics (Olson & Kunasz 1987), giving I, the
+ *      diagonal Lambda* and Psi* = Lambda* over chi, and the effective intensity
+ *      I_eff = I - Psi* eta_atom (Sec. 2.1: local approximate Psi operator);
+ *   3. accumulation of the preconditioned radiative rates (Sec. 2.1:
+ *      preconditioning of the rate equations, overlapping transitions);
+ *   4. statistical equilibrium per depth, linear in the new populations,
+ *      with particle conservation replacing one equation;
+ *   5. maximum relative population change (Sec. 2.3, the convergence
+ *      measure of Fig. 1) and Ng extrapolation (Sec. 2.3, Ng 1974 / Auer).
+ * Start solutions: LTE and zero radiation (Sec. 2.3, "Different starting
+ * solutions").  Collisional-radiative switching (Sec. 2.3) is available
+ * as a constant collision multiplier.  Output: emergent vertical intensity
+ * (Sec. 2.2: only vertical emergent spectra) and per-transition Psi*.
+ *
+ * Everything is SI.  Depth index k = 0 is the top (largest z).
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <ctype.h>
+
+/* CODATA 2018 */
+#define PH 6.62607015e-34
+#define PC 2.99792458e8
+#define PKB 1.380649e-23
+#define PME 9.1093837015e-31
+#define PQE 1.602176634e-19
+#define PEPS0 8.8541878128e-12
+#define PAMU 1.66053906660e-27
+#define PPI 3.14159265358979323846
+/* electron-impact rate constant of the Omega collision model, m^3 s^-1 K^1/2 */
+#define COLL_C0 8.629e-12
+/* reference wavelength of the background opacity law */
+#define BG_LAMBDA_REF 500.0e-9
+#define BG_THETA 8750.0
+/* below this optical step the short-characteristic weights use their series */
+#define SC_SERIES_X 1.0e-2
+
+static __thread char orc_err[256];
+const char *orc_last_error(void) { return orc_err; }
+#define FAIL(code, ...) do { snprintf(orc_err, sizeof orc_err, __VA_ARGS__); return (code); } while (0)
+
+typedef struct {
+    int kind;           /* 0 bound-bound line, 1 bound-free continuum */
+    int l, u;
+    double f;           /* line absorption oscillator strength */
+    int voigt;          /* line: 1 Voigt profile, 0 Gaussian */
+    int coll_kind;      /* 0: Omega model, 1: fixed destruction probability eps */
+    double coll_val;
+    double alpha0;      /* continuum cross-section at the edge, m^2 */
+    int n_own;
+    double *lam_own;    /* the transition's own wavelengths, m */
+    /* derived */
+    double nu0, Aul, Bul, Blu, gamma_rad;
+    double lam_min, lam_max;
+    int n_act;
+    int *act;           /* indices into the union grid, increasing wavelength */
+    double *wnu;        /* trapezoid weights in frequency over the active points */
+} orc_trans;
+
+typedef struct orc_atom {
+    double mass, abund;
+    int L;
+    double *E, *g;
+    int *stage;
+    int n_lines, n_cont, T;   /* transitions: lines first, then continua */
+    orc_trans *tr;
+    int bg_kind;              /* 0 none, 1 H-minus-like law */
+    double c_bg;
+    int NL;
+    double *lam, *nu;         /* union grid, increasing wavelength */
+} orc_atom;
+
+typedef struct {
+    int n_mu;
+    double tol;
+    int max_iter;
+    int ng_order, ng_delay, ng_period;
+    int start;           /* 0 LTE, 1 zero radiation, 2 provided */
+    double coll_scale;   /* collision multiplier (1 = physical) */
+} orc_opts;
+
+/* ------------------------------------------------------------------ */
+/* atom file                                                            */
+/* ------------------------------------------------------------------ */
+typedef struct { char *buf; char *p; } tokstream;
+
+static const char *next_tok(tokstream *ts) {
+    for (;;) {
+        while (*ts->p && isspace((unsigned char)*ts->p)) ts->p++;
+        if (*ts->p == '#') { while (*ts->p && *ts->p != '\n') ts->p++; continue; }
+        break;
+    }
+    if (!*ts->p) return NULL;
+    char *s = ts->p;
+    while (*ts->p && !isspace((unsigned char)*ts->p)) ts->p++;
+    if (*ts->p) { *ts->p = 0; ts->p++; }
+    return s;
+}
+
+static int tok_double(tokstream *ts, double *v) {
+    const char *t = next_tok(ts);
+    if (!t) return -1;
+    char *e; *v = strtod(t, &e);
+    return (*e == 0) ? 0 : -1;
+}
+static int tok_int(tokstream *ts, int *v) {
+    const char *t = next_tok(ts);
+    if (!t) return -1;
+    char *e; long x = strtol(t, &e, 10);
+    *v = (int)x;
+    return (*e == 0) ? 0 : -1;
+}
+static int tok_expect(tokstream *ts, const char *kw) {
+    const char *t = next_tok(ts);
+    return (t && strcmp(t, kw) == 0) ? 0 : -1;
+}
+
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_atom_free(orc_atom *a) {
+    if (!a) return;
+    for (int t = 0; t < a->T; t++) { free(a->tr[t].lam_own); free(a->tr[t].act); free(a->tr[t].wnu); }
+    free(a->tr); free(a->E); free(a->g); free(a->stage); free(a->lam); free(a->nu);
+    free(a);
+}
+
+static int parse_transition(tokstream *ts, orc_trans *t, int kind, int L) {
+    t->kind = kind;
+    if (tok_int(ts, &t->l) || tok_int(ts, &t->u)) return -1;
+    if (t->l < 0 || t->u >= L || t->l >= t->u) return -1;
+    if (kind == 0) {
+        if (tok_double(ts, &t->f)) return -1;
+        const char *p = next_tok(ts);
+        if (!p) return -1;
+        if (!strcmp(p, "VOIGT")) t->voigt = 1; else if (!strcmp(p, "GAUSS")) t->voigt = 0; else return -1;
+    } else {
+        if (tok_double(ts, &t->alpha0)) return -1;
+    }
+    const char *c = next_tok(ts);
+    if (!c) return -1;
+    if (!strcmp(c, "OMEGA")) t->coll_kind = 0; else if (!strcmp(c, "EPS")) t->coll_kind = 1; else return -1;
+    if (tok_double(ts, &t->coll_val) || tok_int(ts, &t->n_own) || t->n_own < 2) return -1;
+    t->lam_own = malloc(sizeof(double) * t->n_own);
+    for (int i = 0; i < t->n_own; i++) {
+        if (tok_double(ts, &t->lam_own[i])) return -1;
+        t->lam_own[i] *= 1e-9;
+    }
+    return 0;
+}
+
+int orc_atom_load(const char *path, orc_atom **out) {
+    *out = NULL;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) FAIL(-1, "cannot open %s", path);
+    fseek(fp, 0, SEEK_END); long n = ftell(fp); fseek(fp, 0, SEEK_SET);
+    tokstream ts; ts.buf = malloc(n + 1);
+    if (fread(ts.buf, 1, n, fp) != (size_t)n) { fclose(fp); free(ts.buf); FAIL(-1, "read error"); }
+    ts.buf[n] = 0; ts.p = ts.buf; fclose(fp);
+    orc_atom *a = calloc(1, sizeof *a);
+    int ver, rc = -1;
+    const char *tk;
+    if (tok_expect(&ts, "RH15D-ATOM") || tok_int(&ts, &ver)) goto bad;
+    if (tok_expect(&ts, "NAME") || !next_tok(&ts)) goto bad;
+    if (tok_expect(&ts, "MASS_AMU") || tok_double(&ts, &a->mass)) goto bad;
+    a->mass *= PAMU;
+    if (tok_expect(&ts, "ABUNDANCE") || tok_double(&ts, &a->abund)) goto bad;
+    if (tok_expect(&ts, "LEVELS") || tok_int(&ts, &a->L) || a->L < 2) goto bad;
+    a->E = malloc(sizeof(double) * a->L); a->g = malloc(sizeof(double) * a->L); a->stage = malloc(sizeof(int) * a->L);
+    for (int i = 0; i < a->L; i++) {
+        if (tok_double(&ts, &a->E[i]) || tok_double(&ts, &a->g[i]) || tok_int(&ts, &a->stage[i])) goto bad;
+        a->E[i] *= PQE;
+    }
+    if (tok_expect(&ts, "LINES") || tok_int(&ts, &a->n_lines) || a->n_lines < 0) goto bad;
+    orc_trans *lines = calloc(a->n_lines ? a->n_lines : 1, sizeof(orc_trans));
+    for (int i = 0; i < a->n_lines; i++) if (parse_transition(&ts, &lines[i], 0, a->L)) { free(lines); goto bad; }
+    if (tok_expect(&ts, "CONTINUA") || tok_int(&ts, &a->n_cont) || a->n_cont < 0) { free(lines); goto bad; }
+    a->T = a->n_lines + a->n_cont;
+    a->tr = calloc(a->T ? a->T : 1, sizeof(orc_trans));
+    memcpy(a->tr, lines, sizeof(orc_trans) * a->n_lines);
+    free(lines);
+    for (int i = 0; i < a->n_cont; i++) if (parse_transition(&ts, &a->tr[a->n_lines + i], 1, a->L)) goto bad;
+    if (tok_expect(&ts, "BACKGROUND") || !(tk = next_tok(&ts))) goto bad;
+    if (!strcmp(tk, "NONE")) a->bg_kind = 0;
+    else if (!strcmp(tk, "HMINUS")) { a->bg_kind = 1; if (tok_double(&ts, &a->c_bg)) goto bad; }
+    else goto bad;
+    if (tok_expect(&ts, "END")) goto bad;
+    rc = 0;
+bad:
+    free(ts.buf);
+    if (rc) { orc_atom_free(a); FAIL(-2, "malformed atom file %s", path); }
+
+    /* atomic data of each transition */
+    for (int t = 0; t < a->T; t++) {
+        orc_trans *tr = &a->tr[t];
+        double dE = a->E[tr->u] - a->E[tr->l];
+        if (!(dE > 0)) { orc_atom_free(a); FAIL(-2, "transition %d has no positive energy gap", t); }
+        tr->nu0 = dE / PH;
+        if (tr->kind == 0) {
+            tr->Aul = 2.0 * PPI * PQE * PQE * tr->nu0 * tr->nu0 / (PEPS0 * PME * PC * PC * PC)
+                      * (a->g[tr->l] / a->g[tr->u]) * tr->f;
+            tr->Bul = tr->Aul * PC * PC / (2.0 * PH * tr->nu0 * tr->nu0 * tr->nu0);
+            tr->Blu = a->g[tr->u] / a->g[tr->l] * tr->Bul;
+        }
+        tr->lam_min = tr->lam_max = tr->lam_own[0];
+        for (int i = 1; i < tr->n_own; i++) {
+            if (tr->lam_own[i] < tr->lam_min) tr->lam_min = tr->lam_own[i];
+            if (tr->lam_own[i] > tr->lam_max) tr->lam_max = tr->lam_own[i];
+        }
+    }
+    /* radiative damping: spontaneous rates out of both levels of each line */
+    for (int t = 0; t < a->n_lines; t++) {
+        orc_trans *tr = &a->tr[t];
+        double gam = 0.0;
+        for (int s = 0; s < a->n_lines; s++) {
+            if (a->tr[s].u == tr->u) gam += a->tr[s].Aul;
+            if (a->tr[s].u == tr->l) gam += a->tr[s].Aul;
+        }
+        tr->gamma_rad = gam;
+    }
+    /* union wavelength grid: all own points, sorted, exact duplicates merged */
+    int tot = 0;
+    for (int t = 0; t < a->T; t++) tot += a->tr[t].n_own;
+    double *all = malloc(sizeof(double) * tot);
+    int q = 0;
+    for (int t = 0; t < a->T; t++) for (int i = 0; i < a->tr[t].n_own; i++) all[q++] = a->tr[t].lam_own[i];
+    qsort(all, tot, sizeof(double), cmp_double);
+    a->lam = malloc(sizeof(double) * tot);
+    a->NL = 0;
+    for (int i = 0; i < tot; i++) if (a->NL == 0 || all[i] != a->lam[a->NL - 1]) a->lam[a->NL++] = all[i];
+    free(all);
+    a->nu = malloc(sizeof(double) * a->NL);
+    for (int j = 0; j < a->NL; j++) a->nu[j] = PC / a->lam[j];
+    /* active points of each transition and their trapezoid weights in frequency */
+    for (int t = 0; t < a->T; t++) {
+        orc_trans *tr = &a->tr[t];
+        tr->act = malloc(sizeof(int) * a->NL);
+        tr->n_act = 0;
+        for (int j = 0; j < a->NL; j++)
+            if (a->lam[j] >= tr->lam_min && a->lam[j] <= tr->lam_max) tr->act[tr->n_act++] = j;
+        tr->wnu = malloc(sizeof(double) * tr->n_act);
+        for (int i = 0; i < tr->n_act; i++) {
+            double nl = a->nu[tr->act[i > 0 ? i - 1 : i]];
+            double nr = a->nu[tr->act[i < tr->n_act - 1 ? i + 1 : i]];
+            tr->wnu[i] = 0.5 * (nl - nr);
+        }
+    }
+    *out = a;
+    return 0;
+}
+
+int orc_atom_info(const orc_atom *a, int *L, int *n_lines, int *n_cont, int *NL) {
+    *L = a->L; *n_lines = a->n_lines; *n_cont = a->n_cont; *NL = a->NL;
+    return 0;
+}
+int orc_atom_lambda(const orc_atom *a, double *lam) { memcpy(lam, a->lam, sizeof(double) * a->NL); return 0; }
+/* per transition: l, u, kind, n_active; weights copied if w != NULL (size n_active) */
+int orc_atom_transition(const orc_atom *a, int t, int *l, int *u, int *kind, int *n_act, int *act, double *w) {
+    if (t < 0 || t >= a->T) return -1;
+    const orc_trans *tr = &a->tr[t];
+    *l = tr->l; *u = tr->u; *kind = tr->kind; *n_act = tr->n_act;
+    if (act) memcpy(act, tr->act, sizeof(int) * tr->n_act);
+    if (w) memcpy(w, tr->wnu, sizeof(double) * tr->n_act);
+    return 0;
+}
+double orc_atom_einstein_A(const orc_atom *a, int t) { return a->tr[t].Aul; }
+
+/* ------------------------------------------------------------------ */
+/* small numerical pieces                                               */
+/* ------------------------------------------------------------------ */
+
+/* Gauss-Legendre nodes and weights on (0, 1), ascending; weights sum to 1. */
+int orc_gauss_legendre(int n, double *x, double *w) {
+    if (n < 1 || n > 64) return -1;
+    for (int i = 0; i < n; i++) {
+        double z = cos(PPI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) { double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = p2; }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; k++) { double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = p2; }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        /* root z of P_n descends with i, so 0.5 (1 - z) ascends on (0, 1) */
+        x[i] = 0.5 * (1.0 - z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return 0;
+}
+
+/* Voigt function H(a, v) = Re w(v + i a) by Humlicek (1982) rational
+ * approximation W4 (four regions in s = |v| + a). */
+double orc_voigt_H(double a, double v) {
+    double x = v, y = a;
+    double s = fabs(x) + y;
+    /* t = y - i x */
+    double tr = y, ti = -x;
+    double wr, wi;
+    if (s >= 15.0) {
+        /* t * 0.5641896 / (0.5 + t^2) */
+        double ur = tr * tr - ti * ti + 0.5, ui = 2.0 * tr * ti;
+        double nr = 0.5641896 * tr, ni = 0.5641896 * ti;
+        double d = ur * ur + ui * ui;
+        wr = (nr * ur + ni * ui) / d; wi = (ni * ur - nr * ui) / d;
+    } else if (s >= 5.5) {
+        /* t (1.410474 + u 0.5641896) / (0.75 + u (3 + u)), u = t^2 */
+        double ur = tr * tr - ti * ti, ui = 2.0 * tr * ti;
+        double pr = 1.410474 + 0.5641896 * ur, pi = 0.5641896 * ui;
+        double nr = tr * pr - ti * pi, ni = tr * pi + ti * pr;
+        double qr = 3.0 + ur, qi = ui;
+        double dr = 0.75 + (ur * qr - ui * qi), di = (ur * qi + ui * qr);
+        double d = dr * dr + di * di;
+        wr = (nr * dr + ni * di) / d; wi = (ni * dr - nr * di) / d;
+    } else if (y >= 0.195 * fabs(x) - 0.176) {
+        static const double pa[5] = {16.4955, 20.20933, 11.96482, 3.778987, 0.5642236};
+        static const double qa[6] = {16.4955, 38.82363, 39.27121, 21.69274, 6.699398, 1.0};
+        double nr = pa[4], ni = 0.0;
+        for (int i = 3; i >= 0; i--) { double r = nr * tr - ni * ti + pa[i], im = nr * ti + ni * tr; nr = r; ni = im; }
+        double dr = qa[5], di = 0.0;
+        for (int i = 4; i >= 0; i--) { double r = dr * tr - di * ti + qa[i], im = dr * ti + di * tr; dr = r; di = im; }
+        double d = dr * dr + di * di;
+        wr = (nr * dr + ni * di) / d; wi = (ni * dr - nr * di) / d;
+    } else {
+        /* exp(u) - t P(u) / Q(u), u = t^2 */
+        static const double pb[7] = {36183.31, -3321.9905, 1540.787, -219.0313, 35.76683, -1.320522, 0.56419};
+        static const double qb[8] = {32066.6, -24322.84, 9022.228, -2186.181, 364.2191, -61.57037, 1.841439, -1.0};
+        double ur = tr * tr - ti * ti, ui = 2.0 * tr * ti;
+        double pr = pb[6], pim = 0.0;
+        for (int i = 5; i >= 0; i--) { double r = pr * ur - pim * ui + pb[i], im = pr * ui + pim * ur; pr = r; pim = im; }
+        double qr = qb[7], qi = 0.0;
+        for (int i = 6; i >= 0; i--) { double r = qr * ur - qi * ui + qb[i], im = qr * ui + qi * ur; qr = r; qi = im; }
+        double nr = tr * pr - ti * pim, ni = tr * pim + ti * pr;
+        double d = qr * qr + qi * qi;
+        double fr = (nr * qr + ni * qi) / d, fi = (ni * qr - nr * qi) / d;
+        double eu = exp(ur);
+        wr = eu * cos(ui) - fr; wi = eu * sin(ui) - fi;
+    }
+    (void)wi;
+    return wr;
+}
+
+/* Linear short-characteristic weights for an optical step x along a ray:
+ * I_b = I_a e + wa S_a + wb S_b. */
+void orc_sc_coefficients(double x, double *e, double *wa, double *wb) {
+    if (x < SC_SERIES_X) {
+        double x2 = x * x, x3 = x2 * x, x4 = x3 * x, x5 = x4 * x, x6 = x5 * x;
+        *wb = x / 2.0 - x2 / 6.0 + x3 / 24.0 - x4 / 120.0 + x5 / 720.0 - x6 / 5040.0;
+        *wa = x / 2.0 - x2 / 3.0 + x3 / 8.0 - x4 / 30.0 + x5 / 144.0 - x6 / 840.0;
+        *e = exp(-x);
+    } else {
+        double em = -expm1(-x);
+        double q = em / x;
+        *e = 1.0 - em;
+        *wb = 1.0 - q;
+        *wa = q - *e;
+    }
+}
+
+/* Formal solution along one ray of n points given the optical steps
+ * dtau[i] between points i-1 and i (dtau[0] unused), the source function
+ * S and the incoming intensity I0 at point 0.  Returns I and the diagonal
+ * Lambda* (0 at the boundary point). */
+int orc_formal_ray(int n, const double *dtau, const double *S, double I0, double *I, double *lstar) {
+    I[0] = I0; lstar[0] = 0.0;
+    for (int i = 1; i < n; i++) {
+        double e, wa, wb;
+        orc_sc_coefficients(dtau[i], &e, &wa, &wb);
+        I[i] = I[i - 1] * e + wa * S[i - 1] + wb * S[i];
+        lstar[i] = wb;
+    }
+    return 0;
+}
+
+/* LTE (Saha-Boltzmann) populations of one depth point, summing to ntot. */
+static void lte_log_ratios(const orc_atom *a, double T, double ne, double *lnr) {
+    double kT = PKB * T;
+    double saha = log(2.0 / ne) + 1.5 * log(2.0 * PPI * PME * kT / (PH * PH));
+    for (int i = 0; i < a->L; i++)
+        lnr[i] = log(a->g[i] / a->g[0]) - (a->E[i] - a->E[0]) / kT + (a->stage[i] - a->stage[0]) * saha;
+}
+static void lte_from_log_ratios(int L, const double *lnr, double ntot, double *n) {
+    double mx = lnr[0];
+    for (int i = 1; i < L; i++) if (lnr[i] > mx) mx = lnr[i];
+    double s = 0.0;
+    for (int i = 0; i < L; i++) s += exp(lnr[i] - mx);
+    for (int i = 0; i < L; i++) n[i] = ntot * exp(lnr[i] - mx) / s;
+}
+int orc_lte_populations(const orc_atom *a, double T, double ne, double ntot, double *n) {
+    double lnr[64];
+    if (a->L > 64) return -1;
+    lte_log_ratios(a, T, ne, lnr);
+    lte_from_log_ratios(a->L, lnr, ntot, n);
+    return 0;
+}
+
+/* Planck function B_nu(T) */
+static double planck(double nu, double T) {
+    double x = PH * nu / (PKB * T);
+    return 2.0 * PH * nu * nu * nu / (PC * PC) * exp(-x) / (-expm1(-x));
+}
+
+/* Dense Gaussian elimination with partial pivoting: solves A x = b (n x n). */
+static int gauss_solve(int n, double *A, double *b) {
+    for (int c = 0; c < n; c++) {
+        int p = c;
+        for (int r = c + 1; r < n; r++) if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
+        if (A[p * n + c] == 0.0) return -1;
+        if (p != c) {
+            for (int k = 0; k < n; k++) { double t = A[c * n + k]; A[c * n + k] = A[p * n + k]; A[p * n + k] = t; }
+            double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < n; r++) {
+            double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; k++) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; r--) {
+        double s = b[r];
+        for (int k = r + 1; k < n; k++) s -= A[r * n + k] * b[k];
+        b[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* one column                                                           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const orc_atom *a;
+    int N, nmu;
+    const double *z, *T, *ne, *nH, *vz, *vt;
+    double *mu, *wmu;
+    double *ntot;        /* [N] */
+    double *lnr;         /* [N][L] Saha-Boltzmann log ratios to level 0 */
+    double *nstar;       /* [N][L] */
+    double *C;           /* [N][L][L]  C[i][j]: rate i -> j */
+    double *kbg;         /* [N] background opacity at 500 nm */
+    double *dnuD;        /* [n_lines][N] */
+    double *adamp;       /* [n_lines][N] */
+    double *norm;        /* [n_lines][N] profile normalisation sum */
+    double **phi;        /* per line: [N][n_act][nmu][2] normalised profile */
+} colstate;
+
+static double line_profile(const orc_atom *a, int t, const colstate *cs, int k, double nu, double mus) {
+    const orc_trans *tr = &a->tr[t];
+    double dnd = cs->dnuD[t * cs->N + k];
+    double v = (nu - tr->nu0 * (1.0 + mus * cs->vz[k] / PC)) / dnd;
+    double H = tr->voigt ? orc_voigt_H(cs->adamp[t * cs->N + k], v) : exp(-v * v);
+    return H / (sqrt(PPI) * dnd);
+}
+
+static void column_prepare(colstate *cs, double coll_scale) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L, nmu = cs->nmu;
+    cs->ntot = malloc(sizeof(double) * N);
+    cs->lnr = malloc(sizeof(double) * N * L);
+    cs->nstar = malloc(sizeof(double) * N * L);
+    cs->C = calloc((size_t)N * L * L, sizeof(double));
+    cs->kbg = malloc(sizeof(double) * N);
+    int nl = a->n_lines ? a->n_lines : 1;
+    cs->dnuD = malloc(sizeof(double) * nl * N);
+    cs->adamp = malloc(sizeof(double) * nl * N);
+    cs->norm = malloc(sizeof(double) * nl * N);
+    cs->phi = calloc(nl, sizeof(double *));
+    for (int k = 0; k < N; k++) {
+        cs->ntot[k] = a->abund * cs->nH[k];
+        lte_log_ratios(a, cs->T[k], cs->ne[k], &cs->lnr[k * L]);
+        lte_from_log_ratios(L, &cs->lnr[k * L], cs->ntot[k], &cs->nstar[k * L]);
+        cs->kbg[k] = (a->bg_kind == 1)
+            ? a->c_bg * cs->nH[k] * cs->ne[k] * pow(cs->T[k], -1.5) * exp(BG_THETA / cs->T[k]) : 0.0;
+        /* collisions */
+        for (int t = 0; t < a->T; t++) {
+            const orc_trans *tr = &a->tr[t];
+            double Cul;
+            if (tr->coll_kind == 0) {
+                Cul = cs->ne[k] * COLL_C0 * tr->coll_val / (a->g[tr->u] * sqrt(cs->T[k]));
+            } else {
+                double x = PH * tr->nu0 / (PKB * cs->T[k]);
+                Cul = tr->coll_val / (1.0 - tr->coll_val) * tr->Aul / (-expm1(-x));
+            }
+            Cul *= coll_scale;
+            double Clu = Cul * exp(cs->lnr[k * L + tr->u] - cs->lnr[k * L + tr->l]);
+            cs->C[(k * L + tr->u) * L + tr->l] += Cul;
+            cs->C[(k * L + tr->l) * L + tr->u] += Clu;
+        }
+    }
+    /* line profiles on every ray of the quadrature, normalised per depth */
+    for (int t = 0; t < a->n_lines; t++) {
+        const orc_trans *tr = &a->tr[t];
+        for (int k = 0; k < N; k++) {
+            double vth2 = 2.0 * PKB * cs->T[k] / a->mass + cs->vt[k] * cs->vt[k];
+            double dnd = tr->nu0 / PC * sqrt(vth2);
+            cs->dnuD[t * N + k] = dnd;
+            cs->adamp[t * N + k] = tr->gamma_rad / (4.0 * PPI * dnd);
+        }
+        int na = tr->n_act;
+        double *ph = malloc(sizeof(double) * (size_t)N * na * nmu * 2);
+        for (int k = 0; k < N; k++) {
+            double sum = 0.0;
+            for (int ja = 0; ja < na; ja++) {
+                double nu = a->nu[tr->act[ja]];
+                for (int m = 0; m < nmu; m++) for (int s = 0; s < 2; s++) {
+                    double mus = s ? cs->mu[m] : -cs->mu[m];     /* s = 1: upward */
+                    double p = line_profile(a, t, cs, k, nu, mus);
+                    ph[(((size_t)k * na + ja) * nmu + m) * 2 + s] = p;
+                    sum += tr->wnu[ja] * 0.5 * cs->wmu[m] * p;
+                }
+            }
+            cs->norm[t * N + k] = sum;
+            for (int i = 0; i < na * nmu * 2; i++) ph[(size_t)k * na * nmu * 2 + i] /= sum;
+        }
+        cs->phi[t] = ph;
+    }
+}
+
+static void column_release(colstate *cs) {
+    free(cs->ntot); free(cs->lnr); free(cs->nstar); free(cs->C); free(cs->kbg);
+    for (int t = 0; t < cs->a->n_lines; t++) free(cs->phi[t]);
+    free(cs->phi); free(cs->dnuD); free(cs->adamp); free(cs->norm);
+}
+
+/* Accumulators of the preconditioned rates. */
+typedef struct { double *P, *Q, *X; } rates;   /* P,Q: [T][N]; X: [T][T][N] */
+
+/* Opacity terms of active transition t at ray (j, m, s), depth k:
+ * V_lu, V_ul, U and the rate weight kappa = 4 pi W / (h nu_t). */
+static void transition_terms(const colstate *cs, const double *n, int t, int ja, int j, int m, int s, int k,
+                             double *Vlu, double *Vul, double *U, double *kap) {
+    const orc_atom *a = cs->a;
+    const orc_trans *tr = &a->tr[t];
+    int L = a->L;
+    double W = tr->wnu[ja] * 0.5 * cs->wmu[m];
+    (void)n;
+    if (tr->kind == 0) {
+        double p = cs->phi[t][(((size_t)k * tr->n_act + ja) * cs->nmu + m) * 2 + s];
+        double c = PH * tr->nu0 / (4.0 * PPI);
+        *Vlu = c * tr->Blu * p; *Vul = c * tr->Bul * p; *U = c * tr->Aul * p;
+        *kap = 4.0 * PPI * W / (PH * tr->nu0);
+    } else {
+        double nu = a->nu[j];
+        double alpha = tr->alpha0 * pow(tr->nu0 / nu, 3.0);
+        double G = exp(cs->lnr[k * L + tr->l] - cs->lnr[k * L + tr->u]) * exp(-PH * nu / (PKB * cs->T[k]));
+        *Vlu = alpha; *Vul = G * alpha; *U = 2.0 * PH * nu * nu * nu / (PC * PC) * G * alpha;
+        *kap = 4.0 * PPI * W / (PH * nu);
+    }
+}
+
+/* One formal-solution sweep over all rays with populations n.
+ * mode 0: preconditioned rates; mode 1: zero-radiation rates (I_eff = 0,
+ * Psi* = 0); mode 2: Psi* averaged per transition into psi_out[T][N]. */
+static void sweep(const colstate *cs, const double *n, int mode, rates *R, double *psi_out) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L, T = a->T;
+    double *chi = malloc(sizeof(double) * N), *eta = malloc(sizeof(double) * N), *S = malloc(sizeof(double) * N);
+    double *etabg = malloc(sizeof(double) * N), *B = malloc(sizeof(double) * N);
+    double *Ieff = malloc(sizeof(double) * N), *psi = malloc(sizeof(double) * N);
+    double *Vlu = malloc(sizeof(double) * T * N), *Vul = malloc(sizeof(double) * T * N);
+    double *U = malloc(sizeof(double) * T * N), *kap = malloc(sizeof(double) * T * N), *chit = malloc(sizeof(double) * T * N);
+    int *act = malloc(sizeof(int) * (T ? T : 1)), *jact = malloc(sizeof(int) * (T ? T : 1));
+    if (R) {
+        memset(R->P, 0, sizeof(double) * T * N);
+        memset(R->Q, 0, sizeof(double) * T * N);
+        memset(R->X, 0, sizeof(double) * T * T * N);
+    }
+    if (psi_out) memset(psi_out, 0, sizeof(double) * T * N);
+    for (int j = 0; j < a->NL; j++) {
+        double nu = a->nu[j];
+        int na = 0;
+        for (int t = 0; t < T; t++) {
+            const orc_trans *tr = &a->tr[t];
+            for (int q = 0; q < tr->n_act; q++) if (tr->act[q] == j) { act[na] = t; jact[na] = q; na++; break; }
+        }
+        if (na == 0) continue;
+        for (int k = 0; k < N; k++) {
+            double chibg = cs->kbg[k] * (a->lam[j] / BG_LAMBDA_REF);
+            B[k] = planck(nu, cs->T[k]);
+            etabg[k] = chibg * B[k];
+            chi[k] = chibg;
+        }
+        for (int m = 0; m < cs->nmu; m++) {
+            double mu = cs->mu[m];
+            for (int s = 0; s < 2; s++) {
+                /* opacities of this ray */
+                for (int k = 0; k < N; k++) {
+                    double c = cs->kbg[k] * (a->lam[j] / BG_LAMBDA_REF), e = etabg[k];
+                    for (int q = 0; q < na; q++) {
+                        int t = act[q];
+                        const orc_trans *tr = &a->tr[t];
+                        size_t o = (size_t)q * N + k;
+                        transition_terms(cs, n, t, jact[q], j, m, s, k, &Vlu[o], &Vul[o], &U[o], &kap[o]);
+                        chit[o] = n[k * L + tr->l] * Vlu[o] - n[k * L + tr->u] * Vul[o];
+                        c += chit[o];
+                        e += n[k * L + tr->u] * U[o];
+                    }
+                    chi[k] = c; eta[k] = e; S[k] = e / c;
+                }
+                /* formal solution */
+                if (mode == 1) {
+                    for (int k = 0; k < N; k++) { Ieff[k] = 0.0; psi[k] = 0.0; }
+                } else if (s == 0) {               /* downward: top to bottom */
+                    double I = 0.0;
+                    Ieff[0] = 0.0; psi[0] = 0.0;
+                    for (int k = 1; k < N; k++) {
+                        double x = 0.5 * (chi[k - 1] + chi[k]) * (cs->z[k - 1] - cs->z[k]) / mu;
+                        double e, wa, wb;
+                        orc_sc_coefficients(x, &e, &wa, &wb);
+                        Ieff[k] = I * e + wa * S[k - 1] + wb * etabg[k] / chi[k];
+                        psi[k] = wb / chi[k];
+                        I = I * e + wa * S[k - 1] + wb * S[k];
+                    }
+                } else {                           /* upward: bottom to top */
+                    double dtv = 0.5 * (chi[N - 1] + chi[N - 2]) * (cs->z[N - 2] - cs->z[N - 1]);
+                    double I = (dtv > 0.0) ? B[N - 1] + mu * (B[N - 1] - B[N - 2]) / dtv : B[N - 1];
+                    Ieff[N - 1] = I; psi[N - 1] = 0.0;
+                    for (int k = N - 2; k >= 0; k--) {
+                        double x = 0.5 * (chi[k + 1] + chi[k]) * (cs->z[k] - cs->z[k + 1]) / mu;
+                        double e, wa, wb;
+                        orc_sc_coefficients(x, &e, &wa, &wb);
+                        Ieff[k] = I * e + wa * S[k + 1] + wb * etabg[k] / chi[k];
+                        psi[k] = wb / chi[k];
+                        I = I * e + wa * S[k + 1] + wb * S[k];
+                    }
+                }
+                /* accumulation */
+                for (int q = 0; q < na; q++) {
+                    int t = act[q];
+                    for (int k = 0; k < N; k++) {
+                        size_t o = (size_t)q * N + k;
+                        if (mode == 2) {
+                            const orc_trans *tr = &a->tr[t];
+                            double W = tr->wnu[jact[q]] * 0.5 * cs->wmu[m];
+                            double om;
+                            if (tr->kind == 0) om = W * cs->phi[t][(((size_t)k * tr->n_act + jact[q]) * cs->nmu + m) * 2 + s];
+                            else { double ws = 0.0; for (int i = 0; i < tr->n_act; i++) ws += tr->wnu[i]; om = W / ws; }
+                            psi_out[t * N + k] += om * psi[k];
+                            continue;
+                        }
+                        R->P[t * N + k] += kap[o] * Vlu[o] * Ieff[k];
+                        R->Q[t * N + k] += kap[o] * (U[o] * (1.0 - chit[o] * psi[k]) + Vul[o] * Ieff[k]);
+                        for (int q2 = 0; q2 < na; q2++) {
+                            if (q2 == q) continue;
+                            int t2 = act[q2];
+                            R->X[((size_t)t * T + t2) * N + k] += kap[o] * chit[o] * psi[k] * U[(size_t)q2 * N + k];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    free(chi); free(eta); free(S); free(etabg); free(B); free(Ieff); free(psi);
+    free(Vlu); free(Vul); free(U); free(kap); free(chit); free(act); free(jact);
+}
+
+/* Statistical equilibrium at every depth; returns 0 or -1 on a singular system. */
+static int solve_se(const colstate *cs, const rates *R, const double *nold, double *nnew) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L, T = a->T;
+    double *G = malloc(sizeof(double) * L * L), *b = malloc(sizeof(double) * L);
+    int rc = 0;
+    for (int k = 0; k < N; k++) {
+        memset(G, 0, sizeof(double) * L * L);
+        for (int t = 0; t < T; t++) {
+            int l = a->tr[t].l, u = a->tr[t].u;
+            double P = R->P[t * N + k], Q = R->Q[t * N + k];
+            G[u * L + l] += P; G[l * L + l] -= P;
+            G[l * L + u] += Q; G[u * L + u] -= Q;
+            for (int t2 = 0; t2 < T; t2++) {
+                if (t2 == t) continue;
+                double X = R->X[((size_t)t * T + t2) * N + k];
+                if (X == 0.0) continue;
+                int u2 = a->tr[t2].u;
+                G[u * L + u2] += X; G[l * L + u2] -= X;
+            }
+        }
+        for (int i = 0; i < L; i++) for (int j = 0; j < L; j++) {
+            if (i == j) continue;
+            double c = cs->C[(k * L + i) * L + j];
+            G[j * L + i] += c; G[i * L + i] -= c;
+        }
+        int istar = 0;
+        for (int i = 1; i < L; i++) if (nold[k * L + i] > nold[k * L + istar]) istar = i;
+        for (int j = 0; j < L; j++) { G[istar * L + j] = 1.0; b[j] = 0.0; }
+        b[istar] = cs->ntot[k];
+        if (gauss_solve(L, G, b)) { rc = -1; }
+        for (int i = 0; i < L; i++) nnew[k * L + i] = b[i];
+    }
+    free(G); free(b);
+    return rc;
+}
+
+/* Emergent intensity at mu = 1 (vertical, upward) for every wavelength. */
+static void emergent(const colstate *cs, const double *n, double *spec) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L;
+    double *chi = malloc(sizeof(double) * N), *S = malloc(sizeof(double) * N), *B = malloc(sizeof(double) * N);
+    for (int j = 0; j < a->NL; j++) {
+        double nu = a->nu[j];
+        for (int k = 0; k < N; k++) {
+            double c = cs->kbg[k] * (a->lam[j] / BG_LAMBDA_REF);
+            B[k] = planck(nu, cs->T[k]);
+            double e = c * B[k];
+            for (int t = 0; t < a->T; t++) {
+                const orc_trans *tr = &a->tr[t];
+                if (!(a->lam[j] >= tr->lam_min && a->lam[j] <= tr->lam_max)) continue;
+                double Vlu, Vul, U;
+                if (tr->kind == 0) {
+                    double p = line_profile(a, t, cs, k, nu, 1.0) / cs->norm[t * N + k];
+                    double cc = PH * tr->nu0 / (4.0 * PPI);
+                    Vlu = cc * tr->Blu * p; Vul = cc * tr->Bul * p; U = cc * tr->Aul * p;
+                } else {
+                    double alpha = tr->alpha0 * pow(tr->nu0 / nu, 3.0);
+                    double G = exp(cs->lnr[k * L + tr->l] - cs->lnr[k * L + tr->u]) * exp(-PH * nu / (PKB * cs->T[k]));
+                    Vlu = alpha; Vul = G * alpha; U = 2.0 * PH * nu * nu * nu / (PC * PC) * G * alpha;
+                }
+                c += n[k * L + tr->l] * Vlu - n[k * L + tr->u] * Vul;
+                e += n[k * L + tr->u] * U;
+            }
+            chi[k] = c; S[k] = e / c;
+        }
+        double dtv = 0.5 * (chi[N - 1] + chi[N - 2]) * (cs->z[N - 2] - cs->z[N - 1]);
+        double I = (dtv > 0.0) ? B[N - 1] + (B[N - 1] - B[N - 2]) / dtv : B[N - 1];
+        for (int k = N - 2; k >= 0; k--) {
+            double x = 0.5 * (chi[k + 1] + chi[k]) * (cs->z[k] - cs->z[k + 1]);
+            double e, wa, wb;
+            orc_sc_coefficients(x, &e, &wa, &wb);
+            I = I * e + wa * S[k + 1] + wb * S[k];
+        }
+        spec[j] = I;
+    }
+    free(chi); free(S); free(B);
+}
+
+/* Ng extrapolation of order M from the ring of the last M+2 iterates
+ * (x[0] newest).  Returns 1 and writes out if applied, 0 if skipped. */
+int orc_ng_step(int M, int n, double *const *x, double *out) {
+    if (M != 2) return 0;
+    double A11 = 0, A12 = 0, A22 = 0, b1 = 0, b2 = 0;
+    for (int i = 0; i < n; i++) {
+        double w = 1.0 / (x[0][i] * x[0][i]);
+        double d0 = x[0][i] - x[1][i], d1 = x[1][i] - x[2][i], d2 = x[2][i] - x[3][i];
+        double e1 = d0 - d1, e2 = d0 - d2;
+        A11 += w * e1 * e1; A12 += w * e1 * e2; A22 += w * e2 * e2;
+        b1 += w * d0 * e1; b2 += w * d0 * e2;
+    }
+    double det = A11 * A22 - A12 * A12;
+    if (!(fabs(det) > 1e-14 * A11 * A22)) return 0;
+    double a1 = (b1 * A22 - b2 * A12) / det, a2 = (b2 * A11 - b1 * A12) / det;
+    for (int i = 0; i < n; i++) {
+        double v = (1.0 - a1 - a2) * x[0][i] + a1 * x[1][i] + a2 * x[2][i];
+        if (!(v > 0.0)) return 0;
+    }
+    for (int i = 0; i < n; i++) out[i] = (1.0 - a1 - a2) * x[0][i] + a1 * x[1][i] + a2 * x[2][i];
+    return 1;
+}
+
+/* Solve one column.  Arrays of the column: N points, top first.
+ * Outputs (any may be NULL except pops): pops[N][L], history[max_iter],
+ * spectrum[NL], psi_star[T][N]; n_iter and status scalars.
+ * status: 0 converged, 1 iteration limit, 2 non-finite or non-positive
+ * populations, 3 singular rate matrix. */
+int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                     const double *nH, const double *vz, const double *vt, const double *init_pops,
+                     const orc_opts *o, double *pops, double *history, int *n_iter, int *status,
+                     double *spectrum, double *psi_star) {
+    if (N < 2) FAIL(-3, "need at least 2 depth points");
+    for (int k = 1; k < N; k++) if (!(z[k] < z[k - 1])) FAIL(-3, "z must decrease with depth index");
+    if (o->n_mu < 1 || o->n_mu > 16) FAIL(-3, "n_mu out of range");
+    if (o->ng_order != 0 && o->ng_order != 2) FAIL(-3, "only Ng order 2 (or 0 = off) is implemented");
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = o->n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * o->n_mu); cs.wmu = malloc(sizeof(double) * o->n_mu);
+    orc_gauss_legendre(o->n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, o->coll_scale > 0 ? o->coll_scale : 1.0);
+    int L = a->L, Tn = a->T, NV = N * L;
+    rates R;
+    R.P = malloc(sizeof(double) * (Tn ? Tn : 1) * N); R.Q = malloc(sizeof(double) * (Tn ? Tn : 1) * N);
+    R.X = malloc(sizeof(double) * (Tn ? Tn * Tn : 1) * N);
+    double *n = malloc(sizeof(double) * NV), *nse = malloc(sizeof(double) * NV);
+    int M = o->ng_order, ring_n = M + 2;
+    double *ring[8] = {0};
+    if (M > 0) for (int i = 0; i < ring_n; i++) ring[i] = malloc(sizeof(double) * NV);
+    int ng_count = 0;
+
+    memcpy(n, cs.nstar, sizeof(double) * NV);
+    if (o->start == 1) {
+        sweep(&cs, n, 1, &R, NULL);
+        solve_se(&cs, &R, cs.nstar, n);
+    } else if (o->start == 2 && init_pops) {
+        memcpy(n, init_pops, sizeof(double) * NV);
+    }
+    if (history) for (int i = 0; i < o->max_iter; i++) history[i] = NAN;
+    int st = 1, it;
+    for (it = 1; it <= o->max_iter; it++) {
+        sweep(&cs, n, 0, &R, NULL);
+        int bad = solve_se(&cs, &R, n, nse);
+        double dmax = 0.0;
+        int finite = 1;
+        for (int i = 0; i < NV; i++) {
+            if (!isfinite(nse[i]) || !(nse[i] > 0.0)) { finite = 0; break; }
+            double d = fabs(nse[i] - n[i]) / nse[i];
+            if (d > dmax) dmax = d;
+        }
+        if (history) history[it - 1] = finite ? dmax : NAN;
+        if (bad) { st = 3; break; }
+        if (!finite) { st = 2; break; }
+        memcpy(n, nse, sizeof(double) * NV);
+        if (dmax < o->tol) { st = 0; break; }
+        if (M > 0 && it >= o->ng_delay) {
+            /* push newest iterate */
+            double *last = ring[ring_n - 1];
+            for (int i = ring_n - 1; i > 0; i--) ring[i] = ring[i - 1];
+            ring[0] = last;
+            memcpy(ring[0], nse, sizeof(double) * NV);
+            ng_count++;
+            /* an attempt every max(period, M+2) collected iterates; the
+             * history restarts after each attempt, applied or skipped */
+            int need = o->ng_period > ring_n ? o->ng_period : ring_n;
+            if (ng_count >= need) {
+                orc_ng_step(M, NV, ring, n);
+                ng_count = 0;
+            }
+        }
+    }
+    if (it > o->max_iter) it = o->max_iter;
+    *n_iter = it;
+    *status = st;
+    memcpy(pops, n, sizeof(double) * NV);
+    if (spectrum) emergent(&cs, n, spectrum);
+    if (psi_star) sweep(&cs, n, 2, NULL, psi_star);
+    for (int i = 0; i < 8; i++) free(ring[i]);
+    free(n); free(nse); free(R.P); free(R.Q); free(R.X);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return 0;
+}
+
+/* Thin helpers for tests: prepared-column quantities. */
+int orc_column_profile_norm(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                            const double *nH, const double *vz, const double *vt, int n_mu, double *nstar,
+                            double *norm) {
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * n_mu); cs.wmu = malloc(sizeof(double) * n_mu);
+    orc_gauss_legendre(n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    if (nstar) memcpy(nstar, cs.nstar, sizeof(double) * N * a->L);
+    if (norm) memcpy(norm, cs.norm, sizeof(double) * N * a->n_lines);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return 0;
+}

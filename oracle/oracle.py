@@ -1,0 +1,182 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import this module; the product
+(the GPU library and its Python binding) never does.
+"""
+from __future__ import annotations
+
+import concurrent.futures
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+START_LTE, START_ZERO_RADIATION, START_PROVIDED = 0, 1, 2
+
+
+def build() -> str:
+    """Compile the oracle with the host C compiler (plain -O2, no vector
+    or fast-math flags: the oracle stays the plain reference)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        L.orc_atom_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        L.orc_atom_free.argtypes = [C.c_void_p]
+        L.orc_atom_info.argtypes = [C.c_void_p, ip, ip, ip, ip]
+        L.orc_atom_lambda.argtypes = [C.c_void_p, dp]
+        L.orc_atom_transition.argtypes = [C.c_void_p, C.c_int, ip, ip, ip, ip, ip, dp]
+        L.orc_atom_einstein_A.argtypes = [C.c_void_p, C.c_int]
+        L.orc_atom_einstein_A.restype = C.c_double
+        L.orc_last_error.restype = C.c_char_p
+        L.orc_gauss_legendre.argtypes = [C.c_int, dp, dp]
+        L.orc_voigt_H.argtypes = [C.c_double, C.c_double]
+        L.orc_voigt_H.restype = C.c_double
+        L.orc_sc_coefficients.argtypes = [C.c_double, dp, dp, dp]
+        L.orc_formal_ray.argtypes = [C.c_int, dp, dp, C.c_double, dp, dp]
+        L.orc_lte_populations.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_solve_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 7 + [C.c_void_p, dp, dp, ip, ip, dp, dp]
+        L.orc_ng_step.argtypes = [C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_double)), dp]
+        L.orc_column_profile_norm.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class _Opts(C.Structure):
+    _fields_ = [("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("ng_order", C.c_int),
+                ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int), ("coll_scale", C.c_double)]
+
+
+class Atom:
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        if lib().orc_atom_load(path.encode(), C.byref(h)) != 0:
+            raise ValueError(lib().orc_last_error().decode())
+        self._h = h
+        L, nl, nc, NL = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        lib().orc_atom_info(h, C.byref(L), C.byref(nl), C.byref(nc), C.byref(NL))
+        self.n_levels, self.n_lines, self.n_cont, self.n_lambda = L.value, nl.value, nc.value, NL.value
+        self.n_trans = self.n_lines + self.n_cont
+        self.lam = np.empty(self.n_lambda)
+        lib().orc_atom_lambda(h, _p(self.lam))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.orc_atom_free(self._h)
+            self._h = None
+
+    def transition(self, t: int) -> dict:
+        l, u, kind, na = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        lib().orc_atom_transition(self._h, t, C.byref(l), C.byref(u), C.byref(kind), C.byref(na), None, None)
+        act = np.empty(na.value, dtype=np.int32)
+        w = np.empty(na.value)
+        lib().orc_atom_transition(self._h, t, C.byref(l), C.byref(u), C.byref(kind), C.byref(na),
+                                  act.ctypes.data_as(C.POINTER(C.c_int)), _p(w))
+        return dict(l=l.value, u=u.value, kind=kind.value, act=act, w=w,
+                    A=lib().orc_atom_einstein_A(self._h, t) if kind.value == 0 else 0.0)
+
+    def lte(self, T: float, n_e: float, n_tot: float) -> np.ndarray:
+        out = np.empty(self.n_levels)
+        lib().orc_lte_populations(self._h, T, n_e, n_tot, _p(out))
+        return out
+
+
+def gauss_legendre(n: int):
+    x, w = np.empty(n), np.empty(n)
+    if lib().orc_gauss_legendre(n, _p(x), _p(w)) != 0:
+        raise ValueError("n out of range")
+    return x, w
+
+
+def voigt(a: float, v: float) -> float:
+    return lib().orc_voigt_H(float(a), float(v))
+
+
+def sc_coefficients(x: float):
+    e, wa, wb = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_sc_coefficients(float(x), C.byref(e), C.byref(wa), C.byref(wb))
+    return e.value, wa.value, wb.value
+
+
+def formal_ray(dtau, S, I0: float):
+    dtau = np.ascontiguousarray(dtau, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    n = len(S)
+    I, ls = np.empty(n), np.empty(n)
+    lib().orc_formal_ray(n, _p(dtau), _p(S), float(I0), _p(I), _p(ls))
+    return I, ls
+
+
+def ng_step(iterates):
+    """Order-2 Ng extrapolation from iterates [x0 (newest), x1, x2, x3];
+    returns the extrapolated vector or None when the step is skipped."""
+    xs = [np.ascontiguousarray(x, dtype=np.float64) for x in iterates]
+    arr = (C.POINTER(C.c_double) * len(xs))(*[_p(x) for x in xs])
+    out = np.empty_like(xs[0])
+    ok = lib().orc_ng_step(2, len(out), arr, _p(out))
+    return out if ok else None
+
+
+def profile_norm(atom: Atom, col: dict, n_mu: int):
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    nstar = np.empty((N, atom.n_levels))
+    norm = np.empty((max(atom.n_lines, 1), N))
+    lib().orc_column_profile_norm(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                  n_mu, _p(nstar), _p(norm))
+    return nstar, norm[: atom.n_lines]
+
+
+def solve_column(atom: Atom, col: dict, n_mu: int = 5, tol: float = 1e-4, max_iter: int = 200,
+                 ng_order: int = 2, ng_delay: int = 5, ng_period: int = 4, start: int = START_LTE,
+                 coll_scale: float = 1.0, init_pops=None, want_spectrum: bool = True,
+                 want_psi: bool = False) -> dict:
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale)
+    pops = np.empty((N, atom.n_levels))
+    hist = np.empty(max(max_iter, 1))
+    spec = np.empty(atom.n_lambda) if want_spectrum else None
+    psi = np.empty((atom.n_trans, N)) if want_psi else None
+    ip = None
+    if init_pops is not None:
+        ip = np.ascontiguousarray(init_pops, dtype=np.float64).reshape(N, atom.n_levels)
+    n_iter, status = C.c_int(), C.c_int()
+    rc = lib().orc_solve_column(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                _p(ip), C.byref(o), _p(pops), _p(hist), C.byref(n_iter), C.byref(status),
+                                _p(spec), _p(psi))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return dict(pops=pops, history=hist[:max_iter], n_iter=n_iter.value, status=status.value, spectrum=spec,
+                psi_star=psi)
+
+
+def solve_columns(atom: Atom, columns, threads: int | None = None, **kw) -> list:
+    """Solve columns independently on a thread pool (ctypes releases the
+    GIL during the call), one column per task, dynamic assignment."""
+    threads = threads or os.cpu_count() or 1
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(solve_column, atom, columns.column(c), **kw) for c in range(columns.n_columns)]
+        return [f.result() for f in futs]

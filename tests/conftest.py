@@ -1,0 +1,64 @@
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_1411_1079_amd import synth  # noqa: E402
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library)")
+    config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+@pytest.fixture(scope="session")
+def atom_dir(tmp_path_factory):
+    d = tmp_path_factory.mktemp("atoms")
+    paths = synth.write_atoms(str(d))
+    paths["tiny"] = write_tiny_atom(os.path.join(str(d), "tiny.atom"))
+    paths["tiny_nobg"] = write_tiny_atom(os.path.join(str(d), "tiny_nobg.atom"), c_bg=None)
+    return paths
+
+
+TINY_MASS = 1.00794
+
+
+def write_tiny_atom(path, c_bg=1.0e-38):
+    """Four-level test atom with Gaussian profiles and every kind of
+    overlap: two lines with the same rest wavelength (a full blend), a
+    line inside a continuum, and two overlapping continua."""
+    levels = [(0.0, 2.0, 0), (1.5, 2.0, 0), (3.0, 4.0, 0), (5.9, 1.0, 1)]
+    ev = synth._EV
+    hc = synth._H * synth._C
+
+    def lam0(lo, hi):
+        return hc / ((levels[hi][0] - levels[lo][0]) * ev) * 1e9
+
+    lines = [
+        dict(l=0, u=1, f=3e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(0, 1), n=9, x_max=4.0)),
+        dict(l=1, u=2, f=2e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(1, 2), n=9, x_max=4.0)),
+        dict(l=0, u=2, f=1e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(0, 2), n=9, x_max=4.0)),
+    ]
+    conts = [dict(l=i, u=3, alpha=a, coll="OMEGA", cval=0.1,
+                  lam=np.sort(synth.continuum_grid_nm(lam0(i, 3), n=5)))
+             for i, a in ((0, 1e-22), (1, 2e-22), (2, 3e-22))]
+    return synth.write_atom(path, "TINY", TINY_MASS, 1.0, levels, lines, conts, c_bg)
+
+
+def tiny_column(n_depth=8, vz=3.0e3):
+    """Short column for the tiny atom: lines thin at the top and thick at
+    the bottom, a temperature minimum, and a velocity gradient."""
+    z = np.linspace(1.2e6, 0.0, n_depth)
+    T = 3200.0 + 400.0 * np.cos(np.linspace(0.0, 3.0, n_depth))
+    nH = 1.0e20 * np.exp(-z / 1.5e5)
+    ne = 1.0e-3 * nH
+    v = vz * np.linspace(1.0, -1.0, n_depth)
+    return dict(z=z, T=T, n_e=ne, n_H=nH, v_z=v, v_turb=np.full(n_depth, 1.0e3))
