@@ -1,0 +1,1183 @@
+// librh15d: per-column multi-level accelerated Lambda iteration (MALI) on
+// MI355X (gfx950).
+//
+// Method (paper Sec. 2.1-2.3): Rybicki & Hummer (1992) MALI with a local
+// diagonal Psi* operator, fully preconditioned rate equations and
+// overlapping transitions, per column (1.5D), Ng acceleration, LTE /
+// zero-radiation / provided start solutions, convergence on the maximum
+// relative population change; vertical emergent spectra only.
+//
+// Mapping onto CDNA4:
+//  * formal solution (k_raysweep): one lane per ray (wavelength, angle,
+//    direction) of a column; the 64 rays of a wavefront share one set of
+//    active transitions, walk the depth recurrence in lock-step, read the
+//    per-depth column data as wave-uniform (scalar) loads and the
+//    normalised line profiles as coalesced rows, and reduce their rate
+//    contributions across the wavefront at every depth, in a fixed order,
+//    into per-depth rate keys (no atomics: results are bitwise
+//    reproducible);
+//  * rate-equation solve (k_se): one lane per depth point, an L x L FP64
+//    system in registers, Gaussian elimination with partial pivoting;
+//  * convergence test and Ng (k_converge): one workgroup per column;
+//  * precision form: the sweep and its rate accumulation in FP32, the rate
+//    solve, Ng and the convergence test in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rh15d_internal.h"
+
+using namespace rh15d;
+
+namespace {
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                  \
+            return RH15D_EDEVICE;                                                      \
+        }                                                                              \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device math
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double d_exp(double x) { return exp(x); }
+__device__ __forceinline__ float d_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
+
+// Linear short-characteristic weights (Olson & Kunasz 1987) of an optical
+// step x: I_b = I_a e + wa S_a + wb S_b.  Below the threshold the weights
+// come from their Taylor series (through x^6), which avoids the
+// cancellation in 1 - (1 - e^-x)/x.
+template <typename R>
+__device__ __forceinline__ void sc_weights(R x, R &e, R &wa, R &wb) {
+    const R thr = sizeof(R) == 8 ? R(1.0e-2) : R(0.1);
+    if (x < thr) {
+        wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * (R(-1.0 / 120.0) +
+             x * (R(1.0 / 720.0) + x * R(-1.0 / 5040.0))))));
+        wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
+             x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
+        e = d_exp(-x);
+    } else {
+        const R one_m_e = -d_expm1(-x);
+        const R q = one_m_e / x;
+        e = R(1) - one_m_e;
+        wb = R(1) - q;
+        wa = q - e;
+    }
+}
+
+// Voigt function H(a, v) = Re w(v + i a), Humlicek (1982) W4: a rational
+// approximation in four regions of s = |v| + a (relative accuracy ~1e-4).
+struct cplx { double r, i; };
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cplx cadd(cplx a, double b) { return {a.r + b, a.i}; }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+__device__ __noinline__ double voigt_w4(double a, double v) {
+    const cplx t = {a, -v};          // t = a - i v
+    const double s = fabs(v) + a;
+    if (s >= 15.0) {
+        cplx den = cadd(cmul(t, t), 0.5);
+        return cdiv({0.5641896 * t.r, 0.5641896 * t.i}, den).r;
+    }
+    if (s >= 5.5) {
+        const cplx u = cmul(t, t);
+        const cplx num = cmul(t, cadd({0.5641896 * u.r, 0.5641896 * u.i}, 1.410474));
+        const cplx den = cadd(cmul(u, cadd(u, 3.0)), 0.75);
+        return cdiv(num, den).r;
+    }
+    if (a >= 0.195 * fabs(v) - 0.176) {
+        cplx num = {0.5642236, 0.0};
+        num = cadd(cmul(num, t), 3.778987);
+        num = cadd(cmul(num, t), 11.96482);
+        num = cadd(cmul(num, t), 20.20933);
+        num = cadd(cmul(num, t), 16.4955);
+        cplx den = {1.0, 0.0};
+        den = cadd(cmul(den, t), 6.699398);
+        den = cadd(cmul(den, t), 21.69274);
+        den = cadd(cmul(den, t), 39.27121);
+        den = cadd(cmul(den, t), 38.82363);
+        den = cadd(cmul(den, t), 16.4955);
+        return cdiv(num, den).r;
+    }
+    const cplx u = cmul(t, t);
+    cplx p = {0.56419, 0.0};
+    p = cadd(cmul(p, u), -1.320522);
+    p = cadd(cmul(p, u), 35.76683);
+    p = cadd(cmul(p, u), -219.0313);
+    p = cadd(cmul(p, u), 1540.787);
+    p = cadd(cmul(p, u), -3321.9905);
+    p = cadd(cmul(p, u), 36183.31);
+    cplx q = {-1.0, 0.0};
+    q = cadd(cmul(q, u), 1.841439);
+    q = cadd(cmul(q, u), -61.57037);
+    q = cadd(cmul(q, u), 364.2191);
+    q = cadd(cmul(q, u), -2186.181);
+    q = cadd(cmul(q, u), 9022.228);
+    q = cadd(cmul(q, u), -24322.84);
+    q = cadd(cmul(q, u), 32066.6);
+    const cplx frac = cdiv(cmul(t, p), q);
+    return exp(u.r) * cos(u.i) - frac.r;
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+    // butterfly over the 64 lanes: every lane ends with the same total,
+    // summed in the same order on every launch
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// rays (2 directions x angles x wavelengths) of one line at one depth that
+// the profile-preparation wavefront holds in registers
+constexpr int kMaxLineRays = 1536;
+
+// ---------------------------------------------------------------------------
+// per-launch arguments
+// ---------------------------------------------------------------------------
+struct ChunkArgs {
+    DevAtom A;
+    const int64_t *doff;      // [n_columns+1] global depth offsets (device)
+    int c_first, S;           // columns of this chunk
+    int64_t G0;               // global depth index of the chunk's first point
+    int64_t TD;               // depth points in the chunk
+    // inputs (global depth index)
+    const double *z, *T, *ne, *nH, *vz, *vt, *init;
+    // outputs
+    double *pops, *history, *spectrum, *psi;
+    int32_t *n_iter, *status;
+    // workspace (chunk-local depth index gc)
+    double *lnr;              // [TD][L] Saha-Boltzmann log ratios to level 0
+    double *kbg;              // [TD] background opacity at the reference wavelength
+    double *gr;               // [TD][n_cont] n*_l / n*_u of each continuum
+    double *norm;             // [TD][n_lines] profile normalisation sums
+    void *phi;                // [TD][ray_cols] normalised profiles (double or float)
+    void *part;               // rate keys: column block at gc0*n_keys, [key][N]
+    double *nse;              // [TD][L] rate-equation solution
+    double *dk;               // [TD] max relative change per depth point
+    int *flag;                // [TD] 0 ok, 1 non-finite/non-positive, 2 singular
+    double *ring;             // [4][TD][L] Ng history
+    int *col_done, *col_it, *ng_count, *ng_head;  // [S]
+    int *done_counter;
+    int max_iter, ng_order, ng_delay, ng_period, start;
+    double tol, coll_scale;
+};
+
+__device__ __forceinline__ int find_column(const ChunkArgs &a, int64_t gc) {
+    // last column of the chunk whose first point is <= gc
+    int lo = 0, hi = a.S - 1;
+    const int64_t g = gc + a.G0;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.doff[a.c_first + mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// column preparation
+// ---------------------------------------------------------------------------
+__global__ void k_prep_depth(ChunkArgs a) {
+    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gc >= a.TD) return;
+    const int64_t g = gc + a.G0;
+    const DevAtom &A = a.A;
+    const int L = A.L;
+    const double T = a.T[g], ne = a.ne[g], nH = a.nH[g];
+    const double kT = kKB * T;
+    const double saha = log(2.0 / ne) + 1.5 * log(2.0 * kPI * kME * kT / (kH * kH));
+    double lr[RH15D_MAX_LEVELS];
+    double mx = -1e300;
+    for (int i = 0; i < L; i++) {
+        lr[i] = log(A.g[i] / A.g[0]) - (A.E[i] - A.E[0]) / kT + (A.stage[i] - A.stage[0]) * saha;
+        a.lnr[gc * L + i] = lr[i];
+        mx = fmax(mx, lr[i]);
+    }
+    double sum = 0.0;
+    for (int i = 0; i < L; i++) sum += exp(lr[i] - mx);
+    const double ntot = A.abund * nH;
+    for (int i = 0; i < L; i++) {
+        double v;
+        if (a.start == RH15D_START_PROVIDED) v = a.init[g * L + i];
+        else v = ntot * exp(lr[i] - mx) / sum;
+        a.pops[g * L + i] = v;
+    }
+    a.kbg[gc] = A.bg_kind == 1 ? A.c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T) : 0.0;
+    for (int c = 0; c < A.n_cont; c++) {
+        const DevTransition &tr = A.tr[A.n_lines + c];
+        a.gr[gc * A.n_cont + c] = exp(lr[tr.l] - lr[tr.u]);
+    }
+}
+
+// One wavefront per (depth point, line): every quadrature ray's profile,
+// normalised so that sum over rays of W phi = 1 at this depth.
+template <typename R>
+__global__ __launch_bounds__(256) void k_prep_profile(ChunkArgs a) {
+    constexpr int kPer = kMaxLineRays / kWave;  // rays per lane
+    const DevAtom &A = a.A;
+    const int64_t pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (pair >= a.TD * A.n_lines) return;
+    const int64_t gc = pair / A.n_lines;
+    const int t = (int)(pair % A.n_lines);
+    const int64_t g = gc + a.G0;
+    const DevTransition &tr = A.tr[t];
+    const double T = a.T[g], vt = a.vt[g], vz = a.vz[g];
+    const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * T / A.mass + vt * vt);
+    const double adamp = tr.gamma / (4.0 * kPI * dnd);
+    const double pre = 1.0 / (sqrt(kPI) * dnd);
+    const int na = tr.n_act, nmu = A.n_mu, nr = 2 * na * nmu;
+    double ph[kPer];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const int r = lane + kWave * i;
+        ph[i] = 0.0;
+        if (r < nr) {
+            const int s = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+            const int j = A.act_j[tr.act_off + ja];
+            const double mus = s ? A.mu[m] : -A.mu[m];
+            const double v = (A.nu[j] - tr.nu0 * (1.0 + mus * vz / kC)) / dnd;
+            const double H = tr.voigt ? voigt_w4(adamp, v) : exp(-v * v);
+            ph[i] = H * pre;
+            acc += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * ph[i];
+        }
+    }
+    const double tot = wave_sum(acc);
+    R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
+#pragma unroll
+    for (int i = 0; i < kPer; i++) {
+        const int r = lane + kWave * i;
+        if (r < nr) phi[r] = static_cast<R>(ph[i] / tot);
+    }
+    if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// formal solution + preconditioned rate accumulation
+// ---------------------------------------------------------------------------
+enum { MODE_RATES = 0, MODE_PSI = 1 };
+
+template <typename R>
+struct PointTerms {
+    R chi, eta, etabg, S, B;
+    R vlu[kMaxSlots], vul[kMaxSlots], U[kMaxSlots], chit[kMaxSlots];
+};
+
+// Opacity and emissivity of a lane's ray at chunk-local depth gc.
+template <typename R>
+__device__ __forceinline__ void point_terms(const ChunkArgs &a, const DevGroup &G, int64_t gc, int64_t g,
+                                            const R *phirow, const int *pidx, const R *alpha, R hnu_k,
+                                            R two_hnu3, R lamfac, PointTerms<R> &p) {
+    const DevAtom &A = a.A;
+    const int L = A.L;
+    const R T = static_cast<R>(a.T[g]);
+    const R x = hnu_k / T;
+    const R ex = d_exp(-x);          // exp(-h nu / k T), kept to full relative precision
+    const R omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
+    p.B = two_hnu3 * ex / omx;
+    const R chibg = static_cast<R>(a.kbg[gc]) * lamfac;
+    p.etabg = chibg * p.B;
+    R chi = chibg, eta = p.etabg;
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) {
+        if (q < G.n_slots) {
+            const DevTransition &tr = A.tr[G.t[q]];
+            const R nl = static_cast<R>(a.pops[g * L + tr.l]);
+            const R nu = static_cast<R>(a.pops[g * L + tr.u]);
+            R vlu, vul, U;
+            if (tr.kind == 0) {
+                const R ph = phirow[pidx[q]];
+                const R c = static_cast<R>(tr.hnu4pi);
+                vlu = c * static_cast<R>(tr.Blu) * ph;
+                vul = c * static_cast<R>(tr.Bul) * ph;
+                U = c * static_cast<R>(tr.A) * ph;
+            } else {
+                const R gf = static_cast<R>(a.gr[gc * A.n_cont + (G.t[q] - A.n_lines)]) * ex;
+                vlu = alpha[q];
+                vul = gf * alpha[q];
+                U = two_hnu3 * gf * alpha[q];
+            }
+            p.vlu[q] = vlu; p.vul[q] = vul; p.U[q] = U;
+            p.chit[q] = nl * vlu - nu * vul;
+            chi += p.chit[q];
+            eta += nu * U;
+        }
+    }
+    p.chi = chi;
+    p.eta = eta;
+    p.S = eta / chi;
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void accumulate(const ChunkArgs &a, const DevGroup &G, const PointTerms<R> &p,
+                                           const R *kap, const R *om, R Ieff, R psi, R *out, int N, int k,
+                                           int lane) {
+    if (MODE == MODE_PSI) {
+#pragma unroll
+        for (int q = 0; q < kMaxSlots; q++) {
+            if (q < G.n_slots) {
+                const R v = wave_sum(om[q] * psi);
+                if (lane == 0) out[(size_t)q * N + k] = v;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) {
+        if (q < G.n_slots) {
+            const R cp = wave_sum(kap[q] * p.vlu[q] * Ieff);
+            const R cq = wave_sum(kap[q] * (p.U[q] * (R(1) - p.chit[q] * psi) + p.vul[q] * Ieff));
+            if (lane == 0) {
+                out[(size_t)q * N + k] = cp;
+                out[(size_t)(G.n_slots + q) * N + k] = cq;
+            }
+        }
+    }
+    for (int pp = 0; pp < G.n_pairs; pp++) {
+        const int q = G.pair[pp] / kMaxSlots, q2 = G.pair[pp] % kMaxSlots;
+        R chq = 0, kq = 0, u2 = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxSlots; i++) {
+            if (i == q) { chq = p.chit[i]; kq = kap[i]; }
+            if (i == q2) u2 = p.U[i];
+        }
+        const R cx = wave_sum(kq * chq * psi * u2);
+        if (lane == 0) out[(size_t)(2 * G.n_slots + pp) * N + k] = cx;
+    }
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_raysweep(ChunkArgs a) {
+    const DevAtom &A = a.A;
+    const int grp = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int colc = blockIdx.y;
+    if (grp >= A.n_groups) return;
+    if (MODE == MODE_RATES && a.col_done[colc]) return;
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = (int)(a.doff[c + 1] - g0);
+    const int64_t gc0 = g0 - a.G0;
+    const DevGroup G = A.groups[grp];
+    const int li = grp * kWave + lane;
+    const R mu = static_cast<R>(A.lanes.mu[li]);
+    const R lamfac = static_cast<R>(A.lanes.lamfac[li]);
+    const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
+    const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
+    int pidx[kMaxSlots];
+    R kap[kMaxSlots], alpha[kMaxSlots], om[kMaxSlots];
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) {
+        pidx[q] = A.lanes.phi_idx[li * kMaxSlots + q];
+        kap[q] = static_cast<R>(A.lanes.kap[li * kMaxSlots + q]);
+        alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
+        const double W = A.lanes.W[li * kMaxSlots + q];
+        om[q] = static_cast<R>(q < G.n_slots && A.tr[G.t[q]].kind == 1 ? W / A.tr[G.t[q]].wsum : W);
+    }
+    R *out = reinterpret_cast<R *>(a.part) + gc0 * A.n_keys + (size_t)G.key_off * N;
+    const R *phi = reinterpret_cast<const R *>(a.phi);
+    PointTerms<R> p;
+
+
+    if (G.s == 0) {
+        // downward rays: from the top (k = 0, no incoming radiation) to the bottom
+        int64_t gc = gc0, g = g0;
+        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+        R omk[kMaxSlots];
+#pragma unroll
+        for (int q = 0; q < kMaxSlots; q++) omk[q] = om[q];
+        if constexpr (MODE == MODE_PSI) {
+#pragma unroll
+            for (int q = 0; q < kMaxSlots; q++)
+                if (q < G.n_slots && A.tr[G.t[q]].kind == 0) omk[q] = om[q] * phi[gc * A.ray_cols + pidx[q]];
+        }
+        accumulate<R, MODE>(a, G, p, kap, omk, R(0), R(0), out, N, 0, lane);
+        R I = 0, chi_prev = p.chi, S_prev = p.S;
+        R z_prev = static_cast<R>(a.z[g]);
+        for (int k = 1; k < N; k++) {
+            gc = gc0 + k; g = g0 + k;
+            point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+            const R zk = static_cast<R>(a.z[g]);
+            const R x = R(0.5) * (chi_prev + p.chi) * (z_prev - zk) / mu;
+            R e, wa, wb;
+            sc_weights<R>(x, e, wa, wb);
+            const R up = I * e + wa * S_prev;
+            const R Ieff = up + wb * p.etabg / p.chi;
+            const R psi = wb / p.chi;
+            I = up + wb * p.S;
+            if constexpr (MODE == MODE_PSI) {
+#pragma unroll
+                for (int q = 0; q < kMaxSlots; q++)
+                    omk[q] = (q < G.n_slots && A.tr[G.t[q]].kind == 0) ? om[q] * phi[gc * A.ray_cols + pidx[q]] : om[q];
+            }
+            accumulate<R, MODE>(a, G, p, kap, omk, Ieff, psi, out, N, k, lane);
+            chi_prev = p.chi; S_prev = p.S; z_prev = zk;
+        }
+    } else {
+        // upward rays: diffusion approximation at the bottom, then to the top
+        int64_t gc = gc0 + N - 2, g = g0 + N - 2;
+        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+        const R chi2 = p.chi, B2 = p.B;
+        gc = gc0 + N - 1; g = g0 + N - 1;
+        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+        const R dtv = R(0.5) * (p.chi + chi2) * static_cast<R>(a.z[g - 1] - a.z[g]);
+        R I = dtv > R(0) ? p.B + mu * (p.B - B2) / dtv : p.B;
+        R omk[kMaxSlots];
+#pragma unroll
+        for (int q = 0; q < kMaxSlots; q++) omk[q] = om[q];
+        if constexpr (MODE == MODE_PSI) {
+#pragma unroll
+            for (int q = 0; q < kMaxSlots; q++)
+                if (q < G.n_slots && A.tr[G.t[q]].kind == 0) omk[q] = om[q] * phi[gc * A.ray_cols + pidx[q]];
+        }
+        accumulate<R, MODE>(a, G, p, kap, omk, I, R(0), out, N, N - 1, lane);
+        R chi_prev = p.chi, S_prev = p.S;
+        R z_prev = static_cast<R>(a.z[g]);
+        for (int k = N - 2; k >= 0; k--) {
+            gc = gc0 + k; g = g0 + k;
+            point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+            const R zk = static_cast<R>(a.z[g]);
+            const R x = R(0.5) * (chi_prev + p.chi) * (zk - z_prev) / mu;
+            R e, wa, wb;
+            sc_weights<R>(x, e, wa, wb);
+            const R up = I * e + wa * S_prev;
+            const R Ieff = up + wb * p.etabg / p.chi;
+            const R psi = wb / p.chi;
+            I = up + wb * p.S;
+            if constexpr (MODE == MODE_PSI) {
+#pragma unroll
+                for (int q = 0; q < kMaxSlots; q++)
+                    omk[q] = (q < G.n_slots && A.tr[G.t[q]].kind == 0) ? om[q] * phi[gc * A.ray_cols + pidx[q]] : om[q];
+            }
+            accumulate<R, MODE>(a, G, p, kap, omk, Ieff, psi, out, N, k, lane);
+            chi_prev = p.chi; S_prev = p.S; z_prev = zk;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// statistical equilibrium per depth point
+// ---------------------------------------------------------------------------
+template <typename R, int L, bool ZERO_RAD>
+__global__ __launch_bounds__(256) void k_se(ChunkArgs a) {
+    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gc >= a.TD) return;
+    const int colc = find_column(a, gc);
+    if (!ZERO_RAD && a.col_done[colc]) return;
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = (int)(a.doff[c + 1] - g0);
+    const int64_t gc0 = g0 - a.G0;
+    const int k = (int)(gc - gc0);
+    const int64_t g = gc + a.G0;
+    const DevAtom &A = a.A;
+    const R *part = reinterpret_cast<const R *>(a.part) + gc0 * A.n_keys;
+    double M[L][L];
+    double nold[L], b[L];
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        nold[i] = a.pops[g * L + i];
+#pragma unroll
+        for (int j = 0; j < L; j++) M[i][j] = 0.0;
+    }
+    const double T = a.T[g], ne = a.ne[g];
+    for (int t = 0; t < A.T; t++) {
+        const DevTransition &tr = A.tr[t];
+        const int l = tr.l, u = tr.u;
+        double P = 0.0, Q = 0.0;
+        if (ZERO_RAD) {
+            // no radiation: only spontaneous de-excitation / recombination
+            if (tr.kind == 0) {
+                Q = tr.A;
+            } else {
+                const double G0 = a.gr[gc * A.n_cont + (t - A.n_lines)];
+                for (int ja = 0; ja < tr.n_act; ja++) {
+                    const double nu = A.nu[A.act_j[tr.act_off + ja]];
+                    const double G = G0 * exp(-kH * nu / (kKB * T));
+                    const double alpha = tr.alpha0 * pow(tr.nu0 / nu, 3.0);
+                    Q += 4.0 * kPI * A.act_w[tr.act_off + ja] / (kH * nu) * 2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha;
+                }
+            }
+        } else {
+            for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) P += static_cast<double>(part[(size_t)A.p_key[i] * N + k]);
+            for (int i = A.q_off[t]; i < A.q_off[t + 1]; i++) Q += static_cast<double>(part[(size_t)A.q_key[i] * N + k]);
+        }
+#pragma unroll
+        for (int i = 0; i < L; i++) {
+            if (i == u) { M[i][l] += P; M[i][i] -= Q; }
+            if (i == l) { M[i][i] -= P; M[i][u] += Q; }
+        }
+        // electron collisions, detailed balance between the two levels
+        double Cul;
+        if (tr.coll_kind == 0) {
+            Cul = ne * kCollC0 * tr.coll_val / (A.g[u] * sqrt(T));
+        } else {
+            const double x = kH * tr.nu0 / (kKB * T);
+            Cul = tr.coll_val / (1.0 - tr.coll_val) * tr.A / (-expm1(-x));
+        }
+        Cul *= a.coll_scale;
+        const double Clu = Cul * exp(a.lnr[gc * L + u] - a.lnr[gc * L + l]);
+#pragma unroll
+        for (int i = 0; i < L; i++) {
+            if (i == l) { M[i][u] += Cul; M[i][i] -= Clu; }
+            if (i == u) { M[i][l] += Clu; M[i][i] -= Cul; }
+        }
+    }
+    if (!ZERO_RAD) {
+        for (int x = 0; x < A.n_xpairs; x++) {
+            double X = 0.0;
+            for (int i = A.x_off[x]; i < A.x_off[x + 1]; i++) X += static_cast<double>(part[(size_t)A.x_key[i] * N + k]);
+            const int l = A.tr[A.x_t[x]].l, u = A.tr[A.x_t[x]].u, u2 = A.tr[A.x_t2[x]].u;
+#pragma unroll
+            for (int i = 0; i < L; i++) {
+#pragma unroll
+                for (int j = 0; j < L; j++) {
+                    if (j == u2 && i == u) M[i][j] += X;
+                    if (j == u2 && i == l) M[i][j] -= X;
+                }
+            }
+        }
+    }
+    // particle conservation replaces the equation of the most populated level
+    int istar = 0;
+#pragma unroll
+    for (int i = 1; i < L; i++) if (nold[i] > nold[istar]) istar = i;
+    const double ntot = A.abund * a.nH[g];
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        b[i] = (i == istar) ? ntot : 0.0;
+#pragma unroll
+        for (int j = 0; j < L; j++) if (i == istar) M[i][j] = 1.0;
+    }
+    // Gaussian elimination with partial pivoting (first largest pivot)
+    bool singular = false;
+#pragma unroll
+    for (int col = 0; col < L; col++) {
+        int p = col;
+        double best = fabs(M[col][col]);
+#pragma unroll
+        for (int r = col + 1; r < L; r++) if (fabs(M[r][col]) > best) { best = fabs(M[r][col]); p = r; }
+        if (best == 0.0) singular = true;
+#pragma unroll
+        for (int r = col + 1; r < L; r++) {
+            if (r == p) {
+#pragma unroll
+                for (int j = 0; j < L; j++) { double tmp = M[col][j]; M[col][j] = M[r][j]; M[r][j] = tmp; }
+                double tmp = b[col]; b[col] = b[r]; b[r] = tmp;
+            }
+        }
+#pragma unroll
+        for (int r = col + 1; r < L; r++) {
+            const double f = M[r][col] / M[col][col];
+#pragma unroll
+            for (int j = col; j < L; j++) M[r][j] -= f * M[col][j];
+            b[r] -= f * b[col];
+        }
+    }
+#pragma unroll
+    for (int r = L - 1; r >= 0; r--) {
+        double s = b[r];
+#pragma unroll
+        for (int j = r + 1; j < L; j++) s -= M[r][j] * b[j];
+        b[r] = s / M[r][r];
+    }
+    if (ZERO_RAD) {
+#pragma unroll
+        for (int i = 0; i < L; i++) a.pops[g * L + i] = b[i];
+        return;
+    }
+    double dmax = 0.0;
+    int fl = singular ? 2 : 0;
+#pragma unroll
+    for (int i = 0; i < L; i++) {
+        a.nse[gc * L + i] = b[i];
+        if (!(b[i] > 0.0) || !isfinite(b[i])) { if (fl == 0) fl = 1; }
+        else dmax = fmax(dmax, fabs(b[i] - nold[i]) / b[i]);
+    }
+    a.dk[gc] = dmax;
+    a.flag[gc] = fl;
+}
+
+// ---------------------------------------------------------------------------
+// convergence test and Ng acceleration, one workgroup per column
+// ---------------------------------------------------------------------------
+constexpr int kConvThreads = 256;
+
+__device__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kConvThreads / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ double block_max(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kConvThreads / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
+    __shared__ double sh[kConvThreads];
+    const int colc = blockIdx.x;
+    if (a.col_done[colc]) return;
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = (int)(a.doff[c + 1] - g0);
+    const int64_t gc0 = g0 - a.G0;
+    const int L = a.A.L;
+    const int NV = N * L;
+    const int it = a.col_it[colc] + 1;
+    double dm = 0.0, fl = 0.0;
+    for (int k = threadIdx.x; k < N; k += kConvThreads) {
+        dm = fmax(dm, a.dk[gc0 + k]);
+        fl = fmax(fl, (double)a.flag[gc0 + k]);
+    }
+    dm = block_max(dm, sh);
+    fl = block_max(fl, sh);
+    double *pops = a.pops + g0 * L;
+    const double *nse = a.nse + gc0 * L;
+    int status = -1;
+    if (fl == 2.0) status = RH15D_SINGULAR;
+    else if (fl == 1.0) status = RH15D_NONFINITE;
+    if (a.history && threadIdx.x == 0) a.history[(size_t)c * a.max_iter + it - 1] = fl > 0.0 ? NAN : dm;
+    if (status < 0) {
+        for (int i = threadIdx.x; i < NV; i += kConvThreads) pops[i] = nse[i];
+        if (dm < a.tol) {
+            status = RH15D_CONVERGED;
+        } else if (a.ng_order == 2 && it >= a.ng_delay) {
+            const size_t stride = (size_t)a.TD * L;
+            int head = (a.ng_head[colc] + 1) & 3;
+            double *newest = a.ring + head * stride + gc0 * L;
+            for (int i = threadIdx.x; i < NV; i += kConvThreads) newest[i] = nse[i];
+            int cnt = a.ng_count[colc] + 1;
+            const int need = a.ng_period > 4 ? a.ng_period : 4;
+            if (cnt >= need) {
+                const double *x0 = a.ring + head * stride + gc0 * L;
+                const double *x1 = a.ring + ((head + 3) & 3) * stride + gc0 * L;
+                const double *x2 = a.ring + ((head + 2) & 3) * stride + gc0 * L;
+                const double *x3 = a.ring + ((head + 1) & 3) * stride + gc0 * L;
+                double s11 = 0, s12 = 0, s22 = 0, r1 = 0, r2 = 0;
+                for (int i = threadIdx.x; i < NV; i += kConvThreads) {
+                    const double w = 1.0 / (x0[i] * x0[i]);
+                    const double d0 = x0[i] - x1[i], d1 = x1[i] - x2[i], d2 = x2[i] - x3[i];
+                    const double e1 = d0 - d1, e2 = d0 - d2;
+                    s11 += w * e1 * e1; s12 += w * e1 * e2; s22 += w * e2 * e2;
+                    r1 += w * d0 * e1; r2 += w * d0 * e2;
+                }
+                s11 = block_sum(s11, sh); s12 = block_sum(s12, sh); s22 = block_sum(s22, sh);
+                r1 = block_sum(r1, sh); r2 = block_sum(r2, sh);
+                const double det = s11 * s22 - s12 * s12;
+                if (fabs(det) > 1e-14 * s11 * s22) {
+                    const double a1 = (r1 * s22 - r2 * s12) / det, a2 = (r2 * s11 - r1 * s12) / det;
+                    double bad = 0.0;
+                    for (int i = threadIdx.x; i < NV; i += kConvThreads) {
+                        const double v = (1.0 - a1 - a2) * x0[i] + a1 * x1[i] + a2 * x2[i];
+                        if (!(v > 0.0)) bad = 1.0;
+                    }
+                    bad = block_max(bad, sh);
+                    if (bad == 0.0)
+                        for (int i = threadIdx.x; i < NV; i += kConvThreads)
+                            pops[i] = (1.0 - a1 - a2) * x0[i] + a1 * x1[i] + a2 * x2[i];
+                }
+                cnt = 0;
+            }
+            if (threadIdx.x == 0) { a.ng_head[colc] = head; a.ng_count[colc] = cnt; }
+        }
+        if (status < 0 && it >= a.max_iter) status = RH15D_MAX_ITER;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.col_it[colc] = it;
+        if (status >= 0) {
+            a.col_done[colc] = 1;
+            a.status[c] = status;
+            a.n_iter[c] = it;
+            atomicAdd(a.done_counter, 1);
+        }
+    }
+}
+
+__global__ void k_init_columns(ChunkArgs a) {
+    const int colc = blockIdx.x * blockDim.x + threadIdx.x;
+    if (colc >= a.S) return;
+    const int c = a.c_first + colc;
+    a.col_done[colc] = a.max_iter == 0 ? 1 : 0;
+    a.col_it[colc] = 0;
+    a.ng_count[colc] = 0;
+    a.ng_head[colc] = 0;
+    a.status[c] = RH15D_MAX_ITER;
+    a.n_iter[c] = 0;
+    if (a.history)
+        for (int i = 0; i < a.max_iter; i++) a.history[(size_t)c * a.max_iter + i] = NAN;
+}
+
+// ---------------------------------------------------------------------------
+// vertical emergent intensity, one lane per (column, wavelength)
+// ---------------------------------------------------------------------------
+__device__ void point_opacity_mu1(const ChunkArgs &a, int j, int64_t gc, int64_t g, double &chi, double &S,
+                                  double &B) {
+    const DevAtom &A = a.A;
+    const int L = A.L;
+    const double nu = A.nu[j];
+    const double T = a.T[g];
+    const double x = kH * nu / (kKB * T);
+    const double ex = exp(-x), omx = x > 0.5 ? 1.0 - ex : -expm1(-x);
+    const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
+    B = two_hnu3 * ex / omx;
+    double c = a.kbg[gc] * (A.lam[j] / kBgLambdaRef);
+    double e = c * B;
+    const double w = sqrt(2.0 * kKB * T / A.mass + a.vt[g] * a.vt[g]);
+    for (int i = A.jact_off[j]; i < A.jact_off[j + 1]; i++) {
+        const int t = A.jact_t[i];
+        const DevTransition &tr = A.tr[t];
+        double vlu, vul, U;
+        if (tr.kind == 0) {
+            const double dnd = tr.nu0 / kC * w;
+            const double v = (nu - tr.nu0 * (1.0 + a.vz[g] / kC)) / dnd;
+            const double H = tr.voigt ? voigt_w4(tr.gamma / (4.0 * kPI * dnd), v) : exp(-v * v);
+            const double ph = H / (sqrt(kPI) * dnd) / a.norm[gc * A.n_lines + t];
+            vlu = tr.hnu4pi * tr.Blu * ph; vul = tr.hnu4pi * tr.Bul * ph; U = tr.hnu4pi * tr.A * ph;
+        } else {
+            const double alpha = tr.alpha0 * pow(tr.nu0 / nu, 3.0);
+            const double G = a.gr[gc * A.n_cont + (t - A.n_lines)] * ex;
+            vlu = alpha; vul = G * alpha; U = two_hnu3 * G * alpha;
+        }
+        c += a.pops[g * L + tr.l] * vlu - a.pops[g * L + tr.u] * vul;
+        e += a.pops[g * L + tr.u] * U;
+    }
+    chi = c;
+    S = e / c;
+}
+
+__global__ void k_emergent(ChunkArgs a) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const DevAtom &A = a.A;
+    if (idx >= (int64_t)a.S * A.NL) return;
+    const int colc = (int)(idx / A.NL), j = (int)(idx % A.NL);
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = (int)(a.doff[c + 1] - g0);
+    const int64_t gc0 = g0 - a.G0;
+    double chi2, S2, B2, chi, S, B;
+    point_opacity_mu1(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
+    point_opacity_mu1(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
+    const double dtv = 0.5 * (chi + chi2) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
+    double I = dtv > 0.0 ? B + (B - B2) / dtv : B;
+    double chi_p = chi, S_p = S;
+    for (int k = N - 2; k >= 0; k--) {
+        point_opacity_mu1(a, j, gc0 + k, g0 + k, chi, S, B);
+        const double x = 0.5 * (chi_p + chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
+        double e, wa, wb;
+        sc_weights<double>(x, e, wa, wb);
+        I = I * e + wa * S_p + wb * S;
+        chi_p = chi; S_p = S;
+    }
+    a.spectrum[(size_t)c * A.NL + j] = I;
+}
+
+template <typename R>
+__global__ void k_psi_gather(ChunkArgs a) {
+    const DevAtom &A = a.A;
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= a.TD * A.T) return;
+    const int64_t gc = idx / A.T;
+    const int t = (int)(idx % A.T);
+    const int colc = find_column(a, gc);
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = (int)(a.doff[c + 1] - g0);
+    const int64_t gc0 = g0 - a.G0;
+    const R *part = reinterpret_cast<const R *>(a.part) + gc0 * A.n_keys;
+    double s = 0.0;
+    for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * N + (gc - gc0)]);
+    a.psi[(gc + a.G0) * A.T + t] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename T>
+int upload(rh15d_atom *atom, const std::vector<T> &v, T **out) {
+    *out = nullptr;
+    if (v.empty()) return RH15D_OK;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, v.size() * sizeof(T)));
+    atom->dev_allocs.push_back(p);
+    HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = static_cast<T *>(p);
+    return RH15D_OK;
+}
+
+int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(atom->mu_);
+    auto key = std::make_pair(dev, n_mu);
+    auto it = atom->dev.find(key);
+    if (it != atom->dev.end()) { *out = &it->second; return RH15D_OK; }
+    HostGroupTables H;
+    build_group_tables(*atom, n_mu, H);
+    if (H.overflow) { set_error("a wavelength has more than %d active transitions", kMaxSlots); return RH15D_EINVAL; }
+    DevAtom D{};
+    D.L = atom->L; D.n_lines = atom->n_lines; D.n_cont = atom->n_cont;
+    D.T = static_cast<int>(atom->tr.size()); D.NL = static_cast<int>(atom->lam.size()); D.n_mu = n_mu;
+    D.n_groups = static_cast<int>(H.groups.size()); D.n_keys = H.n_keys; D.ray_cols = H.ray_cols;
+    D.mass = atom->mass; D.abund = atom->abund; D.c_bg = atom->c_bg; D.bg_kind = atom->bg_kind;
+    std::vector<DevTransition> tr(D.T);
+    std::vector<int> act_j;
+    std::vector<double> act_w;
+    int ray_off = 0;
+    for (int t = 0; t < D.T; t++) {
+        const auto &h = atom->tr[t];
+        DevTransition d{};
+        d.kind = h.kind; d.l = h.l; d.u = h.u; d.voigt = h.voigt; d.coll_kind = h.coll_kind;
+        d.n_act = static_cast<int>(h.act.size()); d.act_off = static_cast<int>(act_j.size());
+        d.ray_off = h.kind == 0 ? ray_off : -1;
+        if (h.kind == 0) ray_off += 2 * d.n_act * n_mu;
+        d.nu0 = h.nu0; d.A = h.A; d.Bul = h.Bul; d.Blu = h.Blu; d.alpha0 = h.alpha0; d.coll_val = h.coll_val;
+        d.gamma = h.gamma; d.hnu4pi = kH * h.nu0 / (4.0 * kPI);
+        d.wsum = 0.0;
+        for (double w : h.w) d.wsum += w;
+        act_j.insert(act_j.end(), h.act.begin(), h.act.end());
+        act_w.insert(act_w.end(), h.w.begin(), h.w.end());
+        tr[t] = d;
+    }
+    if (ray_off != H.ray_cols) { set_error("internal: ray table mismatch"); return RH15D_EINVAL; }
+    for (const auto &d : tr)
+        if (d.kind == 0 && 2 * d.n_act * n_mu > kMaxLineRays) {
+            set_error("a line has %d rays per depth (limit %d)", 2 * d.n_act * n_mu, kMaxLineRays);
+            return RH15D_EINVAL;
+        }
+    int rc = RH15D_OK;
+    std::vector<double> E(atom->E), g(atom->g);
+    std::vector<int> st(atom->stage);
+#define UP(vec, dst) do { if ((rc = upload(atom, vec, dst)) != RH15D_OK) return rc; } while (0)
+    UP(E, &D.E); UP(g, &D.g); UP(st, &D.stage); UP(tr, &D.tr);
+    std::vector<double> lam(atom->lam), nu(atom->nu);
+    UP(lam, &D.lam); UP(nu, &D.nu); UP(act_j, &D.act_j); UP(act_w, &D.act_w);
+    UP(H.mu, &D.mu); UP(H.wmu, &D.wmu);
+    std::vector<int> jo(atom->jact_off), jt(atom->jact_t);
+    UP(jo, &D.jact_off); UP(jt, &D.jact_t);
+    UP(H.groups, &D.groups);
+    UP(H.lane_j, &D.lanes.j); UP(H.lane_m, &D.lanes.m); UP(H.lane_nu, &D.lanes.nu); UP(H.lane_mu, &D.lanes.mu);
+    UP(H.lane_lamfac, &D.lanes.lamfac); UP(H.lane_hnu_k, &D.lanes.hnu_k); UP(H.lane_2hnu3c2, &D.lanes.two_hnu3c2);
+    UP(H.phi_idx, &D.lanes.phi_idx); UP(H.W, &D.lanes.W); UP(H.kap, &D.lanes.kap); UP(H.alpha, &D.lanes.alpha);
+    UP(H.p_off, &D.p_off); UP(H.p_key, &D.p_key); UP(H.q_off, &D.q_off); UP(H.q_key, &D.q_key);
+    D.n_xpairs = static_cast<int>(H.x_t.size());
+    UP(H.x_t, &D.x_t); UP(H.x_t2, &D.x_t2); UP(H.x_off, &D.x_off); UP(H.x_key, &D.x_key);
+#undef UP
+    auto res = atom->dev.emplace(key, D);
+    *out = &res.first->second;
+    return RH15D_OK;
+}
+
+struct Layout {
+    size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_nse, off_dk, off_flag, off_ring,
+        off_cols, off_counter, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const DevAtom &D, int64_t n_columns, int64_t TDmax, int Smax, bool fp32, bool ng) {
+    const size_t R = fp32 ? 4 : 8;
+    Layout l{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    l.off_doff = take((n_columns + 1) * 8);
+    l.off_lnr = take(TDmax * D.L * 8);
+    l.off_kbg = take(TDmax * 8);
+    l.off_gr = take(TDmax * std::max(D.n_cont, 1) * 8);
+    l.off_norm = take(TDmax * std::max(D.n_lines, 1) * 8);
+    l.off_phi = take(TDmax * std::max(D.ray_cols, 1) * R);
+    l.off_part = take(TDmax * D.n_keys * R);
+    l.off_nse = take(TDmax * D.L * 8);
+    l.off_dk = take(TDmax * 8);
+    l.off_flag = take(TDmax * 4);
+    l.off_ring = take(ng ? 4 * TDmax * D.L * 8 : 8);
+    l.off_cols = take((size_t)Smax * 4 * 4);
+    l.off_counter = take(256);
+    l.total = o;
+    return l;
+}
+
+int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *o) {
+    if (!atom || !cols || !o) { set_error("null argument"); return RH15D_EINVAL; }
+    if (cols->n_columns < 0 || (cols->n_columns > 0 && !cols->depth_offset)) { set_error("bad column count or offsets"); return RH15D_EINVAL; }
+    if (o->n_mu < 1 || o->n_mu > RH15D_MAX_MU) { set_error("n_mu must be in 1..%d", RH15D_MAX_MU); return RH15D_EINVAL; }
+    if (o->ng_order != 0 && o->ng_order != 2) { set_error("ng_order must be 0 or 2"); return RH15D_EINVAL; }
+    if (o->max_iter < 0) { set_error("max_iter must be >= 0"); return RH15D_EINVAL; }
+    if (o->precision != RH15D_FP64 && o->precision != RH15D_FP32) { set_error("unknown precision"); return RH15D_EINVAL; }
+    if (o->start < 0 || o->start > 2) { set_error("unknown start"); return RH15D_EINVAL; }
+    if (o->start == RH15D_START_PROVIDED && !cols->init_pops) { set_error("start=PROVIDED needs init_pops"); return RH15D_EINVAL; }
+    if (!(o->tol >= 0.0)) { set_error("tol must be >= 0"); return RH15D_EINVAL; }
+    if (cols->depth_offset && cols->depth_offset[0] != 0) { set_error("depth_offset[0] must be 0"); return RH15D_EINVAL; }
+    for (int64_t c = 0; c < cols->n_columns; c++) {
+        const int64_t n = cols->depth_offset[c + 1] - cols->depth_offset[c];
+        if (n < 2 || n > RH15D_MAX_DEPTH) { set_error("column %lld has %lld depth points (need 2..%d)", (long long)c, (long long)n, RH15D_MAX_DEPTH); return RH15D_EINVAL; }
+    }
+    if (cols->n_columns > 0 && (!cols->z || !cols->T || !cols->n_e || !cols->n_H || !cols->v_z || !cols->v_turb)) {
+        set_error("null column array"); return RH15D_EINVAL;
+    }
+    return RH15D_OK;
+}
+
+// Columns per chunk: the caller's choice, else as many as fit a 24 GiB
+// working set (the device has 288 GB of HBM; chunks this size keep
+// thousands of columns in flight).
+int chunk_columns(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o) {
+    if (o->batch_columns > 0) return (int)std::min<int64_t>(o->batch_columns, std::max<int64_t>(cols->n_columns, 1));
+    const size_t per_point = (o->precision == RH15D_FP32 ? 4 : 8) * (size_t)(D.ray_cols + D.n_keys) + 8 * (6 * D.L + 8);
+    const size_t budget = size_t(24) << 30;
+    const int64_t max_pts = budget / per_point;
+    const int64_t per_col = RH15D_MAX_DEPTH / 2;
+    int64_t S = std::max<int64_t>(1, max_pts / per_col);
+    S = std::min<int64_t>(S, 16384);
+    return (int)std::min<int64_t>(S, std::max<int64_t>(cols->n_columns, 1));
+}
+
+int64_t chunk_max_depth(const rh15d_columns *cols, int S) {
+    int64_t best = 0;
+    for (int64_t c0 = 0; c0 < cols->n_columns; c0 += S) {
+        const int64_t c1 = std::min<int64_t>(cols->n_columns, c0 + S);
+        best = std::max(best, cols->depth_offset[c1] - cols->depth_offset[c0]);
+    }
+    return best;
+}
+
+template <int L>
+void launch_se(ChunkArgs &a, bool fp32, bool zero, hipStream_t st) {
+    const int blocks = (int)((a.TD + 255) / 256);
+    if (fp32) {
+        if (zero) hipLaunchKernelGGL((k_se<float, L, true>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_se<float, L, false>), dim3(blocks), dim3(256), 0, st, a);
+    } else {
+        if (zero) hipLaunchKernelGGL((k_se<double, L, true>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_se<double, L, false>), dim3(blocks), dim3(256), 0, st, a);
+    }
+}
+
+void se_dispatch(ChunkArgs &a, bool fp32, bool zero, hipStream_t st) {
+    switch (a.A.L) {
+        case 2: launch_se<2>(a, fp32, zero, st); break;
+        case 3: launch_se<3>(a, fp32, zero, st); break;
+        case 4: launch_se<4>(a, fp32, zero, st); break;
+        case 5: launch_se<5>(a, fp32, zero, st); break;
+        case 6: launch_se<6>(a, fp32, zero, st); break;
+        case 7: launch_se<7>(a, fp32, zero, st); break;
+        default: launch_se<8>(a, fp32, zero, st); break;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rh15d_last_error(void) { return rh15d::last_error(); }
+
+int rh15d_load_atom(const char *path, rh15d_atom **out) {
+    if (!path || !out) { set_error("null argument"); return RH15D_EINVAL; }
+    *out = nullptr;
+    auto *a = new rh15d_atom();
+    std::string err;
+    int rc = parse_atom_file(path, a, err);
+    if (rc != RH15D_OK) { set_error("%s: %s", path, err.c_str()); delete a; return rc; }
+    *out = a;
+    return RH15D_OK;
+}
+
+void rh15d_free_atom(rh15d_atom *atom) {
+    if (!atom) return;
+    for (void *p : atom->dev_allocs) (void)hipFree(p);
+    delete atom;
+}
+
+int rh15d_atom_get_info(const rh15d_atom *atom, rh15d_atom_info *info) {
+    if (!atom || !info) { set_error("null argument"); return RH15D_EINVAL; }
+    info->n_levels = atom->L;
+    info->n_lines = atom->n_lines;
+    info->n_continua = atom->n_cont;
+    info->n_transitions = static_cast<int>(atom->tr.size());
+    info->n_lambda = static_cast<int>(atom->lam.size());
+    return RH15D_OK;
+}
+
+int rh15d_atom_lambda(const rh15d_atom *atom, double *lambda_host) {
+    if (!atom || !lambda_host) { set_error("null argument"); return RH15D_EINVAL; }
+    std::memcpy(lambda_host, atom->lam.data(), atom->lam.size() * sizeof(double));
+    return RH15D_OK;
+}
+
+int rh15d_default_options(rh15d_options *o) {
+    if (!o) { set_error("null argument"); return RH15D_EINVAL; }
+    o->precision = RH15D_FP64;
+    o->n_mu = 5;
+    o->tol = 1e-4;
+    o->max_iter = 200;
+    o->ng_order = 2;
+    o->ng_delay = 5;
+    o->ng_period = 4;
+    o->start = RH15D_START_LTE;
+    o->coll_scale = 1.0;
+    o->scheduler = RH15D_SCHED_CHUNKED;
+    o->batch_columns = 0;
+    return RH15D_OK;
+}
+
+int rh15d_workspace_size(const rh15d_atom *atom_c, const rh15d_columns *cols, const rh15d_options *o, size_t *bytes) {
+    int rc = validate(atom_c, cols, o);
+    if (rc != RH15D_OK) return rc;
+    if (!bytes) { set_error("null argument"); return RH15D_EINVAL; }
+    DevAtom *D = nullptr;
+    if ((rc = get_dev_atom(const_cast<rh15d_atom *>(atom_c), o->n_mu, &D)) != RH15D_OK) return rc;
+    const int S = chunk_columns(*D, cols, o);
+    const int64_t TD = std::max<int64_t>(chunk_max_depth(cols, S), 2);
+    *bytes = make_layout(*D, cols->n_columns, TD, S, o->precision == RH15D_FP32, o->ng_order == 2).total;
+    return RH15D_OK;
+}
+
+int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, const rh15d_options *o,
+                        const rh15d_outputs *out, void *workspace, size_t workspace_bytes, void *hip_stream) {
+    int rc = validate(atom_c, cols, o);
+    if (rc != RH15D_OK) return rc;
+    if (!out || (cols->n_columns > 0 && (!out->pops || !out->n_iter || !out->status))) {
+        set_error("null output array"); return RH15D_EINVAL;
+    }
+    if (cols->n_columns == 0) return RH15D_OK;
+    rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
+    DevAtom *D = nullptr;
+    if ((rc = get_dev_atom(atom, o->n_mu, &D)) != RH15D_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool fp32 = o->precision == RH15D_FP32;
+    const int S = chunk_columns(*D, cols, o);
+    const int64_t TDmax = std::max<int64_t>(chunk_max_depth(cols, S), 2);
+    const Layout lay = make_layout(*D, cols->n_columns, TDmax, S, fp32, o->ng_order == 2);
+    void *own = nullptr;
+    if (!workspace) {
+        HIP_TRY(hipMalloc(&own, lay.total));
+        workspace = own;
+        workspace_bytes = lay.total;
+    }
+    if (workspace_bytes < lay.total) { set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total); return RH15D_ENOMEM; }
+    char *ws = static_cast<char *>(workspace);
+    int *h_counter = nullptr;
+    int result = RH15D_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        result = RH15D_EDEVICE;
+    };
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h_counter), sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) { fail(e, "hipHostMalloc"); if (own) (void)hipFree(own); return result; }
+
+    ChunkArgs a{};
+    a.A = *D;
+    a.doff = reinterpret_cast<const int64_t *>(ws + lay.off_doff);
+    a.z = cols->z; a.T = cols->T; a.ne = cols->n_e; a.nH = cols->n_H; a.vz = cols->v_z; a.vt = cols->v_turb;
+    a.init = cols->init_pops;
+    a.pops = out->pops; a.history = out->history; a.spectrum = out->spectrum; a.psi = out->psi_star;
+    a.n_iter = out->n_iter; a.status = out->status;
+    a.lnr = reinterpret_cast<double *>(ws + lay.off_lnr);
+    a.kbg = reinterpret_cast<double *>(ws + lay.off_kbg);
+    a.gr = reinterpret_cast<double *>(ws + lay.off_gr);
+    a.norm = reinterpret_cast<double *>(ws + lay.off_norm);
+    a.phi = ws + lay.off_phi;
+    a.part = ws + lay.off_part;
+    a.nse = reinterpret_cast<double *>(ws + lay.off_nse);
+    a.dk = reinterpret_cast<double *>(ws + lay.off_dk);
+    a.flag = reinterpret_cast<int *>(ws + lay.off_flag);
+    a.ring = reinterpret_cast<double *>(ws + lay.off_ring);
+    int *colbuf = reinterpret_cast<int *>(ws + lay.off_cols);
+    a.col_done = colbuf; a.col_it = colbuf + S; a.ng_count = colbuf + 2 * S; a.ng_head = colbuf + 3 * S;
+    a.done_counter = reinterpret_cast<int *>(ws + lay.off_counter);
+    a.max_iter = o->max_iter; a.ng_order = o->ng_order; a.ng_delay = o->ng_delay; a.ng_period = o->ng_period;
+    a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale;
+
+    e = hipMemcpyAsync(const_cast<int64_t *>(a.doff), cols->depth_offset, (cols->n_columns + 1) * sizeof(int64_t),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) fail(e, "copy depth offsets");
+
+    for (int64_t c0 = 0; result == RH15D_OK && c0 < cols->n_columns; c0 += S) {
+        const int64_t c1 = std::min<int64_t>(cols->n_columns, c0 + S);
+        a.c_first = (int)c0;
+        a.S = (int)(c1 - c0);
+        a.G0 = cols->depth_offset[c0];
+        a.TD = cols->depth_offset[c1] - a.G0;
+        const int tdb = (int)((a.TD + 255) / 256);
+        hipLaunchKernelGGL(k_prep_depth, dim3(tdb), dim3(256), 0, st, a);
+        const int64_t pairs = a.TD * D->n_lines;
+        if (pairs > 0) {
+            const int pb = (int)((pairs + 3) / 4);
+            if (fp32) hipLaunchKernelGGL(k_prep_profile<float>, dim3(pb), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_prep_profile<double>, dim3(pb), dim3(256), 0, st, a);
+        }
+        if (o->start == RH15D_START_ZERO_RADIATION) se_dispatch(a, fp32, true, st);
+        hipLaunchKernelGGL(k_init_columns, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
+        e = hipMemsetAsync(a.done_counter, 0, sizeof(int), st);
+        if (e != hipSuccess) { fail(e, "memset"); break; }
+        const dim3 sweep_grid((D->n_groups + 3) / 4, a.S);
+        for (int it = 1; it <= o->max_iter; it++) {
+            if (fp32) hipLaunchKernelGGL((k_raysweep<float, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_raysweep<double, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+            se_dispatch(a, fp32, false, st);
+            hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
+            e = hipMemcpyAsync(h_counter, a.done_counter, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) { fail(e, "iteration"); break; }
+            if (*h_counter >= a.S) break;
+        }
+        if (result != RH15D_OK) break;
+        if (out->spectrum) {
+            const int64_t n = (int64_t)a.S * D->NL;
+            hipLaunchKernelGGL(k_emergent, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, a);
+        }
+        if (out->psi_star) {
+            // Psi* of the final populations: one more sweep, averaging Psi*
+            // per transition instead of accumulating rates
+            if (fp32) hipLaunchKernelGGL((k_raysweep<float, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_raysweep<double, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
+            const int64_t n = a.TD * D->T;
+            if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_psi_gather<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) { fail(e, "kernel launch"); break; }
+    }
+    if (result == RH15D_OK) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) fail(e, "synchronize");
+    }
+    (void)hipHostFree(h_counter);
+    if (own) (void)hipFree(own);
+    return result;
+}
+
+}  // extern "C"
+

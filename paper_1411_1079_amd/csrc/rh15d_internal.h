@@ -1,0 +1,144 @@
+// Internal data structures of librh15d shared by the host-side setup
+// (atom_setup.cpp) and the gfx950 kernels (mali.hip).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+#include <map>
+#include <mutex>
+
+#include "rh15d.h"
+
+namespace rh15d {
+
+// CODATA 2018, SI
+constexpr double kH = 6.62607015e-34;
+constexpr double kC = 2.99792458e8;
+constexpr double kKB = 1.380649e-23;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kQE = 1.602176634e-19;
+constexpr double kEPS0 = 8.8541878128e-12;
+constexpr double kAMU = 1.66053906660e-27;
+constexpr double kPI = 3.14159265358979323846;
+// Omega electron-impact model: C_ul = n_e * kCollC0 * Omega / (g_u sqrt(T))
+constexpr double kCollC0 = 8.629e-12;
+// background law kappa = C_bg n_H n_e T^-3/2 exp(kBgTheta/T) (lambda / kBgLambdaRef)
+constexpr double kBgLambdaRef = 500.0e-9;
+constexpr double kBgTheta = 8750.0;
+
+// A wavefront of 64 rays ("group") touches at most this many transitions.
+constexpr int kMaxSlots = 4;
+constexpr int kMaxPairs = kMaxSlots * (kMaxSlots - 1);
+constexpr int kMaxKeys = 2 * kMaxSlots + kMaxPairs;
+constexpr int kWave = 64;
+
+struct HostTransition {
+    int kind = 0;  // 0 line, 1 continuum
+    int l = 0, u = 0;
+    double f = 0, alpha0 = 0, coll_val = 0;
+    int voigt = 0, coll_kind = 0;
+    std::vector<double> own;  // own sampling, m
+    // derived
+    double nu0 = 0, A = 0, Bul = 0, Blu = 0, gamma = 0, lam_min = 0, lam_max = 0;
+    std::vector<int> act;     // active union indices (increasing wavelength)
+    std::vector<double> w;    // trapezoid weights in frequency
+};
+
+// Plain-old-data transition record as the kernels read it.
+struct DevTransition {
+    int kind, l, u, voigt;
+    int coll_kind, n_act, act_off, ray_off;  // ray_off: offset of this line's rays in a depth row
+    double nu0, A, Bul, Blu;                  // Einstein coefficients (per unit frequency)
+    double alpha0, coll_val, gamma, hnu4pi;   // hnu4pi = h nu0 / (4 pi)
+    double wsum;                              // sum of the trapezoid weights
+    double pad;
+};
+
+// A group: up to 64 rays of one direction sharing one set of transitions.
+struct DevGroup {
+    int s;            // 0 down (top to bottom), 1 up
+    int n_slots;      // transitions touched
+    int t[kMaxSlots]; // transition index of each slot
+    int n_pairs;      // ordered slot pairs (q, q') accumulated as cross terms
+    int pair[kMaxPairs];  // q * kMaxSlots + q'
+    int key_off;      // first key of this group
+    int n_keys;       // 2 n_slots + n_pairs
+    int pad[2];
+};
+
+// Per-lane ray constants (structure of arrays, index group * 64 + lane).
+struct DevLanes {
+    int *j;           // union wavelength index
+    int *m;           // angle index
+    double *nu;       // frequency
+    double *mu;       // cosine of the ray with the vertical
+    double *lamfac;   // lambda / kBgLambdaRef
+    double *hnu_k;    // h nu / k_B
+    double *two_hnu3c2;
+    // per slot q (index (group*64+lane)*kMaxSlots + q)
+    int *phi_idx;     // line: column in the per-depth profile row; continuum: -1
+    double *W;        // quadrature weight w_nu(t, j) * w_mu / 2 (0 on padding lanes)
+    double *kap;      // 4 pi W / (h nu_t)
+    double *alpha;    // continuum cross-section at nu_j
+};
+
+// Everything the kernels need about an atom and an angle quadrature.
+struct DevAtom {
+    int L, n_lines, n_cont, T, NL, n_mu;
+    int n_groups, n_keys;       // ray groups and rate keys per depth
+    int ray_cols;               // line rays per depth row: sum over lines of 2 n_act n_mu
+    int pad0;
+    double mass, abund, c_bg;
+    int bg_kind, pad1;
+    double *E, *g; int *stage;  // levels
+    DevTransition *tr;
+    double *lam, *nu;           // union grid
+    int *act_j; double *act_w;  // concatenated active lists and weights
+    double *mu, *wmu;           // Gauss-Legendre on (0,1)
+    int *jact_off, *jact_t;     // per wavelength: active transitions (CSR)
+    DevGroup *groups;
+    DevLanes lanes;
+    // rate keys per transition and per ordered transition pair (CSR)
+    int *p_off, *p_key;         // [T+1], keys of P_t
+    int *q_off, *q_key;         // [T+1], keys of Q'_t
+    int n_xpairs;
+    int *x_t, *x_t2, *x_off, *x_key;  // [n_xpairs], [n_xpairs+1]
+};
+
+struct HostGroupTables {
+    std::vector<DevGroup> groups;
+    std::vector<int> lane_j, lane_m, phi_idx;
+    std::vector<double> lane_nu, lane_mu, lane_lamfac, lane_hnu_k, lane_2hnu3c2, W, kap, alpha;
+    std::vector<int> p_off, p_key, q_off, q_key, x_t, x_t2, x_off, x_key;
+    int n_keys = 0, ray_cols = 0;
+    std::vector<double> mu, wmu;
+    int lanes_used = 0;
+    bool overflow = false;  // a wavelength had more than kMaxSlots active transitions
+};
+
+}  // namespace rh15d
+
+struct rh15d_atom {
+    double mass = 0, abund = 1, c_bg = 0;
+    int bg_kind = 0;
+    int L = 0, n_lines = 0, n_cont = 0;
+    std::vector<double> E, g;
+    std::vector<int> stage;
+    std::vector<rh15d::HostTransition> tr;  // lines, then continua
+    std::vector<double> lam, nu;            // union grid
+    std::vector<int> jact_off, jact_t;
+    // device copies per (device, n_mu), built on first use
+    std::mutex mu_;
+    std::map<std::pair<int, int>, rh15d::DevAtom> dev;
+    std::vector<void *> dev_allocs;
+};
+
+namespace rh15d {
+// host setup (atom_setup.cpp)
+int parse_atom_file(const char *path, rh15d_atom *a, std::string &err);
+void gauss_legendre_01(int n, std::vector<double> &x, std::vector<double> &w);
+void build_group_tables(const rh15d_atom &a, int n_mu, HostGroupTables &out);
+void set_error(const char *fmt, ...);
+const char *last_error();
+}  // namespace rh15d

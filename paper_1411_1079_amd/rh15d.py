@@ -1,0 +1,213 @@
+"""Python binding of librh15d (ctypes over the C ABI in include/rh15d.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the
+library is not built, importing this module raises; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librh15d.so")
+
+FP64, FP32 = 0, 1
+START_LTE, START_ZERO_RADIATION, START_PROVIDED = 0, 1, 2
+SCHED_CHUNKED, SCHED_SLOTS = 0, 1
+CONVERGED, MAX_ITER, NONFINITE, SINGULAR = 0, 1, 2, 3
+
+EXPORTS = (
+    "rh15d_load_atom", "rh15d_free_atom", "rh15d_atom_get_info", "rh15d_atom_lambda", "rh15d_default_options",
+    "rh15d_workspace_size", "rh15d_solve_columns", "rh15d_last_error",
+)
+
+
+class AtomInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int), ("n_lines", C.c_int), ("n_continua", C.c_int), ("n_transitions", C.c_int),
+                ("n_lambda", C.c_int)]
+
+
+class Columns(C.Structure):
+    _fields_ = [("n_columns", C.c_int64), ("depth_offset", C.POINTER(C.c_int64))] + \
+               [(n, C.c_void_p) for n in ("z", "T", "n_e", "n_H", "v_z", "v_turb", "init_pops")]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("ng_order", C.c_int), ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int),
+                ("coll_scale", C.c_double), ("scheduler", C.c_int), ("batch_columns", C.c_int)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star")]
+
+
+_lib = None
+
+
+def lib():
+    """Load librh15d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() or "
+                               "python paper_1411_1079_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        L.rh15d_load_atom.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        L.rh15d_free_atom.argtypes = [C.c_void_p]
+        L.rh15d_free_atom.restype = None
+        L.rh15d_atom_get_info.argtypes = [C.c_void_p, C.POINTER(AtomInfo)]
+        L.rh15d_atom_lambda.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.rh15d_default_options.argtypes = [C.POINTER(Options)]
+        L.rh15d_workspace_size.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(Options), C.POINTER(C.c_size_t)]
+        L.rh15d_solve_columns.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(Options), C.POINTER(Outputs),
+                                          C.c_void_p, C.c_size_t, C.c_void_p]
+        L.rh15d_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class RH15DError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librh15d error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise RH15DError(rc, lib().rh15d_last_error().decode())
+
+
+class Atom:
+    """A model atom loaded by the library (rh15d_load_atom)."""
+
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        _check(lib().rh15d_load_atom(path.encode(), C.byref(h)))
+        self._h = h
+        info = AtomInfo()
+        _check(lib().rh15d_atom_get_info(h, C.byref(info)))
+        self.n_levels, self.n_lines, self.n_continua = info.n_levels, info.n_lines, info.n_continua
+        self.n_transitions, self.n_lambda = info.n_transitions, info.n_lambda
+        self.lam = np.empty(self.n_lambda)
+        _check(lib().rh15d_atom_lambda(h, self.lam.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.rh15d_free_atom(self._h)
+            self._h = None
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _check(lib().rh15d_default_options(C.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class DeviceColumns:
+    """Columns resident on the device: CSR offsets on the host, per-depth
+    fields as float64 CUDA tensors."""
+    offset: np.ndarray
+    z: object
+    T: object
+    n_e: object
+    n_H: object
+    v_z: object
+    v_turb: object
+    init_pops: object = None
+
+    @property
+    def n_columns(self):
+        return len(self.offset) - 1
+
+    @property
+    def total_depth(self):
+        return int(self.offset[-1])
+
+    @staticmethod
+    def from_host(cols, device="cuda", init_pops=None):
+        import torch
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+        return DeviceColumns(offset=np.ascontiguousarray(cols.offset, dtype=np.int64), z=t(cols.z), T=t(cols.T),
+                             n_e=t(cols.n_e), n_H=t(cols.n_H), v_z=t(cols.v_z), v_turb=t(cols.v_turb),
+                             init_pops=None if init_pops is None else t(init_pops))
+
+
+def _cols_struct(dc: DeviceColumns) -> Columns:
+    off = dc.offset
+    s = Columns()
+    s.n_columns = dc.n_columns
+    s.depth_offset = off.ctypes.data_as(C.POINTER(C.c_int64))
+    for n in ("z", "T", "n_e", "n_H", "v_z", "v_turb"):
+        ten = getattr(dc, n)
+        assert ten.dtype.is_floating_point and ten.element_size() == 8 and ten.is_contiguous()
+        setattr(s, n, ten.data_ptr())
+    s.init_pops = dc.init_pops.data_ptr() if dc.init_pops is not None else None
+    return s
+
+
+def workspace_size(atom: Atom, dc: DeviceColumns, opts: Options) -> int:
+    n = C.c_size_t()
+    _check(lib().rh15d_workspace_size(atom._h, C.byref(_cols_struct(dc)), C.byref(opts), C.byref(n)))
+    return n.value
+
+
+class Solver:
+    """Reusable output and workspace buffers for repeated solves."""
+
+    def __init__(self, atom: Atom, dc: DeviceColumns, opts: Options, want_spectrum=True, want_psi=False,
+                 want_history=True):
+        import torch
+        self.atom, self.dc, self.opts = atom, dc, opts
+        dev = dc.z.device
+        L, n = atom.n_levels, dc.n_columns
+        self.pops = torch.empty((dc.total_depth, L), dtype=torch.float64, device=dev)
+        self.history = torch.empty((n, max(opts.max_iter, 1)), dtype=torch.float64, device=dev) if want_history else None
+        self.n_iter = torch.empty(n, dtype=torch.int32, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        self.spectrum = torch.empty((n, atom.n_lambda), dtype=torch.float64, device=dev) if want_spectrum else None
+        self.psi_star = (torch.empty((dc.total_depth, atom.n_transitions), dtype=torch.float64, device=dev)
+                         if want_psi else None)
+        self.ws_bytes = workspace_size(atom, dc, opts)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self._cols = _cols_struct(dc)
+        self._out = Outputs()
+        for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star"):
+            ten = getattr(self, name)
+            setattr(self._out, name, ten.data_ptr() if ten is not None else None)
+
+    def run(self, stream=None):
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.dc.z.device)
+        ws = self.workspace.data_ptr()
+        ws_al = (ws + 255) & ~255
+        _check(lib().rh15d_solve_columns(self.atom._h, C.byref(self._cols), C.byref(self.opts), C.byref(self._out),
+                                         C.c_void_p(ws_al), self.ws_bytes, C.c_void_p(st.cuda_stream)))
+        return self
+
+    def result(self) -> dict:
+        out = dict(pops=self.pops, n_iter=self.n_iter, status=self.status)
+        if self.history is not None:
+            out["history"] = self.history
+        if self.spectrum is not None:
+            out["spectrum"] = self.spectrum
+        if self.psi_star is not None:
+            out["psi_star"] = self.psi_star
+        return out
+
+
+def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, **opts) -> dict:
+    """Solve every column; returns CUDA tensors (pops, history, n_iter,
+    status, spectrum, psi_star)."""
+    o = default_options(**opts)
+    return Solver(atom, dc, o, want_spectrum=want_spectrum, want_psi=want_psi).run().result()

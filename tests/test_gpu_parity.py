@@ -1,0 +1,155 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64: lock-step (same start, same iteration count, same Ng decisions),
+element by element, within 1e-10 relative.  FP32 form: populations and
+emergent intensities within 1e-3 of the oracle converged to 1e-10, for
+a GPU run converged to 1e-4 maximum relative change."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1411_1079_amd import synth
+
+import conftest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rh():
+    from paper_1411_1079_amd import rh15d
+    return rh15d
+
+
+def gpu_solve(atom_path, cols, want_psi=False, init_pops=None, **opts):
+    rh = _rh()
+    print(f"[gpu] {atom_path.split('/')[-1]} columns={cols.n_columns} depth={int(cols.offset[-1])} opts={opts}",
+          flush=True)
+    atom = rh.Atom(atom_path)
+    dc = rh.DeviceColumns.from_host(cols, init_pops=init_pops)
+    out = rh.solve(atom, dc, want_psi=want_psi, **opts)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def oracle_solve(atom_path, cols, **kw):
+    a = O.Atom(atom_path)
+    return [O.solve_column(a, cols.column(c), **kw) for c in range(cols.n_columns)]
+
+
+def compare(g, orc, cols, rtol, psi=False, spectrum=True):
+    for c, r in enumerate(orc):
+        a, b = int(cols.offset[c]), int(cols.offset[c + 1])
+        assert g["status"][c] == r["status"], (c, g["status"][c], r["status"])
+        assert g["n_iter"][c] == r["n_iter"], (c, g["n_iter"][c], r["n_iter"])
+        np.testing.assert_allclose(g["pops"][a:b], r["pops"], rtol=rtol, atol=0, err_msg=f"pops column {c}")
+        n = r["n_iter"]
+        if n > 0:
+            # a relative change built from populations that agree to rtol
+            # agrees to about 2 rtol in absolute terms
+            np.testing.assert_allclose(g["history"][c, :n], r["history"][:n], rtol=1e-6, atol=4 * rtol,
+                                       err_msg=f"history column {c}")
+        if spectrum:
+            np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=rtol, atol=0, err_msg=f"spectrum {c}")
+        if psi:
+            ps = g["psi_star"][a:b].T
+            np.testing.assert_allclose(ps, r["psi_star"], rtol=rtol, atol=1e-300, err_msg=f"psi {c}")
+
+
+def test_two_level_lockstep(atom_dir):
+    cols = synth.cfg1_column()
+    for it in (1, 2, 9, 40):
+        kw = dict(n_mu=3, tol=0.0, max_iter=it, ng_order=2, ng_delay=5, ng_period=4)
+        g = gpu_solve(atom_dir["two_level"], cols, want_psi=True, **kw)
+        orc = oracle_solve(atom_dir["two_level"], cols, want_psi=True, **kw)
+        compare(g, orc, cols, 1e-10, psi=True)
+
+
+def test_h6_cfg2_lockstep(atom_dir):
+    cols = synth.cfg2_columns(seed=0, n_columns=6)
+    kw = dict(n_mu=5, tol=1e-4, max_iter=60)
+    g = gpu_solve(atom_dir["h6"], cols, **kw)
+    orc = oracle_solve(atom_dir["h6"], cols, **kw)
+    assert all(r["status"] == 0 for r in orc)
+    compare(g, orc, cols, 1e-10)
+
+
+def test_h6_cfg2_ng_and_weak_collisions(atom_dir):
+    """Weaker collisions: more iterations, so Ng extrapolation is active."""
+    cols = synth.cfg2_columns(seed=4, n_columns=3)
+    kw = dict(n_mu=5, tol=1e-6, max_iter=80, coll_scale=1e-2, ng_delay=3)
+    g = gpu_solve(atom_dir["h6"], cols, want_psi=True, **kw)
+    orc = oracle_solve(atom_dir["h6"], cols, want_psi=True, **kw)
+    assert all(r["n_iter"] > 10 for r in orc)
+    compare(g, orc, cols, 1e-10, psi=True)
+
+
+def test_tiny_overlaps_ragged(atom_dir):
+    """Blends, a line inside a continuum, overlapping continua, velocity
+    fields; ragged columns including the minimum of two depth points."""
+    parts = [conftest.tiny_column(8), conftest.tiny_column(12, vz=-5e3), conftest.tiny_column(2),
+             conftest.tiny_column(5, vz=1e4)]
+    cols = synth.Columns.from_list(parts)
+    for it in (1, 3, 40):
+        kw = dict(n_mu=3, tol=1e-9, max_iter=it, coll_scale=1e-5)
+        g = gpu_solve(atom_dir["tiny"], cols, want_psi=True, **kw)
+        orc = oracle_solve(atom_dir["tiny"], cols, want_psi=True, **kw)
+        compare(g, orc, cols, 1e-10, psi=True)
+
+
+def test_cube_columns_lockstep(atom_dir):
+    cube = synth.cube_columns(1, 16, 16)
+    nd = np.diff(cube.offset)
+    pick = [int(np.argmin(nd)), int(np.argmax(nd)), 3, 77, 130]
+    cols = cube.select(pick)
+    kw = dict(n_mu=5, tol=1e-4, max_iter=60)
+    g = gpu_solve(atom_dir["h6"], cols, **kw)
+    orc = oracle_solve(atom_dir["h6"], cols, **kw)
+    compare(g, orc, cols, 1e-10)
+
+
+def test_start_solutions(atom_dir):
+    cols = synth.cfg2_columns(seed=3, n_columns=3)
+    for start in (O.START_ZERO_RADIATION, O.START_LTE):
+        for it in (0, 1, 3):
+            kw = dict(n_mu=5, tol=0.0, max_iter=it, start=start)
+            g = gpu_solve(atom_dir["h6"], cols, **kw)
+            orc = oracle_solve(atom_dir["h6"], cols, **kw)
+            compare(g, orc, cols, 1e-10)
+    # provided start: the oracle's 2-iteration populations, then 2 more
+    orc2 = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=0.0, max_iter=2)
+    init = np.concatenate([r["pops"] for r in orc2])
+    kw = dict(n_mu=5, tol=0.0, max_iter=2, start=O.START_PROVIDED)
+    g = gpu_solve(atom_dir["h6"], cols, init_pops=init, **kw)
+    orc = [O.solve_column(O.Atom(atom_dir["h6"]), cols.column(c), init_pops=orc2[c]["pops"], **kw)
+           for c in range(cols.n_columns)]
+    compare(g, orc, cols, 1e-10)
+
+
+def test_chunking_and_determinism(atom_dir):
+    """Columns are independent: chunk size does not change any result
+    (bitwise), and repeated runs are bitwise identical."""
+    cols = synth.cfg2_columns(seed=9, n_columns=11)
+    kw = dict(n_mu=4, tol=1e-5, max_iter=60)
+    a = gpu_solve(atom_dir["h6"], cols, batch_columns=0, **kw)
+    b = gpu_solve(atom_dir["h6"], cols, batch_columns=4, **kw)
+    c = gpu_solve(atom_dir["h6"], cols, batch_columns=0, **kw)
+    for k in ("pops", "spectrum", "n_iter", "status"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k])
+
+
+def test_fp32_precision_form(atom_dir):
+    """Formal solution and rate accumulation in FP32: within 1e-3 of the
+    FP64 oracle converged to 1e-10 when converged to 1e-4."""
+    cube = synth.cube_columns(1, 16, 16)
+    cols = synth.Columns.from_list([synth.cfg2_columns(seed=0, n_columns=3).column(c) for c in range(3)] +
+                                   [cube.column(c) for c in (5, 90, 200)])
+    g = gpu_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-4, max_iter=100, precision=1)
+    orc = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-10, max_iter=200)
+    for c, r in enumerate(orc):
+        a, b = int(cols.offset[c]), int(cols.offset[c + 1])
+        assert g["status"][c] == 0
+        np.testing.assert_allclose(g["pops"][a:b], r["pops"], rtol=1e-3)
+        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-3)
