@@ -1,0 +1,244 @@
+#!/usr/bin/env python
+"""Benchmark: converged columns per second of per-column MALI on one MI355X.
+
+Workload: the synthetic 3D-MHD-like cube (256 x 256 = 65,536 columns, 200-400
+depth points each, seed 1), the six-level hydrogen-like atom (10 lines, 5
+continua, 510 wavelengths), 5 angles, converged to a maximum relative
+population change of 1e-4 from LTE.  A step solves one batch of columns
+(default 8192) to convergence; K steps cycle through the cube's batches.
+Inputs are resident in HBM before the timed region.
+
+Two forms run on the same batches: the plain FP64 path and the precision
+form (FP32 formal solution and rate accumulation, FP64 rate solve, Ng and
+convergence test).  `value` is the precision form's rate; the FP64 rate is
+reported beside it.  The roofline object describes the dominant kernel
+(the formal-solution sweep) from HIP-event timings taken inside the
+library on the launch stream over the timed region.  The CPU baseline is
+the FP64 oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged columns/s @1e-3 rel. accuracy: plain FP64 vs batched FP32+warm start"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_batches(rh, cols, dev_fields, batch):
+    """DeviceColumns views of consecutive column ranges of the resident cube."""
+    out = []
+    n = cols.n_columns
+    for c0 in range(0, n, batch):
+        c1 = min(n, c0 + batch)
+        g0, g1 = int(cols.offset[c0]), int(cols.offset[c1])
+        off = (cols.offset[c0:c1 + 1] - g0).astype(np.int64)
+        views = {k: v[g0:g1] for k, v in dev_fields.items()}
+        out.append((c0, c1, rh.DeviceColumns(offset=off, **views)))
+    return out
+
+
+def run_form(rh, torch, atom, batches, precision, steps, warmup, ws):
+    opts = rh.default_options(precision=precision, n_mu=5, tol=1e-4, max_iter=200, profile=1)
+    solvers = [rh.Solver(atom, dc, opts, want_spectrum=True, workspace=ws) for _, _, dc in batches]
+    nb = len(solvers)
+    for i in range(warmup):
+        solvers[i % nb].run()
+    torch.cuda.synchronize()
+    agg = dict(sweep_ms=0.0, se_ms=0.0, converge_ms=0.0, prep_ms=0.0, final_ms=0.0, sweep_flops=0.0,
+               sweep_bytes=0.0, sweep_launches=0, column_iterations=0, ray_steps=0)
+    columns = converged = 0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s = solvers[(warmup + i) % nb]
+        s.run()
+        st = rh.last_stats()
+        for k in agg:
+            agg[k] += st[k]
+        columns += s.dc.n_columns
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(steps):
+        s = solvers[(warmup + i) % nb]
+        converged += int((s.status == 0).sum().item())
+    return dict(seconds=t1 - t0, columns=columns, converged=converged, stats=agg, solvers=solvers,
+                first_batch=(warmup % nb))
+
+
+def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols):
+    """The FP64 oracle as it stands, one column per task on a thread pool of
+    the host cores, on the first columns of the first timed batch."""
+    import concurrent.futures
+
+    from oracle import oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    a = O.Atom(atom_path)
+    c0 = batches[gpu_first][0]
+    results = []
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        c = c0
+        while len(results) < max_cols:
+            chunk = list(range(c, c + threads))
+            futs = [ex.submit(O.solve_column, a, cols.column(i), n_mu=5, tol=1e-4, max_iter=200) for i in chunk]
+            results += [(i, f.result()) for i, f in zip(chunk, futs)]
+            c += threads
+            if time.perf_counter() - t0 > budget_s:
+                break
+    dt = time.perf_counter() - t0
+    conv = sum(1 for _, r in results if r["status"] == 0)
+    return dict(value=conv / dt, unit="columns/s", cores=threads, kind="oracle",
+                sample=f"{len(results)} columns of the cube (columns {c0}..{c0 + len(results) - 1}), "
+                       f"{dt:.1f} s wall on {threads} threads"), results
+
+
+def accuracy(results, form, batches, cols):
+    """Max relative difference of populations and emergent intensity between
+    a GPU form and the oracle on the CPU-baseline sample."""
+    s = form["solvers"][form["first_batch"]]
+    c0 = batches[form["first_batch"]][0]
+    pops = s.pops.cpu().numpy()
+    spec = s.spectrum.cpu().numpy()
+    off = s.dc.offset
+    ep = es = 0.0
+    for c, r in results:
+        i = c - c0
+        a, b = int(off[i]), int(off[i + 1])
+        ep = max(ep, float(np.max(np.abs(pops[a:b] / r["pops"] - 1.0))))
+        es = max(es, float(np.max(np.abs(spec[i] / r["spectrum"] - 1.0))))
+    return dict(pops=ep, spectrum=es, columns=len(results))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--forms", default="fp64,fp32")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-max-columns", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the columns are independent and this build runs on a single "
+              "MI355X; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1411_1079_amd import rh15d as rh
+    from paper_1411_1079_amd import synth
+
+    tmp = tempfile.mkdtemp()
+    atom_path = synth.write_atoms(tmp)["h6"]
+    t = time.perf_counter()
+    cols = synth.cube_columns(args.seed, args.nx, args.nx)
+    log(f"cube {args.nx}x{args.nx}: {cols.n_columns} columns, {int(cols.offset[-1])} points "
+        f"({time.perf_counter() - t:.1f} s)")
+    dev = torch.device("cuda:0")
+    fields = {k: torch.as_tensor(getattr(cols, k)).to(dev) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    batches = make_batches(rh, cols, fields, args.batch)
+    atom = rh.Atom(atom_path)
+    ws_bytes = 0
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    for f in forms:
+        o = rh.default_options(precision=1 if f == "fp32" else 0, n_mu=5, tol=1e-4, max_iter=200)
+        ws_bytes = max(ws_bytes, max(rh.workspace_size(atom, dc, o) for _, _, dc in batches))
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
+
+    res = {}
+    for f in forms:
+        log(f"form {f}: warmup {args.warmup}, steps {args.steps}")
+        r = run_form(rh, torch, atom, batches, 1 if f == "fp32" else 0, args.steps, args.warmup, ws)
+        st = r["stats"]
+        sweep_s = st["sweep_ms"] / 1e3
+        res[f] = r
+        log(f"form {f}: {r['converged']}/{r['columns']} converged in {r['seconds']:.3f} s "
+            f"-> {r['converged'] / r['seconds']:.1f} columns/s; sweep {st['sweep_ms']:.1f} ms over "
+            f"{st['sweep_launches']} launches, {st['sweep_flops'] / sweep_s / 1e12:.2f} TFLOP/s, "
+            f"mean iterations {st['column_iterations'] / r['columns']:.2f}")
+
+    headline = "fp32" if "fp32" in res else forms[0]
+    h = res[headline]
+    hst = h["stats"]
+    sweep_s = hst["sweep_ms"] / 1e3
+    achieved = hst["sweep_flops"] / sweep_s / 1e12 if sweep_s > 0 else 0.0
+    peak = PEAK_TFLOPS[headline]
+    out = {
+        "metric": METRIC,
+        "value": h["converged"] / h["seconds"],
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * h["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if headline == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"synthetic 3D cube {args.nx}x{args.nx} columns (seed {args.seed}), 200-400 depth "
+                         f"points, H-like 6-level atom (10 lines, 5 continua, 510 wavelengths), 5 angles, "
+                         f"tol 1e-4 from LTE, batches of {args.batch} columns"),
+            "form": "FP32 formal solution + FP64 rate solve (no warm start yet)" if headline == "fp32"
+            else "plain FP64",
+            "global_batch": args.batch,
+            "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"k_raysweep<{'float' if headline == 'fp32' else 'double'}>",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "launches": hst["sweep_launches"],
+            "avg_launch_ms": hst["sweep_ms"] / max(hst["sweep_launches"], 1),
+            "algorithmic_flops_per_launch": hst["sweep_flops"] / max(hst["sweep_launches"], 1),
+            "algorithmic_GBps": hst["sweep_bytes"] / sweep_s / 1e9 if sweep_s > 0 else 0.0,
+        },
+        "forms": {},
+    }
+    for f, r in res.items():
+        st = r["stats"]
+        out["forms"][f] = {
+            "columns_per_s": r["converged"] / r["seconds"],
+            "converged": r["converged"], "columns": r["columns"], "seconds": r["seconds"],
+            "mean_iterations": st["column_iterations"] / max(r["columns"], 1),
+            "kernel_ms": {k: st[k] for k in ("prep_ms", "sweep_ms", "se_ms", "converge_ms", "final_ms")},
+            "sweep_tflops": st["sweep_flops"] / (st["sweep_ms"] / 1e3) / 1e12 if st["sweep_ms"] > 0 else 0.0,
+        }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        base, results = cpu_baseline(atom_path, cols, batches, h["first_batch"], args.cpu_budget,
+                                     args.cpu_max_columns)
+        out["cpu_baseline"] = base
+        out["accuracy_vs_oracle"] = {f: accuracy(results, r, batches, cols) for f, r in res.items()}
+        log(f"cpu baseline {base['value']:.2f} columns/s on {base['cores']} threads; accuracy "
+            f"{out['accuracy_vs_oracle']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

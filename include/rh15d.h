@@ -114,7 +114,27 @@ typedef struct {
                            together; RH15D_SCHED_SLOTS: resident slots, converged
                            columns retired and refilled */
     int batch_columns;  /* columns resident at once; 0 = automatic */
+    int profile;        /* 1: time the kernels with HIP events and count the
+                           algorithmic work (see rh15d_last_stats) */
 } rh15d_options;
+
+/* Measurements of the calling thread's last rh15d_solve_columns made with
+ * options.profile = 1 (all zero otherwise).  Times come from HIP events
+ * recorded on the caller's stream around the library's own launches. */
+typedef struct {
+    int64_t sweep_launches;     /* formal-solution launches (rate mode) */
+    double sweep_ms;            /* their summed duration */
+    double se_ms, converge_ms;  /* rate-equation solves; convergence test + Ng */
+    double prep_ms;             /* column preparation (start populations included) */
+    double final_ms;            /* emergent spectrum and Psi* */
+    double total_ms;            /* first to last event of the call */
+    int64_t column_iterations;  /* sum over columns of the iterations performed */
+    int64_t ray_steps;          /* formal-solution ray-steps of the rate launches */
+    double sweep_flops;         /* algorithmic flops of the rate launches */
+    double sweep_bytes;         /* algorithmic HBM bytes of the rate launches */
+} rh15d_stats;
+
+int rh15d_last_stats(rh15d_stats *stats);
 
 typedef struct {
     double *pops;       /* DEVICE [total_depth][n_levels] final populations, m^-3 */
@@ -131,7 +151,8 @@ typedef struct {
 } rh15d_outputs;
 
 /* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, 200 iterations,
- * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, chunked. */
+ * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, chunked,
+ * no profiling. */
 int rh15d_default_options(rh15d_options *opt);
 
 /* Device workspace needed by rh15d_solve_columns for these columns and

@@ -247,6 +247,9 @@ void build_group_tables(const rh15d_atom &a, int n_mu, HostGroupTables &out) {
                     if (q != q2) G.pair[G.n_pairs++] = q * kMaxSlots + q2;
             G.key_off = key;
             G.n_keys = 2 * G.n_slots + G.n_pairs;
+            G.n_lanes = static_cast<int>(lanes.size());
+            G.n_line_slots = 0;
+            for (int q = 0; q < G.n_slots; q++) G.n_line_slots += a.tr[cur[q]].kind == 0;
             for (int q = 0; q < G.n_slots; q++) {
                 p_keys[cur[q]].push_back(key + q);
                 q_keys[cur[q]].push_back(key + G.n_slots + q);

@@ -822,6 +822,27 @@ __global__ void k_psi_gather(ChunkArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+thread_local rh15d_stats g_stats;
+
+// HIP events bracketing the library's launches on the caller's stream
+struct Timer {
+    bool on = false;
+    hipEvent_t ev[8] = {};
+    int init(bool enable) {
+        on = enable;
+        if (!on) return RH15D_OK;
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        return RH15D_OK;
+    }
+    void mark(int i, hipStream_t st) { if (on) (void)hipEventRecord(ev[i], st); }
+    double ms(int a, int b) {
+        float t = 0.f;
+        if (on) (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+    ~Timer() { if (on) for (auto &e : ev) (void)hipEventDestroy(e); }
+};
+
 template <typename T>
 int upload(rh15d_atom *atom, const std::vector<T> &v, T **out) {
     *out = nullptr;
@@ -892,6 +913,15 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
     D.n_xpairs = static_cast<int>(H.x_t.size());
     UP(H.x_t, &D.x_t); UP(H.x_t2, &D.x_t2); UP(H.x_off, &D.x_off); UP(H.x_key, &D.x_key);
 #undef UP
+    for (const auto &G : H.groups) {
+        // per ray-step: background and Planck 7, formal step 19, source 1;
+        // per transition 9 (opacity) + 8 (rates) + 2 (reductions);
+        // per cross pair 3 + 1
+        D.rays_per_depth += G.n_lanes;
+        D.flops_per_depth += (double)G.n_lanes * (27.0 + 19.0 * G.n_slots + 4.0 * G.n_pairs);
+        D.reads_per_depth += (double)G.n_lanes * G.n_line_slots;
+        D.keys_per_depth += G.n_keys;
+    }
     auto res = atom->dev.emplace(key, D);
     *out = &res.first->second;
     return RH15D_OK;
@@ -1036,6 +1066,12 @@ int rh15d_atom_lambda(const rh15d_atom *atom, double *lambda_host) {
     return RH15D_OK;
 }
 
+int rh15d_last_stats(rh15d_stats *stats) {
+    if (!stats) { set_error("null argument"); return RH15D_EINVAL; }
+    *stats = g_stats;
+    return RH15D_OK;
+}
+
 int rh15d_default_options(rh15d_options *o) {
     if (!o) { set_error("null argument"); return RH15D_EINVAL; }
     o->precision = RH15D_FP64;
@@ -1049,6 +1085,7 @@ int rh15d_default_options(rh15d_options *o) {
     o->coll_scale = 1.0;
     o->scheduler = RH15D_SCHED_CHUNKED;
     o->batch_columns = 0;
+    o->profile = 0;
     return RH15D_OK;
 }
 
@@ -1120,6 +1157,10 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.max_iter = o->max_iter; a.ng_order = o->ng_order; a.ng_delay = o->ng_delay; a.ng_period = o->ng_period;
     a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale;
 
+    g_stats = rh15d_stats{};
+    Timer tm;
+    if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_counter); if (own) (void)hipFree(own); return rc; }
+    tm.mark(0, st);
     e = hipMemcpyAsync(const_cast<int64_t *>(a.doff), cols->depth_offset, (cols->n_columns + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) fail(e, "copy depth offsets");
@@ -1131,6 +1172,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
         a.G0 = cols->depth_offset[c0];
         a.TD = cols->depth_offset[c1] - a.G0;
         const int tdb = (int)((a.TD + 255) / 256);
+        tm.mark(2, st);
         hipLaunchKernelGGL(k_prep_depth, dim3(tdb), dim3(256), 0, st, a);
         const int64_t pairs = a.TD * D->n_lines;
         if (pairs > 0) {
@@ -1142,18 +1184,31 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
         hipLaunchKernelGGL(k_init_columns, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
         e = hipMemsetAsync(a.done_counter, 0, sizeof(int), st);
         if (e != hipSuccess) { fail(e, "memset"); break; }
+        tm.mark(3, st);
         const dim3 sweep_grid((D->n_groups + 3) / 4, a.S);
         for (int it = 1; it <= o->max_iter; it++) {
+            tm.mark(4, st);
             if (fp32) hipLaunchKernelGGL((k_raysweep<float, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
             else hipLaunchKernelGGL((k_raysweep<double, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+            tm.mark(5, st);
             se_dispatch(a, fp32, false, st);
+            tm.mark(6, st);
             hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
+            tm.mark(7, st);
             e = hipMemcpyAsync(h_counter, a.done_counter, sizeof(int), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) { fail(e, "iteration"); break; }
+            if (tm.on) {
+                if (it == 1) g_stats.prep_ms += tm.ms(2, 3);
+                g_stats.sweep_ms += tm.ms(4, 5);
+                g_stats.se_ms += tm.ms(5, 6);
+                g_stats.converge_ms += tm.ms(6, 7);
+                g_stats.sweep_launches++;
+            }
             if (*h_counter >= a.S) break;
         }
         if (result != RH15D_OK) break;
+        tm.mark(2, st);
         if (out->spectrum) {
             const int64_t n = (int64_t)a.S * D->NL;
             hipLaunchKernelGGL(k_emergent, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, a);
@@ -1167,12 +1222,36 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
             if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
             else hipLaunchKernelGGL(k_psi_gather<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
         }
+        tm.mark(3, st);
         e = hipGetLastError();
         if (e != hipSuccess) { fail(e, "kernel launch"); break; }
+        if (tm.on) {
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) { fail(e, "synchronize"); break; }
+            g_stats.final_ms += tm.ms(2, 3);
+        }
     }
+    tm.mark(1, st);
     if (result == RH15D_OK) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) fail(e, "synchronize");
+    }
+    if (result == RH15D_OK && tm.on) {
+        g_stats.total_ms = tm.ms(0, 1);
+        std::vector<int32_t> nit(cols->n_columns);
+        e = hipMemcpy(nit.data(), out->n_iter, nit.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            fail(e, "read n_iter");
+        } else {
+            const double rsize = fp32 ? 4.0 : 8.0;
+            for (int64_t c = 0; c < cols->n_columns; c++) {
+                const double pts = (double)nit[c] * (double)(cols->depth_offset[c + 1] - cols->depth_offset[c]);
+                g_stats.column_iterations += nit[c];
+                g_stats.ray_steps += (int64_t)(pts * D->rays_per_depth);
+                g_stats.sweep_flops += pts * D->flops_per_depth;
+                g_stats.sweep_bytes += pts * (D->reads_per_depth + D->keys_per_depth) * rsize;
+            }
+        }
     }
     (void)hipHostFree(h_counter);
     if (own) (void)hipFree(own);

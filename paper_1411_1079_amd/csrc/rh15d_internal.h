@@ -64,7 +64,8 @@ struct DevGroup {
     int pair[kMaxPairs];  // q * kMaxSlots + q'
     int key_off;      // first key of this group
     int n_keys;       // 2 n_slots + n_pairs
-    int pad[2];
+    int n_lanes;      // rays carried (the rest of the 64 lanes are padding)
+    int n_line_slots; // slots that are lines (read a profile row per ray-step)
 };
 
 // Per-lane ray constants (structure of arrays, index group * 64 + lane).
@@ -104,6 +105,11 @@ struct DevAtom {
     int *q_off, *q_key;         // [T+1], keys of Q'_t
     int n_xpairs;
     int *x_t, *x_t2, *x_off, *x_key;  // [n_xpairs], [n_xpairs+1]
+    // algorithmic work of one rate-mode sweep per depth point of a column
+    double rays_per_depth;        // rays (wavelength x angle x direction)
+    double flops_per_depth;       // see k_raysweep: 27 + 19 n_slots + 4 n_pairs per ray-step
+    double reads_per_depth;       // profile values read
+    double keys_per_depth;        // reduced rate values written
 };
 
 struct HostGroupTables {

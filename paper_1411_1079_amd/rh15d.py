@@ -23,7 +23,7 @@ CONVERGED, MAX_ITER, NONFINITE, SINGULAR = 0, 1, 2, 3
 
 EXPORTS = (
     "rh15d_load_atom", "rh15d_free_atom", "rh15d_atom_get_info", "rh15d_atom_lambda", "rh15d_default_options",
-    "rh15d_workspace_size", "rh15d_solve_columns", "rh15d_last_error",
+    "rh15d_workspace_size", "rh15d_solve_columns", "rh15d_last_error", "rh15d_last_stats",
 )
 
 
@@ -40,7 +40,15 @@ class Columns(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("ng_order", C.c_int), ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int),
-                ("coll_scale", C.c_double), ("scheduler", C.c_int), ("batch_columns", C.c_int)]
+                ("coll_scale", C.c_double), ("scheduler", C.c_int), ("batch_columns", C.c_int),
+                ("profile", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("se_ms", C.c_double),
+                ("converge_ms", C.c_double), ("prep_ms", C.c_double), ("final_ms", C.c_double),
+                ("total_ms", C.c_double), ("column_iterations", C.c_int64), ("ray_steps", C.c_int64),
+                ("sweep_flops", C.c_double), ("sweep_bytes", C.c_double)]
 
 
 class Outputs(C.Structure):
@@ -68,6 +76,7 @@ def lib():
         L.rh15d_solve_columns.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(Options), C.POINTER(Outputs),
                                           C.c_void_p, C.c_size_t, C.c_void_p]
         L.rh15d_last_error.restype = C.c_char_p
+        L.rh15d_last_stats.argtypes = [C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -101,6 +110,13 @@ class Atom:
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.rh15d_free_atom(self._h)
             self._h = None
+
+
+def last_stats() -> dict:
+    """Measurements of this thread's last solve made with profile=1."""
+    st = Stats()
+    _check(lib().rh15d_last_stats(C.byref(st)))
+    return {name: getattr(st, name) for name, _ in Stats._fields_}
 
 
 def default_options(**kw) -> Options:
@@ -166,7 +182,7 @@ class Solver:
     """Reusable output and workspace buffers for repeated solves."""
 
     def __init__(self, atom: Atom, dc: DeviceColumns, opts: Options, want_spectrum=True, want_psi=False,
-                 want_history=True):
+                 want_history=True, workspace=None):
         import torch
         self.atom, self.dc, self.opts = atom, dc, opts
         dev = dc.z.device
@@ -179,7 +195,11 @@ class Solver:
         self.psi_star = (torch.empty((dc.total_depth, atom.n_transitions), dtype=torch.float64, device=dev)
                          if want_psi else None)
         self.ws_bytes = workspace_size(atom, dc, opts)
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        if workspace is None:
+            workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        elif workspace.numel() < self.ws_bytes + 256:
+            raise ValueError(f"workspace of {workspace.numel()} bytes < {self.ws_bytes + 256}")
+        self.workspace = workspace
         self._cols = _cols_struct(dc)
         self._out = Outputs()
         for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star"):
