@@ -72,11 +72,15 @@ def run_form(rh, torch, atom, batches, precision, steps, warmup, ws):
         columns += s.dc.n_columns
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    iters = []
     for i in range(steps):
         s = solvers[(warmup + i) % nb]
         converged += int((s.status == 0).sum().item())
+        iters.append(s.n_iter.cpu().numpy())
+    iters = np.concatenate(iters)
+    hist = {f"p{q}": float(np.percentile(iters, q)) for q in (50, 90, 99, 100)}
     return dict(seconds=t1 - t0, columns=columns, converged=converged, stats=agg, solvers=solvers,
-                first_batch=(warmup % nb))
+                first_batch=(warmup % nb), iter_percentiles=hist)
 
 
 def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols):
@@ -175,7 +179,7 @@ def main():
         log(f"form {f}: {r['converged']}/{r['columns']} converged in {r['seconds']:.3f} s "
             f"-> {r['converged'] / r['seconds']:.1f} columns/s; sweep {st['sweep_ms']:.1f} ms over "
             f"{st['sweep_launches']} launches, {st['sweep_flops'] / sweep_s / 1e12:.2f} TFLOP/s, "
-            f"mean iterations {st['column_iterations'] / r['columns']:.2f}")
+            f"mean iterations {st['column_iterations'] / r['columns']:.2f} {r['iter_percentiles']}")
 
     headline = "fp32" if "fp32" in res else forms[0]
     h = res[headline]
@@ -226,6 +230,7 @@ def main():
             "columns_per_s": r["converged"] / r["seconds"],
             "converged": r["converged"], "columns": r["columns"], "seconds": r["seconds"],
             "mean_iterations": st["column_iterations"] / max(r["columns"], 1),
+            "iteration_percentiles": r["iter_percentiles"],
             "kernel_ms": {k: st[k] for k in ("prep_ms", "sweep_ms", "se_ms", "converge_ms", "final_ms")},
             "sweep_tflops": st["sweep_flops"] / (st["sweep_ms"] / 1e3) / 1e12 if st["sweep_ms"] > 0 else 0.0,
         }

@@ -51,6 +51,16 @@ __device__ __forceinline__ float d_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
 
+// Reciprocals: hardware estimate, refined by Newton steps in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Linear short-characteristic weights (Olson & Kunasz 1987) of an optical
 // step x: I_b = I_a e + wa S_a + wb S_b.  Below the threshold the weights
 // come from their Taylor series (through x^6), which avoids the
@@ -64,10 +74,16 @@ __device__ __forceinline__ void sc_weights(R x, R &e, R &wa, R &wb) {
         wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
              x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
         e = d_exp(-x);
-    } else {
+    } else if constexpr (sizeof(R) == 8) {
         const R one_m_e = -d_expm1(-x);
-        const R q = one_m_e / x;
+        const R q = one_m_e * rcp(x);
         e = R(1) - one_m_e;
+        wb = R(1) - q;
+        wa = q - e;
+    } else {
+        // x >= 0.1: 1 - e^-x carries at most a few ulp of relative error
+        e = d_exp(-x);
+        const R q = (R(1) - e) * __builtin_amdgcn_rcpf(x);
         wb = R(1) - q;
         wa = q - e;
     }
@@ -166,6 +182,9 @@ struct ChunkArgs {
     double *norm;             // [TD][n_lines] profile normalisation sums
     void *phi;                // [TD][ray_cols] normalised profiles (double or float)
     void *part;               // rate keys: column block at gc0*n_keys, [key][N]
+    void *rec;                // [TD][rec_w] per-depth data of the sweep (sweep precision)
+    float *popsf;             // [TD][L] FP32 copy of the populations (FP32 form)
+    int rec_w, pad_rw;
     double *nse;              // [TD][L] rate-equation solution
     double *dk;               // [TD] max relative change per depth point
     int *flag;                // [TD] 0 ok, 1 non-finite/non-positive, 2 singular
@@ -175,6 +194,12 @@ struct ChunkArgs {
     int max_iter, ng_order, ng_delay, ng_period, start;
     double tol, coll_scale;
 };
+
+// Per-depth data of the sweep (chunk-local depth gc), in the sweep's precision:
+// [0] z(k-1) - z(k) (0 at the top point), [1] 1/T, [2] background opacity at
+// the reference wavelength, [3] unused, [4 + c] n*_l / n*_u of continuum c.
+constexpr int kRecHead = 4;
+__host__ __device__ __forceinline__ int rec_width(int n_cont) { return (kRecHead + n_cont + 1) & ~1; }
 
 __device__ __forceinline__ int find_column(const ChunkArgs &a, int64_t gc) {
     // last column of the chunk whose first point is <= gc
@@ -190,6 +215,7 @@ __device__ __forceinline__ int find_column(const ChunkArgs &a, int64_t gc) {
 // ---------------------------------------------------------------------------
 // column preparation
 // ---------------------------------------------------------------------------
+template <typename R>
 __global__ void k_prep_depth(ChunkArgs a) {
     const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gc >= a.TD) return;
@@ -214,11 +240,22 @@ __global__ void k_prep_depth(ChunkArgs a) {
         if (a.start == RH15D_START_PROVIDED) v = a.init[g * L + i];
         else v = ntot * exp(lr[i] - mx) / sum;
         a.pops[g * L + i] = v;
+        if (a.popsf) a.popsf[gc * L + i] = static_cast<float>(v);
     }
-    a.kbg[gc] = A.bg_kind == 1 ? A.c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T) : 0.0;
+    const double kbg = A.bg_kind == 1 ? A.c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T) : 0.0;
+    a.kbg[gc] = kbg;
+    const int colc = find_column(a, gc);
+    const bool top = (g == a.doff[a.c_first + colc]);
+    R *rec = reinterpret_cast<R *>(a.rec) + gc * a.rec_w;
+    rec[0] = static_cast<R>(top ? 0.0 : a.z[g - 1] - a.z[g]);
+    rec[1] = static_cast<R>(1.0 / T);
+    rec[2] = static_cast<R>(kbg);
+    rec[3] = R(0);
     for (int c = 0; c < A.n_cont; c++) {
         const DevTransition &tr = A.tr[A.n_lines + c];
-        a.gr[gc * A.n_cont + c] = exp(lr[tr.l] - lr[tr.u]);
+        const double gr = exp(lr[tr.l] - lr[tr.u]);
+        a.gr[gc * A.n_cont + c] = gr;
+        rec[kRecHead + c] = static_cast<R>(gr);
     }
 }
 
@@ -271,201 +308,217 @@ __global__ __launch_bounds__(256) void k_prep_profile(ChunkArgs a) {
 // ---------------------------------------------------------------------------
 enum { MODE_RATES = 0, MODE_PSI = 1 };
 
+__device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// One DPP stage: the value of another lane of the row (or the broadcast
+// lane), 0 where the pattern has no source or the row is masked off.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_src(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_src(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes: an inclusive scan with row shifts 1, 2, 4, 8 and
+// the row broadcasts of lanes 15 and 31; lane 63 ends with the total.  The
+// order of the additions is fixed, so results are reproducible.
 template <typename R>
-struct PointTerms {
-    R chi, eta, etabg, S, B;
-    R vlu[kMaxSlots], vul[kMaxSlots], U[kMaxSlots], chit[kMaxSlots];
+__device__ __forceinline__ R wave_total(R v) {
+    v += dpp_src<0x111, 0xf>(v);
+    v += dpp_src<0x112, 0xf>(v);
+    v += dpp_src<0x114, 0xf>(v);
+    v += dpp_src<0x118, 0xf>(v);
+    v += dpp_src<0x142, 0xa>(v);
+    v += dpp_src<0x143, 0xc>(v);
+    return v;
+}
+
+
+template <typename R>
+__device__ __forceinline__ const R *pops_row(const ChunkArgs &a, int64_t g, int64_t gc) {
+    if constexpr (sizeof(R) == 8) return a.pops + g * a.A.L;
+    else return a.popsf + gc * a.A.L;
+}
+
+template <typename R, int NS>
+struct Point {
+    R chi, rchi, S, etabg, B;
+    R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
 };
 
-// Opacity and emissivity of a lane's ray at chunk-local depth gc.
-template <typename R>
-__device__ __forceinline__ void point_terms(const ChunkArgs &a, const DevGroup &G, int64_t gc, int64_t g,
-                                            const R *phirow, const int *pidx, const R *alpha, R hnu_k,
-                                            R two_hnu3, R lamfac, PointTerms<R> &p) {
+// Uniform (per wavefront) description of the transitions a group touches.
+template <typename R, int NS>
+struct Slots {
+    int kind[NS], l[NS], u[NS], c[NS];
+    R cblu[NS], cbul[NS], ca[NS];
+};
+
+// Opacity, emissivity and source function of a lane's ray at depth point k.
+template <typename R, int NS>
+__device__ __forceinline__ void eval_point(const ChunkArgs &a, const Slots<R, NS> &sl, int64_t g, int64_t gc,
+                                           const int *pidx, const R *alpha, R hnu_k, R two_hnu3, R lamfac,
+                                           Point<R, NS> &p) {
     const DevAtom &A = a.A;
-    const int L = A.L;
-    const R T = static_cast<R>(a.T[g]);
-    const R x = hnu_k / T;
-    const R ex = d_exp(-x);          // exp(-h nu / k T), kept to full relative precision
+    const R *rec = reinterpret_cast<const R *>(a.rec) + gc * a.rec_w;
+    const R *n = pops_row<R>(a, g, gc);
+    const R x = hnu_k * rec[1];
+    const R ex = d_exp(-x);  // exp(-h nu / k T)
     const R omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
-    p.B = two_hnu3 * ex / omx;
-    const R chibg = static_cast<R>(a.kbg[gc]) * lamfac;
+    p.B = two_hnu3 * ex * rcp(omx);
+    const R chibg = rec[2] * lamfac;
     p.etabg = chibg * p.B;
     R chi = chibg, eta = p.etabg;
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; q++) {
-        if (q < G.n_slots) {
-            const DevTransition &tr = A.tr[G.t[q]];
-            const R nl = static_cast<R>(a.pops[g * L + tr.l]);
-            const R nu = static_cast<R>(a.pops[g * L + tr.u]);
-            R vlu, vul, U;
-            if (tr.kind == 0) {
-                const R ph = phirow[pidx[q]];
-                const R c = static_cast<R>(tr.hnu4pi);
-                vlu = c * static_cast<R>(tr.Blu) * ph;
-                vul = c * static_cast<R>(tr.Bul) * ph;
-                U = c * static_cast<R>(tr.A) * ph;
-            } else {
-                const R gf = static_cast<R>(a.gr[gc * A.n_cont + (G.t[q] - A.n_lines)]) * ex;
-                vlu = alpha[q];
-                vul = gf * alpha[q];
-                U = two_hnu3 * gf * alpha[q];
-            }
-            p.vlu[q] = vlu; p.vul[q] = vul; p.U[q] = U;
-            p.chit[q] = nl * vlu - nu * vul;
-            chi += p.chit[q];
-            eta += nu * U;
+    for (int q = 0; q < NS; q++) {
+        const R nl = n[sl.l[q]], nu = n[sl.u[q]];
+        if (sl.kind[q] == 0) {
+            const R ph = reinterpret_cast<const R *>(a.phi)[gc * A.ray_cols + pidx[q]];
+            p.ph[q] = ph;
+            p.vlu[q] = sl.cblu[q] * ph;
+            p.vul[q] = sl.cbul[q] * ph;
+            p.U[q] = sl.ca[q] * ph;
+        } else {
+            const R gf = rec[kRecHead + sl.c[q]] * ex;
+            p.ph[q] = R(1);
+            p.vlu[q] = alpha[q];
+            p.vul[q] = gf * alpha[q];
+            p.U[q] = two_hnu3 * p.vul[q];
         }
+        p.cht[q] = nl * p.vlu[q] - nu * p.vul[q];
+        chi += p.cht[q];
+        eta += nu * p.U[q];
     }
     p.chi = chi;
-    p.eta = eta;
-    p.S = eta / chi;
+    p.rchi = rcp(chi);
+    p.S = eta * p.rchi;
 }
 
-template <typename R, int MODE>
-__device__ __forceinline__ void accumulate(const ChunkArgs &a, const DevGroup &G, const PointTerms<R> &p,
-                                           const R *kap, const R *om, R Ieff, R psi, R *out, int N, int k,
-                                           int lane) {
-    if (MODE == MODE_PSI) {
+// Rate contributions of one depth point, summed over the wavefront's rays.
+template <typename R, int NS, int MODE>
+__device__ __forceinline__ void accumulate(const Point<R, NS> &p, const R *kap, const R *om, R Ieff, R psi,
+                                           R *out, int N, int k, int lane) {
+    if constexpr (MODE == MODE_PSI) {
 #pragma unroll
-        for (int q = 0; q < kMaxSlots; q++) {
-            if (q < G.n_slots) {
-                const R v = wave_sum(om[q] * psi);
-                if (lane == 0) out[(size_t)q * N + k] = v;
-            }
+        for (int q = 0; q < NS; q++) {
+            const R v = wave_total(om[q] * p.ph[q] * psi);
+            if (lane == kWave - 1) out[(size_t)q * N + k] = v;
         }
-        return;
-    }
+    } else {
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; q++) {
-        if (q < G.n_slots) {
-            const R cp = wave_sum(kap[q] * p.vlu[q] * Ieff);
-            const R cq = wave_sum(kap[q] * (p.U[q] * (R(1) - p.chit[q] * psi) + p.vul[q] * Ieff));
-            if (lane == 0) {
+        for (int q = 0; q < NS; q++) {
+            const R cp = wave_total(kap[q] * p.vlu[q] * Ieff);
+            const R cq = wave_total(kap[q] * (p.U[q] * (R(1) - p.cht[q] * psi) + p.vul[q] * Ieff));
+            if (lane == kWave - 1) {
                 out[(size_t)q * N + k] = cp;
-                out[(size_t)(G.n_slots + q) * N + k] = cq;
+                out[(size_t)(NS + q) * N + k] = cq;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NS; q++) {
+#pragma unroll
+            for (int q2 = 0; q2 < NS; q2++) {
+                if (q2 == q) continue;
+                const int rank = q * (NS - 1) + (q2 < q ? q2 : q2 - 1);
+                const R cx = wave_total(kap[q] * p.cht[q] * psi * p.U[q2]);
+                if (lane == kWave - 1) out[(size_t)(2 * NS + rank) * N + k] = cx;
             }
         }
     }
-    for (int pp = 0; pp < G.n_pairs; pp++) {
-        const int q = G.pair[pp] / kMaxSlots, q2 = G.pair[pp] % kMaxSlots;
-        R chq = 0, kq = 0, u2 = 0;
+}
+
+// One wavefront: 64 rays of one direction through one column.  Down rays
+// start at the top with no incoming radiation; up rays start at the bottom
+// with the diffusion approximation I = B + mu dB/dtau.
+template <typename R, int MODE, int NS>
+__device__ __forceinline__ void sweep_group(const ChunkArgs &a, int grp, int colc, int lane) {
+    const DevAtom &A = a.A;
+    const int c = a.c_first + colc;
+    const int64_t g0 = a.doff[c];
+    const int N = rfl((int)(a.doff[c + 1] - g0));
+    const int64_t gc0 = g0 - a.G0;
+    const DevGroup &G = A.groups[grp];
+    const int s_dir = rfl(G.s);
+    const int key_off = rfl(G.key_off);
+    Slots<R, NS> sl;
 #pragma unroll
-        for (int i = 0; i < kMaxSlots; i++) {
-            if (i == q) { chq = p.chit[i]; kq = kap[i]; }
-            if (i == q2) u2 = p.U[i];
-        }
-        const R cx = wave_sum(kq * chq * psi * u2);
-        if (lane == 0) out[(size_t)(2 * G.n_slots + pp) * N + k] = cx;
+    for (int q = 0; q < NS; q++) {
+        const DevTransition &tr = A.tr[rfl(G.t[q])];
+        sl.kind[q] = rfl(tr.kind);
+        sl.l[q] = rfl(tr.l);
+        sl.u[q] = rfl(tr.u);
+        sl.c[q] = rfl(tr.kind == 1 ? G.t[q] - A.n_lines : 0);
+        sl.cblu[q] = static_cast<R>(tr.hnu4pi * tr.Blu);
+        sl.cbul[q] = static_cast<R>(tr.hnu4pi * tr.Bul);
+        sl.ca[q] = static_cast<R>(tr.hnu4pi * tr.A);
+    }
+    const int li = grp * kWave + lane;
+    const R mu = static_cast<R>(A.lanes.mu[li]);
+    const R invmu = R(1) / mu;
+    const R lamfac = static_cast<R>(A.lanes.lamfac[li]);
+    const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
+    const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
+    int pidx[NS];
+    R kap[NS], alpha[NS], om[NS];
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+        pidx[q] = A.lanes.phi_idx[li * kMaxSlots + q];
+        kap[q] = static_cast<R>(A.lanes.kap[li * kMaxSlots + q]);
+        alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
+        const double W = A.lanes.W[li * kMaxSlots + q];
+        om[q] = static_cast<R>(sl.kind[q] == 1 ? W / A.tr[G.t[q]].wsum : W);
+    }
+    R *out = reinterpret_cast<R *>(a.part) + gc0 * A.n_keys + (size_t)key_off * N;
+    const R *rec = reinterpret_cast<const R *>(a.rec);
+    const int step = s_dir == 0 ? 1 : -1;
+    int k = s_dir == 0 ? 0 : N - 1;
+    Point<R, NS> p;
+    eval_point<R, NS>(a, sl, g0 + k, gc0 + k, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+    R I;
+    if (s_dir == 0) {
+        I = R(0);
+    } else {
+        Point<R, NS> p2;
+        eval_point<R, NS>(a, sl, g0 + N - 2, gc0 + N - 2, pidx, alpha, hnu_k, two_hnu3, lamfac, p2);
+        const R dtv = R(0.5) * (p.chi + p2.chi) * rec[(gc0 + N - 1) * a.rec_w];
+        I = dtv > R(0) ? p.B + mu * (p.B - p2.B) * rcp(dtv) : p.B;
+    }
+    accumulate<R, NS, MODE>(p, kap, om, I, R(0), out, N, k, lane);
+    R chi_p = p.chi, S_p = p.S;
+    for (int i = 1; i < N; i++) {
+        const int kp = k;
+        k += step;
+        eval_point<R, NS>(a, sl, g0 + k, gc0 + k, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+        const R dz = rec[(gc0 + (step > 0 ? k : kp)) * a.rec_w];
+        const R x = R(0.5) * (chi_p + p.chi) * dz * invmu;
+        R e, wa, wb;
+        sc_weights<R>(x, e, wa, wb);
+        const R up = I * e + wa * S_p;
+        const R Ieff = up + wb * p.etabg * p.rchi;
+        const R psi = wb * p.rchi;
+        I = up + wb * p.S;
+        accumulate<R, NS, MODE>(p, kap, om, Ieff, psi, out, N, k, lane);
+        chi_p = p.chi;
+        S_p = p.S;
     }
 }
 
 template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_raysweep(ChunkArgs a) {
-    const DevAtom &A = a.A;
-    const int grp = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const int grp = rfl(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int colc = blockIdx.y;
-    if (grp >= A.n_groups) return;
+    if (grp >= a.A.n_groups) return;
     if (MODE == MODE_RATES && a.col_done[colc]) return;
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = (int)(a.doff[c + 1] - g0);
-    const int64_t gc0 = g0 - a.G0;
-    const DevGroup G = A.groups[grp];
-    const int li = grp * kWave + lane;
-    const R mu = static_cast<R>(A.lanes.mu[li]);
-    const R lamfac = static_cast<R>(A.lanes.lamfac[li]);
-    const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
-    const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
-    int pidx[kMaxSlots];
-    R kap[kMaxSlots], alpha[kMaxSlots], om[kMaxSlots];
-#pragma unroll
-    for (int q = 0; q < kMaxSlots; q++) {
-        pidx[q] = A.lanes.phi_idx[li * kMaxSlots + q];
-        kap[q] = static_cast<R>(A.lanes.kap[li * kMaxSlots + q]);
-        alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
-        const double W = A.lanes.W[li * kMaxSlots + q];
-        om[q] = static_cast<R>(q < G.n_slots && A.tr[G.t[q]].kind == 1 ? W / A.tr[G.t[q]].wsum : W);
-    }
-    R *out = reinterpret_cast<R *>(a.part) + gc0 * A.n_keys + (size_t)G.key_off * N;
-    const R *phi = reinterpret_cast<const R *>(a.phi);
-    PointTerms<R> p;
-
-
-    if (G.s == 0) {
-        // downward rays: from the top (k = 0, no incoming radiation) to the bottom
-        int64_t gc = gc0, g = g0;
-        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-        R omk[kMaxSlots];
-#pragma unroll
-        for (int q = 0; q < kMaxSlots; q++) omk[q] = om[q];
-        if constexpr (MODE == MODE_PSI) {
-#pragma unroll
-            for (int q = 0; q < kMaxSlots; q++)
-                if (q < G.n_slots && A.tr[G.t[q]].kind == 0) omk[q] = om[q] * phi[gc * A.ray_cols + pidx[q]];
-        }
-        accumulate<R, MODE>(a, G, p, kap, omk, R(0), R(0), out, N, 0, lane);
-        R I = 0, chi_prev = p.chi, S_prev = p.S;
-        R z_prev = static_cast<R>(a.z[g]);
-        for (int k = 1; k < N; k++) {
-            gc = gc0 + k; g = g0 + k;
-            point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-            const R zk = static_cast<R>(a.z[g]);
-            const R x = R(0.5) * (chi_prev + p.chi) * (z_prev - zk) / mu;
-            R e, wa, wb;
-            sc_weights<R>(x, e, wa, wb);
-            const R up = I * e + wa * S_prev;
-            const R Ieff = up + wb * p.etabg / p.chi;
-            const R psi = wb / p.chi;
-            I = up + wb * p.S;
-            if constexpr (MODE == MODE_PSI) {
-#pragma unroll
-                for (int q = 0; q < kMaxSlots; q++)
-                    omk[q] = (q < G.n_slots && A.tr[G.t[q]].kind == 0) ? om[q] * phi[gc * A.ray_cols + pidx[q]] : om[q];
-            }
-            accumulate<R, MODE>(a, G, p, kap, omk, Ieff, psi, out, N, k, lane);
-            chi_prev = p.chi; S_prev = p.S; z_prev = zk;
-        }
-    } else {
-        // upward rays: diffusion approximation at the bottom, then to the top
-        int64_t gc = gc0 + N - 2, g = g0 + N - 2;
-        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-        const R chi2 = p.chi, B2 = p.B;
-        gc = gc0 + N - 1; g = g0 + N - 1;
-        point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-        const R dtv = R(0.5) * (p.chi + chi2) * static_cast<R>(a.z[g - 1] - a.z[g]);
-        R I = dtv > R(0) ? p.B + mu * (p.B - B2) / dtv : p.B;
-        R omk[kMaxSlots];
-#pragma unroll
-        for (int q = 0; q < kMaxSlots; q++) omk[q] = om[q];
-        if constexpr (MODE == MODE_PSI) {
-#pragma unroll
-            for (int q = 0; q < kMaxSlots; q++)
-                if (q < G.n_slots && A.tr[G.t[q]].kind == 0) omk[q] = om[q] * phi[gc * A.ray_cols + pidx[q]];
-        }
-        accumulate<R, MODE>(a, G, p, kap, omk, I, R(0), out, N, N - 1, lane);
-        R chi_prev = p.chi, S_prev = p.S;
-        R z_prev = static_cast<R>(a.z[g]);
-        for (int k = N - 2; k >= 0; k--) {
-            gc = gc0 + k; g = g0 + k;
-            point_terms<R>(a, G, gc, g, phi + gc * A.ray_cols, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-            const R zk = static_cast<R>(a.z[g]);
-            const R x = R(0.5) * (chi_prev + p.chi) * (zk - z_prev) / mu;
-            R e, wa, wb;
-            sc_weights<R>(x, e, wa, wb);
-            const R up = I * e + wa * S_prev;
-            const R Ieff = up + wb * p.etabg / p.chi;
-            const R psi = wb / p.chi;
-            I = up + wb * p.S;
-            if constexpr (MODE == MODE_PSI) {
-#pragma unroll
-                for (int q = 0; q < kMaxSlots; q++)
-                    omk[q] = (q < G.n_slots && A.tr[G.t[q]].kind == 0) ? om[q] * phi[gc * A.ray_cols + pidx[q]] : om[q];
-            }
-            accumulate<R, MODE>(a, G, p, kap, omk, Ieff, psi, out, N, k, lane);
-            chi_prev = p.chi; S_prev = p.S; z_prev = zk;
-        }
+    switch (rfl(a.A.groups[grp].n_slots)) {
+        case 1: sweep_group<R, MODE, 1>(a, grp, colc, lane); break;
+        case 2: sweep_group<R, MODE, 2>(a, grp, colc, lane); break;
+        case 3: sweep_group<R, MODE, 3>(a, grp, colc, lane); break;
+        default: sweep_group<R, MODE, 4>(a, grp, colc, lane); break;
     }
 }
 
@@ -597,7 +650,10 @@ __global__ __launch_bounds__(256) void k_se(ChunkArgs a) {
     }
     if (ZERO_RAD) {
 #pragma unroll
-        for (int i = 0; i < L; i++) a.pops[g * L + i] = b[i];
+        for (int i = 0; i < L; i++) {
+            a.pops[g * L + i] = b[i];
+            if (a.popsf) a.popsf[gc * L + i] = static_cast<float>(b[i]);
+        }
         return;
     }
     double dmax = 0.0;
@@ -712,6 +768,8 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
         if (status < 0 && it >= a.max_iter) status = RH15D_MAX_ITER;
     }
     __syncthreads();
+    if (a.popsf)
+        for (int i = threadIdx.x; i < NV; i += kConvThreads) a.popsf[gc0 * L + i] = static_cast<float>(pops[i]);
     if (threadIdx.x == 0) {
         a.col_it[colc] = it;
         if (status >= 0) {
@@ -929,7 +987,7 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
 
 struct Layout {
     size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_nse, off_dk, off_flag, off_ring,
-        off_cols, off_counter, total;
+        off_cols, off_counter, off_rec, off_popsf, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -952,6 +1010,8 @@ Layout make_layout(const DevAtom &D, int64_t n_columns, int64_t TDmax, int Smax,
     l.off_ring = take(ng ? 4 * TDmax * D.L * 8 : 8);
     l.off_cols = take((size_t)Smax * 4 * 4);
     l.off_counter = take(256);
+    l.off_rec = take(TDmax * rec_width(D.n_cont) * R);
+    l.off_popsf = take(fp32 ? TDmax * D.L * 4 : 8);
     l.total = o;
     return l;
 }
@@ -1151,6 +1211,9 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.dk = reinterpret_cast<double *>(ws + lay.off_dk);
     a.flag = reinterpret_cast<int *>(ws + lay.off_flag);
     a.ring = reinterpret_cast<double *>(ws + lay.off_ring);
+    a.rec = ws + lay.off_rec;
+    a.rec_w = rec_width(D->n_cont);
+    a.popsf = fp32 ? reinterpret_cast<float *>(ws + lay.off_popsf) : nullptr;
     int *colbuf = reinterpret_cast<int *>(ws + lay.off_cols);
     a.col_done = colbuf; a.col_it = colbuf + S; a.ng_count = colbuf + 2 * S; a.ng_head = colbuf + 3 * S;
     a.done_counter = reinterpret_cast<int *>(ws + lay.off_counter);
@@ -1173,7 +1236,8 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
         a.TD = cols->depth_offset[c1] - a.G0;
         const int tdb = (int)((a.TD + 255) / 256);
         tm.mark(2, st);
-        hipLaunchKernelGGL(k_prep_depth, dim3(tdb), dim3(256), 0, st, a);
+        if (fp32) hipLaunchKernelGGL(k_prep_depth<float>, dim3(tdb), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_prep_depth<double>, dim3(tdb), dim3(256), 0, st, a);
         const int64_t pairs = a.TD * D->n_lines;
         if (pairs > 0) {
             const int pb = (int)((pairs + 3) / 4);
