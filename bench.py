@@ -52,8 +52,16 @@ def make_batches(rh, cols, dev_fields, batch):
     return out
 
 
-def run_form(rh, torch, atom, batches, precision, steps, warmup, ws):
-    opts = rh.default_options(precision=precision, n_mu=5, tol=1e-4, max_iter=200, profile=1)
+FORMS = {
+    # plain FP64 MALI, fixed chunks of columns iterated together
+    "fp64": dict(precision=0, scheduler=0),
+    # precision form on the slot scheduler (retire converged columns, refill slots)
+    "fp32": dict(precision=1, scheduler=1),
+}
+
+
+def run_form(rh, torch, atom, batches, form, steps, warmup, ws):
+    opts = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, profile=1, **FORMS[form])
     solvers = [rh.Solver(atom, dc, opts, want_spectrum=True, workspace=ws) for _, _, dc in batches]
     nb = len(solvers)
     for i in range(warmup):
@@ -131,9 +139,9 @@ def accuracy(results, form, batches, cols):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--forms", default="fp64,fp32")
@@ -164,7 +172,7 @@ def main():
     ws_bytes = 0
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     for f in forms:
-        o = rh.default_options(precision=1 if f == "fp32" else 0, n_mu=5, tol=1e-4, max_iter=200)
+        o = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, **FORMS[f])
         ws_bytes = max(ws_bytes, max(rh.workspace_size(atom, dc, o) for _, _, dc in batches))
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
@@ -172,7 +180,7 @@ def main():
     res = {}
     for f in forms:
         log(f"form {f}: warmup {args.warmup}, steps {args.steps}")
-        r = run_form(rh, torch, atom, batches, 1 if f == "fp32" else 0, args.steps, args.warmup, ws)
+        r = run_form(rh, torch, atom, batches, f, args.steps, args.warmup, ws)
         st = r["stats"]
         sweep_s = st["sweep_ms"] / 1e3
         res[f] = r
@@ -204,8 +212,8 @@ def main():
             "workload": (f"synthetic 3D cube {args.nx}x{args.nx} columns (seed {args.seed}), 200-400 depth "
                          f"points, H-like 6-level atom (10 lines, 5 continua, 510 wavelengths), 5 angles, "
                          f"tol 1e-4 from LTE, batches of {args.batch} columns"),
-            "form": "FP32 formal solution + FP64 rate solve (no warm start yet)" if headline == "fp32"
-            else "plain FP64",
+            "form": "slot scheduler, FP32 formal solution + FP64 rate solve (no warm start yet)" if headline == "fp32"
+            else "plain FP64, chunked",
             "global_batch": args.batch,
             "parallelism": "1 GPU",
         },

@@ -8,7 +8,7 @@
 // relative population change; vertical emergent spectra only.
 //
 // Mapping onto CDNA4:
-//  * formal solution (k_raysweep): one lane per ray (wavelength, angle,
+//  * formal solution (k_sweep): one lane per ray (wavelength, angle,
 //    direction) of a column; the 64 rays of a wavefront share one set of
 //    active transitions, walk the depth recurrence in lock-step, read the
 //    per-depth column data as wave-uniform (scalar) loads and the
@@ -19,6 +19,12 @@
 //  * rate-equation solve (k_se): one lane per depth point, an L x L FP64
 //    system in registers, Gaussian elimination with partial pivoting;
 //  * convergence test and Ng (k_converge): one workgroup per column;
+//  * columns live in "slots" of a fixed depth stride; one iteration is a
+//    fixed sequence of kernels (sweep, rate solve, convergence + Ng, output
+//    of finished columns, refill of free slots from a column queue on the
+//    device), so it can be captured once as a hipGraph and replayed.  The
+//    plain scheduler refills only when every slot is free (fixed chunks);
+//    the slot scheduler refills a slot as soon as its column is done;
 //  * precision form: the sweep and its rate accumulation in FP32, the rate
 //    solve, Ng and the convergence test in FP64.
 #include <hip/hip_runtime.h>
@@ -156,6 +162,7 @@ __device__ __forceinline__ R wave_sum(R v) {
 }
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t rfl_wave(int64_t x) { return (int64_t)__builtin_amdgcn_readfirstlane((int)x); }
 
 // rays (2 directions x angles x wavelengths) of one line at one depth that
 // the profile-preparation wavefront holds in registers
@@ -164,62 +171,69 @@ constexpr int kMaxLineRays = 1536;
 // ---------------------------------------------------------------------------
 // per-launch arguments
 // ---------------------------------------------------------------------------
-struct ChunkArgs {
+enum SlotState { SLOT_FREE = 0, SLOT_ACTIVE = 1, SLOT_DONE = 2, SLOT_PENDING = 3 };
+enum Counter { CTR_NEXT = 0, CTR_EMITTED = 1, CTR_RETIRE = 2, CTR_REFILL = 3, CTR_COUNT = 8 };
+
+struct RunArgs {
     DevAtom A;
-    const int64_t *doff;      // [n_columns+1] global depth offsets (device)
-    int c_first, S;           // columns of this chunk
-    int64_t G0;               // global depth index of the chunk's first point
-    int64_t TD;               // depth points in the chunk
+    const int64_t *doff;      // [n_columns+1] depth offsets of the columns (device)
+    int64_t n_columns;
+    int S, ND;                // slots, depth stride of a slot
+    int chunked;              // refill only when every slot is free
+    int rec_w;
     // inputs (global depth index)
     const double *z, *T, *ne, *nH, *vz, *vt, *init;
-    // outputs
+    // outputs (global depth / column index)
     double *pops, *history, *spectrum, *psi;
     int32_t *n_iter, *status;
-    // workspace (chunk-local depth index gc)
-    double *lnr;              // [TD][L] Saha-Boltzmann log ratios to level 0
-    double *kbg;              // [TD] background opacity at the reference wavelength
-    double *gr;               // [TD][n_cont] n*_l / n*_u of each continuum
-    double *norm;             // [TD][n_lines] profile normalisation sums
-    void *phi;                // [TD][ray_cols] normalised profiles (double or float)
-    void *part;               // rate keys: column block at gc0*n_keys, [key][N]
-    void *rec;                // [TD][rec_w] per-depth data of the sweep (sweep precision)
-    float *popsf;             // [TD][L] FP32 copy of the populations (FP32 form)
-    int rec_w, pad_rw;
-    double *nse;              // [TD][L] rate-equation solution
-    double *dk;               // [TD] max relative change per depth point
-    int *flag;                // [TD] 0 ok, 1 non-finite/non-positive, 2 singular
-    double *ring;             // [4][TD][L] Ng history
-    int *col_done, *col_it, *ng_count, *ng_head;  // [S]
-    int *done_counter;
+    // per slot
+    int *slot_col, *slot_state, *slot_it, *ng_count, *ng_head;
+    int *ctr;                 // [CTR_COUNT]
+    int *retire_list, *refill_list;
+    // workspace, slot-local depth index gc = slot * ND + k
+    double *lnr;              // [gc][L] Saha-Boltzmann log ratios to level 0
+    double *kbg;              // [gc] background opacity at the reference wavelength
+    double *gr;               // [gc][n_cont] n*_l / n*_u of each continuum
+    double *norm;             // [gc][n_lines] profile normalisation sums
+    void *phi;                // [gc][ray_cols] normalised profiles (sweep precision)
+    void *part;               // rate keys: slot block at slot*ND*n_keys, [key][N]
+    void *rec;                // [gc][rec_w] per-depth data of the sweep (sweep precision)
+    float *popsf;             // [gc][L] FP32 copy of the populations (FP32 form)
+    double *nse;              // [gc][L] rate-equation solution
+    double *dk;               // [gc] max relative change per depth point
+    int *flag;                // [gc] 0 ok, 1 non-finite/non-positive, 2 singular
+    double *ring;             // [4][S*ND][L] Ng history
     int max_iter, ng_order, ng_delay, ng_period, start;
     double tol, coll_scale;
 };
 
-// Per-depth data of the sweep (chunk-local depth gc), in the sweep's precision:
+// Per-depth data of the sweep (slot-local depth gc), in the sweep's precision:
 // [0] z(k-1) - z(k) (0 at the top point), [1] 1/T, [2] background opacity at
 // the reference wavelength, [3] unused, [4 + c] n*_l / n*_u of continuum c.
 constexpr int kRecHead = 4;
 __host__ __device__ __forceinline__ int rec_width(int n_cont) { return (kRecHead + n_cont + 1) & ~1; }
 
-__device__ __forceinline__ int find_column(const ChunkArgs &a, int64_t gc) {
-    // last column of the chunk whose first point is <= gc
-    int lo = 0, hi = a.S - 1;
-    const int64_t g = gc + a.G0;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (a.doff[a.c_first + mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+struct ColGeom {
+    int col, N;
+    int64_t g0, gc0;
+};
+__device__ __forceinline__ ColGeom geom(const RunArgs &a, int slot) {
+    ColGeom c;
+    c.col = a.slot_col[slot];
+    c.g0 = a.doff[c.col];
+    c.N = (int)(a.doff[c.col + 1] - c.g0);
+    c.gc0 = (int64_t)slot * a.ND;
+    return c;
 }
 
 // ---------------------------------------------------------------------------
-// column preparation
+// column preparation (slots being refilled)
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_prep_depth(ChunkArgs a) {
-    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gc >= a.TD) return;
-    const int64_t g = gc + a.G0;
+__device__ void prep_point(const RunArgs &a, int slot, int k) {
+    const ColGeom cg = geom(a, slot);
+    if (k >= cg.N) return;
+    const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
     const int L = A.L;
     const double T = a.T[g], ne = a.ne[g], nH = a.nH[g];
@@ -244,10 +258,8 @@ __global__ void k_prep_depth(ChunkArgs a) {
     }
     const double kbg = A.bg_kind == 1 ? A.c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T) : 0.0;
     a.kbg[gc] = kbg;
-    const int colc = find_column(a, gc);
-    const bool top = (g == a.doff[a.c_first + colc]);
     R *rec = reinterpret_cast<R *>(a.rec) + gc * a.rec_w;
-    rec[0] = static_cast<R>(top ? 0.0 : a.z[g - 1] - a.z[g]);
+    rec[0] = static_cast<R>(k == 0 ? 0.0 : a.z[g - 1] - a.z[g]);
     rec[1] = static_cast<R>(1.0 / T);
     rec[2] = static_cast<R>(kbg);
     rec[3] = R(0);
@@ -259,18 +271,22 @@ __global__ void k_prep_depth(ChunkArgs a) {
     }
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void k_prep_depth(RunArgs a) {
+    const int64_t n = (int64_t)a.ctr[CTR_REFILL] * a.ND;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x)
+        prep_point<R>(a, a.refill_list[w / a.ND], (int)(w % a.ND));
+}
+
 // One wavefront per (depth point, line): every quadrature ray's profile,
 // normalised so that sum over rays of W phi = 1 at this depth.
 template <typename R>
-__global__ __launch_bounds__(256) void k_prep_profile(ChunkArgs a) {
+__device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int lane) {
     constexpr int kPer = kMaxLineRays / kWave;  // rays per lane
+    const ColGeom cg = geom(a, slot);
+    if (k >= cg.N) return;
     const DevAtom &A = a.A;
-    const int64_t pair = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (pair >= a.TD * A.n_lines) return;
-    const int64_t gc = pair / A.n_lines;
-    const int t = (int)(pair % A.n_lines);
-    const int64_t g = gc + a.G0;
+    const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevTransition &tr = A.tr[t];
     const double T = a.T[g], vt = a.vt[g], vz = a.vz[g];
     const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * T / A.mass + vt * vt);
@@ -303,9 +319,19 @@ __global__ __launch_bounds__(256) void k_prep_profile(ChunkArgs a) {
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
 }
 
-// ---------------------------------------------------------------------------
-// formal solution + preconditioned rate accumulation
-// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_prep_profile(RunArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int nl = a.A.n_lines;
+    const int64_t n = (int64_t)a.ctr[CTR_REFILL] * a.ND * nl;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t w = rfl_wave(blockIdx.x * 4 + (threadIdx.x >> 6)); w < n; w += waves) {
+        const int t = (int)(w % nl);
+        const int64_t sk = w / nl;
+        prep_profile_item<R>(a, a.refill_list[sk / a.ND], (int)(sk % a.ND), t, lane);
+    }
+}
+
 enum { MODE_RATES = 0, MODE_PSI = 1 };
 
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -340,7 +366,7 @@ __device__ __forceinline__ R wave_total(R v) {
 
 
 template <typename R>
-__device__ __forceinline__ const R *pops_row(const ChunkArgs &a, int64_t g, int64_t gc) {
+__device__ __forceinline__ const R *pops_row(const RunArgs &a, int64_t g, int64_t gc) {
     if constexpr (sizeof(R) == 8) return a.pops + g * a.A.L;
     else return a.popsf + gc * a.A.L;
 }
@@ -360,7 +386,7 @@ struct Slots {
 
 // Opacity, emissivity and source function of a lane's ray at depth point k.
 template <typename R, int NS>
-__device__ __forceinline__ void eval_point(const ChunkArgs &a, const Slots<R, NS> &sl, int64_t g, int64_t gc,
+__device__ __forceinline__ void eval_point(const RunArgs &a, const Slots<R, NS> &sl, int64_t g, int64_t gc,
                                            const int *pidx, const R *alpha, R hnu_k, R two_hnu3, R lamfac,
                                            Point<R, NS> &p) {
     const DevAtom &A = a.A;
@@ -435,12 +461,12 @@ __device__ __forceinline__ void accumulate(const Point<R, NS> &p, const R *kap, 
 // start at the top with no incoming radiation; up rays start at the bottom
 // with the diffusion approximation I = B + mu dB/dtau.
 template <typename R, int MODE, int NS>
-__device__ __forceinline__ void sweep_group(const ChunkArgs &a, int grp, int colc, int lane) {
+__device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane) {
     const DevAtom &A = a.A;
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = rfl((int)(a.doff[c + 1] - g0));
-    const int64_t gc0 = g0 - a.G0;
+    const ColGeom cg = geom(a, slot);
+    const int64_t g0 = cg.g0;
+    const int N = rfl(cg.N);
+    const int64_t gc0 = cg.gc0;
     const DevGroup &G = A.groups[grp];
     const int s_dir = rfl(G.s);
     const int key_off = rfl(G.key_off);
@@ -508,17 +534,23 @@ __device__ __forceinline__ void sweep_group(const ChunkArgs &a, int grp, int col
 }
 
 template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_raysweep(ChunkArgs a) {
+__global__ __launch_bounds__(256) void k_sweep(RunArgs a) {
     const int grp = rfl(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int colc = blockIdx.y;
     if (grp >= a.A.n_groups) return;
-    if (MODE == MODE_RATES && a.col_done[colc]) return;
+    int slot;
+    if (MODE == MODE_RATES) {
+        slot = blockIdx.y;
+        if (a.slot_state[slot] != SLOT_ACTIVE) return;
+    } else {
+        if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
+        slot = rfl(a.retire_list[blockIdx.y]);
+    }
     switch (rfl(a.A.groups[grp].n_slots)) {
-        case 1: sweep_group<R, MODE, 1>(a, grp, colc, lane); break;
-        case 2: sweep_group<R, MODE, 2>(a, grp, colc, lane); break;
-        case 3: sweep_group<R, MODE, 3>(a, grp, colc, lane); break;
-        default: sweep_group<R, MODE, 4>(a, grp, colc, lane); break;
+        case 1: sweep_group<R, MODE, 1>(a, grp, slot, lane); break;
+        case 2: sweep_group<R, MODE, 2>(a, grp, slot, lane); break;
+        case 3: sweep_group<R, MODE, 3>(a, grp, slot, lane); break;
+        default: sweep_group<R, MODE, 4>(a, grp, slot, lane); break;
     }
 }
 
@@ -526,19 +558,13 @@ __global__ __launch_bounds__(256) void k_raysweep(ChunkArgs a) {
 // statistical equilibrium per depth point
 // ---------------------------------------------------------------------------
 template <typename R, int L, bool ZERO_RAD>
-__global__ __launch_bounds__(256) void k_se(ChunkArgs a) {
-    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gc >= a.TD) return;
-    const int colc = find_column(a, gc);
-    if (!ZERO_RAD && a.col_done[colc]) return;
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = (int)(a.doff[c + 1] - g0);
-    const int64_t gc0 = g0 - a.G0;
-    const int k = (int)(gc - gc0);
-    const int64_t g = gc + a.G0;
+__device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
+    const ColGeom cg = geom(a, slot);
+    if (k >= cg.N) return;
+    const int N = cg.N;
+    const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
-    const R *part = reinterpret_cast<const R *>(a.part) + gc0 * A.n_keys;
+    const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
     double M[L][L];
     double nold[L], b[L];
 #pragma unroll
@@ -668,8 +694,24 @@ __global__ __launch_bounds__(256) void k_se(ChunkArgs a) {
     a.flag[gc] = fl;
 }
 
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_se(RunArgs a) {
+    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gc >= (int64_t)a.S * a.ND) return;
+    const int slot = (int)(gc / a.ND);
+    if (a.slot_state[slot] != SLOT_ACTIVE) return;
+    se_point<R, L, false>(a, slot, (int)(gc % a.ND));
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_se_zero_radiation(RunArgs a) {
+    const int64_t n = (int64_t)a.ctr[CTR_REFILL] * a.ND;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x)
+        se_point<double, L, true>(a, a.refill_list[w / a.ND], (int)(w % a.ND));
+}
+
 // ---------------------------------------------------------------------------
-// convergence test and Ng acceleration, one workgroup per column
+// convergence test and Ng acceleration, one workgroup per slot
 // ---------------------------------------------------------------------------
 constexpr int kConvThreads = 256;
 
@@ -698,17 +740,16 @@ __device__ double block_max(double v, double *sh) {
     return r;
 }
 
-__global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
+__global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
     __shared__ double sh[kConvThreads];
-    const int colc = blockIdx.x;
-    if (a.col_done[colc]) return;
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = (int)(a.doff[c + 1] - g0);
-    const int64_t gc0 = g0 - a.G0;
+    const int slot = blockIdx.x;
+    if (a.slot_state[slot] != SLOT_ACTIVE) return;
+    const ColGeom cg = geom(a, slot);
+    const int c = cg.col, N = cg.N;
+    const int64_t g0 = cg.g0, gc0 = cg.gc0;
     const int L = a.A.L;
     const int NV = N * L;
-    const int it = a.col_it[colc] + 1;
+    const int it = a.slot_it[slot] + 1;
     double dm = 0.0, fl = 0.0;
     for (int k = threadIdx.x; k < N; k += kConvThreads) {
         dm = fmax(dm, a.dk[gc0 + k]);
@@ -727,11 +768,11 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
         if (dm < a.tol) {
             status = RH15D_CONVERGED;
         } else if (a.ng_order == 2 && it >= a.ng_delay) {
-            const size_t stride = (size_t)a.TD * L;
-            int head = (a.ng_head[colc] + 1) & 3;
+            const size_t stride = (size_t)a.S * a.ND * L;
+            const int head = (a.ng_head[slot] + 1) & 3;
             double *newest = a.ring + head * stride + gc0 * L;
             for (int i = threadIdx.x; i < NV; i += kConvThreads) newest[i] = nse[i];
-            int cnt = a.ng_count[colc] + 1;
+            int cnt = a.ng_count[slot] + 1;
             const int need = a.ng_period > 4 ? a.ng_period : 4;
             if (cnt >= need) {
                 const double *x0 = a.ring + head * stride + gc0 * L;
@@ -763,7 +804,7 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
                 }
                 cnt = 0;
             }
-            if (threadIdx.x == 0) { a.ng_head[colc] = head; a.ng_count[colc] = cnt; }
+            if (threadIdx.x == 0) { a.ng_head[slot] = head; a.ng_count[slot] = cnt; }
         }
         if (status < 0 && it >= a.max_iter) status = RH15D_MAX_ITER;
     }
@@ -771,34 +812,20 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(ChunkArgs a) {
     if (a.popsf)
         for (int i = threadIdx.x; i < NV; i += kConvThreads) a.popsf[gc0 * L + i] = static_cast<float>(pops[i]);
     if (threadIdx.x == 0) {
-        a.col_it[colc] = it;
+        a.slot_it[slot] = it;
         if (status >= 0) {
-            a.col_done[colc] = 1;
             a.status[c] = status;
             a.n_iter[c] = it;
-            atomicAdd(a.done_counter, 1);
+            a.slot_state[slot] = SLOT_DONE;
+            a.retire_list[atomicAdd(&a.ctr[CTR_RETIRE], 1)] = slot;
         }
     }
 }
 
-__global__ void k_init_columns(ChunkArgs a) {
-    const int colc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (colc >= a.S) return;
-    const int c = a.c_first + colc;
-    a.col_done[colc] = a.max_iter == 0 ? 1 : 0;
-    a.col_it[colc] = 0;
-    a.ng_count[colc] = 0;
-    a.ng_head[colc] = 0;
-    a.status[c] = RH15D_MAX_ITER;
-    a.n_iter[c] = 0;
-    if (a.history)
-        for (int i = 0; i < a.max_iter; i++) a.history[(size_t)c * a.max_iter + i] = NAN;
-}
-
 // ---------------------------------------------------------------------------
-// vertical emergent intensity, one lane per (column, wavelength)
+// output of finished columns: vertical emergent intensity and Psi*
 // ---------------------------------------------------------------------------
-__device__ void point_opacity_mu1(const ChunkArgs &a, int j, int64_t gc, int64_t g, double &chi, double &S,
+__device__ void point_opacity_mu1(const RunArgs &a, int j, int64_t gc, int64_t g, double &chi, double &S,
                                   double &B) {
     const DevAtom &A = a.A;
     const int L = A.L;
@@ -833,48 +860,127 @@ __device__ void point_opacity_mu1(const ChunkArgs &a, int j, int64_t gc, int64_t
     S = e / c;
 }
 
-__global__ void k_emergent(ChunkArgs a) {
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
     const DevAtom &A = a.A;
-    if (idx >= (int64_t)a.S * A.NL) return;
-    const int colc = (int)(idx / A.NL), j = (int)(idx % A.NL);
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = (int)(a.doff[c + 1] - g0);
-    const int64_t gc0 = g0 - a.G0;
-    double chi2, S2, B2, chi, S, B;
-    point_opacity_mu1(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
-    point_opacity_mu1(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
-    const double dtv = 0.5 * (chi + chi2) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
-    double I = dtv > 0.0 ? B + (B - B2) / dtv : B;
-    double chi_p = chi, S_p = S;
-    for (int k = N - 2; k >= 0; k--) {
-        point_opacity_mu1(a, j, gc0 + k, g0 + k, chi, S, B);
-        const double x = 0.5 * (chi_p + chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
-        double e, wa, wb;
-        sc_weights<double>(x, e, wa, wb);
-        I = I * e + wa * S_p + wb * S;
-        chi_p = chi; S_p = S;
+    const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = a.retire_list[w / A.NL], j = (int)(w % A.NL);
+        const ColGeom cg = geom(a, slot);
+        const int N = cg.N;
+        const int64_t g0 = cg.g0, gc0 = cg.gc0;
+        double chi2, S2, B2, chi, S, B;
+        point_opacity_mu1(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
+        point_opacity_mu1(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
+        const double dtv = 0.5 * (chi + chi2) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
+        double I = dtv > 0.0 ? B + (B - B2) / dtv : B;
+        double chi_p = chi, S_p = S;
+        for (int k = N - 2; k >= 0; k--) {
+            point_opacity_mu1(a, j, gc0 + k, g0 + k, chi, S, B);
+            const double x = 0.5 * (chi_p + chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
+            double e, wa, wb;
+            sc_weights<double>(x, e, wa, wb);
+            I = I * e + wa * S_p + wb * S;
+            chi_p = chi; S_p = S;
+        }
+        a.spectrum[(size_t)cg.col * A.NL + j] = I;
     }
-    a.spectrum[(size_t)c * A.NL + j] = I;
 }
 
 template <typename R>
-__global__ void k_psi_gather(ChunkArgs a) {
+__global__ __launch_bounds__(256) void k_psi_gather(RunArgs a) {
     const DevAtom &A = a.A;
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= a.TD * A.T) return;
-    const int64_t gc = idx / A.T;
-    const int t = (int)(idx % A.T);
-    const int colc = find_column(a, gc);
-    const int c = a.c_first + colc;
-    const int64_t g0 = a.doff[c];
-    const int N = (int)(a.doff[c + 1] - g0);
-    const int64_t gc0 = g0 - a.G0;
-    const R *part = reinterpret_cast<const R *>(a.part) + gc0 * A.n_keys;
-    double s = 0.0;
-    for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * N + (gc - gc0)]);
-    a.psi[(gc + a.G0) * A.T + t] = s;
+    const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * a.ND * A.T;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(w % A.T);
+        const int64_t sk = w / A.T;
+        const int slot = a.retire_list[sk / a.ND], k = (int)(sk % a.ND);
+        const ColGeom cg = geom(a, slot);
+        if (k >= cg.N) continue;
+        const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
+        double s = 0.0;
+        for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * cg.N + k]);
+        a.psi[(cg.g0 + k) * A.T + t] = s;
+    }
+}
+
+// Finished columns leave their slots; free slots take the next columns of
+// the queue (in slot order, so a run is reproducible).  The plain scheduler
+// waits until every slot is free.
+constexpr int kRefillThreads = 1024;
+
+__global__ __launch_bounds__(kRefillThreads) void k_refill(RunArgs a) {
+    __shared__ int sh[kRefillThreads];
+    __shared__ int busy;
+    const int t = threadIdx.x;
+    const int nret = a.ctr[CTR_RETIRE];
+    for (int i = t; i < nret; i += kRefillThreads) a.slot_state[a.retire_list[i]] = SLOT_FREE;
+    if (t == 0) busy = 0;
+    __syncthreads();
+    const int per = (a.S + kRefillThreads - 1) / kRefillThreads;
+    const int s0 = t * per, s1 = min(a.S, s0 + per);
+    int nfree = 0;
+    for (int s = s0; s < s1; s++) {
+        if (a.slot_state[s] == SLOT_FREE) nfree++;
+        else atomicOr(&busy, 1);
+    }
+    sh[t] = nfree;
+    __syncthreads();
+    for (int o = 1; o < kRefillThreads; o <<= 1) {  // inclusive scan
+        const int v = t >= o ? sh[t - o] : 0;
+        __syncthreads();
+        sh[t] += v;
+        __syncthreads();
+    }
+    const int next = a.ctr[CTR_NEXT];
+    const int total_free = sh[kRefillThreads - 1];
+    int avail = (int)min<int64_t>((int64_t)total_free, a.n_columns - next);
+    if (a.chunked && busy) avail = 0;
+    int rank = sh[t] - nfree;
+    for (int s = s0; s < s1; s++) {
+        if (a.slot_state[s] != SLOT_FREE) continue;
+        if (rank < avail) {
+            a.slot_col[s] = next + rank;
+            a.slot_state[s] = SLOT_PENDING;
+            a.refill_list[rank] = s;
+        }
+        rank++;
+    }
+    __syncthreads();
+    if (t == 0) {
+        a.ctr[CTR_EMITTED] += nret;
+        a.ctr[CTR_RETIRE] = 0;
+        a.ctr[CTR_REFILL] = avail;
+        a.ctr[CTR_NEXT] = next + avail;
+    }
+}
+
+__global__ void k_init_slots(RunArgs a) {
+    const int n = a.ctr[CTR_REFILL];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int slot = a.refill_list[i];
+        const int c = a.slot_col[slot];
+        a.slot_it[slot] = 0;
+        a.ng_count[slot] = 0;
+        a.ng_head[slot] = 0;
+        a.status[c] = RH15D_MAX_ITER;
+        a.n_iter[c] = 0;
+        if (a.history)
+            for (int k = 0; k < a.max_iter; k++) a.history[(size_t)c * a.max_iter + k] = NAN;
+        if (a.max_iter == 0) {
+            a.slot_state[slot] = SLOT_DONE;
+            a.retire_list[atomicAdd(&a.ctr[CTR_RETIRE], 1)] = slot;
+        } else {
+            a.slot_state[slot] = SLOT_ACTIVE;
+        }
+    }
+}
+
+__global__ void k_setup(RunArgs a) {
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < a.S; s += gridDim.x * blockDim.x) {
+        a.slot_state[s] = SLOT_FREE;
+        a.slot_col[s] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < CTR_COUNT) a.ctr[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -986,32 +1092,34 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
 }
 
 struct Layout {
-    size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_nse, off_dk, off_flag, off_ring,
-        off_cols, off_counter, off_rec, off_popsf, total;
+    size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_rec, off_popsf, off_nse, off_dk,
+        off_flag, off_ring, off_slots, off_ctr, off_lists, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(const DevAtom &D, int64_t n_columns, int64_t TDmax, int Smax, bool fp32, bool ng) {
+Layout make_layout(const DevAtom &D, int64_t n_columns, int S, int ND, bool fp32, bool ng) {
     const size_t R = fp32 ? 4 : 8;
+    const size_t P = (size_t)S * ND;
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     l.off_doff = take((n_columns + 1) * 8);
-    l.off_lnr = take(TDmax * D.L * 8);
-    l.off_kbg = take(TDmax * 8);
-    l.off_gr = take(TDmax * std::max(D.n_cont, 1) * 8);
-    l.off_norm = take(TDmax * std::max(D.n_lines, 1) * 8);
-    l.off_phi = take(TDmax * std::max(D.ray_cols, 1) * R);
-    l.off_part = take(TDmax * D.n_keys * R);
-    l.off_nse = take(TDmax * D.L * 8);
-    l.off_dk = take(TDmax * 8);
-    l.off_flag = take(TDmax * 4);
-    l.off_ring = take(ng ? 4 * TDmax * D.L * 8 : 8);
-    l.off_cols = take((size_t)Smax * 4 * 4);
-    l.off_counter = take(256);
-    l.off_rec = take(TDmax * rec_width(D.n_cont) * R);
-    l.off_popsf = take(fp32 ? TDmax * D.L * 4 : 8);
+    l.off_lnr = take(P * D.L * 8);
+    l.off_kbg = take(P * 8);
+    l.off_gr = take(P * std::max(D.n_cont, 1) * 8);
+    l.off_norm = take(P * std::max(D.n_lines, 1) * 8);
+    l.off_phi = take(P * std::max(D.ray_cols, 1) * R);
+    l.off_part = take(P * D.n_keys * R);
+    l.off_rec = take(P * rec_width(D.n_cont) * R);
+    l.off_popsf = take(fp32 ? P * D.L * 4 : 8);
+    l.off_nse = take(P * D.L * 8);
+    l.off_dk = take(P * 8);
+    l.off_flag = take(P * 4);
+    l.off_ring = take(ng ? 4 * P * D.L * 8 : 8);
+    l.off_slots = take((size_t)S * 5 * 4);
+    l.off_ctr = take(CTR_COUNT * 4);
+    l.off_lists = take((size_t)S * 2 * 4);
     l.total = o;
     return l;
 }
@@ -1019,11 +1127,14 @@ Layout make_layout(const DevAtom &D, int64_t n_columns, int64_t TDmax, int Smax,
 int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *o) {
     if (!atom || !cols || !o) { set_error("null argument"); return RH15D_EINVAL; }
     if (cols->n_columns < 0 || (cols->n_columns > 0 && !cols->depth_offset)) { set_error("bad column count or offsets"); return RH15D_EINVAL; }
+    if (cols->n_columns > (int64_t)1 << 30) { set_error("too many columns"); return RH15D_EINVAL; }
     if (o->n_mu < 1 || o->n_mu > RH15D_MAX_MU) { set_error("n_mu must be in 1..%d", RH15D_MAX_MU); return RH15D_EINVAL; }
     if (o->ng_order != 0 && o->ng_order != 2) { set_error("ng_order must be 0 or 2"); return RH15D_EINVAL; }
     if (o->max_iter < 0) { set_error("max_iter must be >= 0"); return RH15D_EINVAL; }
     if (o->precision != RH15D_FP64 && o->precision != RH15D_FP32) { set_error("unknown precision"); return RH15D_EINVAL; }
     if (o->start < 0 || o->start > 2) { set_error("unknown start"); return RH15D_EINVAL; }
+    if (o->scheduler != RH15D_SCHED_CHUNKED && o->scheduler != RH15D_SCHED_SLOTS) { set_error("unknown scheduler"); return RH15D_EINVAL; }
+    if (o->batch_columns < 0) { set_error("batch_columns must be >= 0"); return RH15D_EINVAL; }
     if (o->start == RH15D_START_PROVIDED && !cols->init_pops) { set_error("start=PROVIDED needs init_pops"); return RH15D_EINVAL; }
     if (!(o->tol >= 0.0)) { set_error("tol must be >= 0"); return RH15D_EINVAL; }
     if (cols->depth_offset && cols->depth_offset[0] != 0) { set_error("depth_offset[0] must be 0"); return RH15D_EINVAL; }
@@ -1037,52 +1148,94 @@ int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_opti
     return RH15D_OK;
 }
 
-// Columns per chunk: the caller's choice, else as many as fit a 24 GiB
-// working set (the device has 288 GB of HBM; chunks this size keep
-// thousands of columns in flight).
-int chunk_columns(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o) {
-    if (o->batch_columns > 0) return (int)std::min<int64_t>(o->batch_columns, std::max<int64_t>(cols->n_columns, 1));
-    const size_t per_point = (o->precision == RH15D_FP32 ? 4 : 8) * (size_t)(D.ray_cols + D.n_keys) + 8 * (6 * D.L + 8);
-    const size_t budget = size_t(24) << 30;
-    const int64_t max_pts = budget / per_point;
-    const int64_t per_col = RH15D_MAX_DEPTH / 2;
-    int64_t S = std::max<int64_t>(1, max_pts / per_col);
-    S = std::min<int64_t>(S, 16384);
-    return (int)std::min<int64_t>(S, std::max<int64_t>(cols->n_columns, 1));
+int max_depth(const rh15d_columns *cols) {
+    int64_t nd = 2;
+    for (int64_t c = 0; c < cols->n_columns; c++) nd = std::max(nd, cols->depth_offset[c + 1] - cols->depth_offset[c]);
+    return (int)nd;
 }
 
-int64_t chunk_max_depth(const rh15d_columns *cols, int S) {
-    int64_t best = 0;
-    for (int64_t c0 = 0; c0 < cols->n_columns; c0 += S) {
-        const int64_t c1 = std::min<int64_t>(cols->n_columns, c0 + S);
-        best = std::max(best, cols->depth_offset[c1] - cols->depth_offset[c0]);
-    }
-    return best;
+// Resident columns: the caller's choice, else as many as fit a 40 GiB
+// working set (the device has 288 GB of HBM), at most 8192.
+int slot_count(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o, int ND) {
+    const int64_t n = std::max<int64_t>(cols->n_columns, 1);
+    if (o->batch_columns > 0) return (int)std::min<int64_t>(o->batch_columns, n);
+    const Layout one = make_layout(D, 0, 1, ND, o->precision == RH15D_FP32, o->ng_order == 2);
+    const size_t budget = size_t(40) << 30;
+    int64_t S = std::max<int64_t>(1, (int64_t)(budget / one.total));
+    return (int)std::min<int64_t>(std::min<int64_t>(S, 8192), n);
+}
+
+unsigned grid_for(int64_t work, int per_block, unsigned cap) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + per_block - 1) / per_block, cap));
 }
 
 template <int L>
-void launch_se(ChunkArgs &a, bool fp32, bool zero, hipStream_t st) {
-    const int blocks = (int)((a.TD + 255) / 256);
-    if (fp32) {
-        if (zero) hipLaunchKernelGGL((k_se<float, L, true>), dim3(blocks), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_se<float, L, false>), dim3(blocks), dim3(256), 0, st, a);
-    } else {
-        if (zero) hipLaunchKernelGGL((k_se<double, L, true>), dim3(blocks), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_se<double, L, false>), dim3(blocks), dim3(256), 0, st, a);
+void launch_se_l(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
+    if (zero) {
+        hipLaunchKernelGGL(k_se_zero_radiation<L>, dim3(grid_for((int64_t)a.S * a.ND, 256, 16384)), dim3(256), 0, st, a);
+        return;
+    }
+    const unsigned blocks = grid_for((int64_t)a.S * a.ND, 256, 1u << 30);
+    if (fp32) hipLaunchKernelGGL((k_se<float, L>), dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_se<double, L>), dim3(blocks), dim3(256), 0, st, a);
+}
+
+void launch_se(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
+    switch (a.A.L) {
+        case 2: launch_se_l<2>(a, fp32, zero, st); break;
+        case 3: launch_se_l<3>(a, fp32, zero, st); break;
+        case 4: launch_se_l<4>(a, fp32, zero, st); break;
+        case 5: launch_se_l<5>(a, fp32, zero, st); break;
+        case 6: launch_se_l<6>(a, fp32, zero, st); break;
+        case 7: launch_se_l<7>(a, fp32, zero, st); break;
+        default: launch_se_l<8>(a, fp32, zero, st); break;
     }
 }
 
-void se_dispatch(ChunkArgs &a, bool fp32, bool zero, hipStream_t st) {
-    switch (a.A.L) {
-        case 2: launch_se<2>(a, fp32, zero, st); break;
-        case 3: launch_se<3>(a, fp32, zero, st); break;
-        case 4: launch_se<4>(a, fp32, zero, st); break;
-        case 5: launch_se<5>(a, fp32, zero, st); break;
-        case 6: launch_se<6>(a, fp32, zero, st); break;
-        case 7: launch_se<7>(a, fp32, zero, st); break;
-        default: launch_se<8>(a, fp32, zero, st); break;
+struct Launcher {
+    RunArgs a;
+    bool fp32, zero_start, want_spec, want_psi;
+    hipStream_t st;
+    dim3 sweep_grid;
+
+    void refill_phase(Timer *tm) {
+        hipLaunchKernelGGL(k_refill, dim3(1), dim3(kRefillThreads), 0, st, a);
+        const int64_t pts = (int64_t)a.S * a.ND;
+        if (fp32) hipLaunchKernelGGL(k_prep_depth<float>, dim3(grid_for(pts, 256, 16384)), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(k_prep_depth<double>, dim3(grid_for(pts, 256, 16384)), dim3(256), 0, st, a);
+        if (a.A.n_lines > 0) {
+            const unsigned pb = grid_for(pts * a.A.n_lines, 4, 65536);
+            if (fp32) hipLaunchKernelGGL(k_prep_profile<float>, dim3(pb), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_prep_profile<double>, dim3(pb), dim3(256), 0, st, a);
+        }
+        if (zero_start) launch_se(a, fp32, true, st);
+        hipLaunchKernelGGL(k_init_slots, dim3(grid_for(a.S, 256, 1024)), dim3(256), 0, st, a);
+        (void)tm;
     }
-}
+
+    void iteration(Timer *tm) {
+        if (tm) tm->mark(2, st);
+        if (fp32) hipLaunchKernelGGL((k_sweep<float, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_sweep<double, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+        if (tm) tm->mark(3, st);
+        launch_se(a, fp32, false, st);
+        if (tm) tm->mark(4, st);
+        hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
+        if (tm) tm->mark(5, st);
+        if (want_spec)
+            hipLaunchKernelGGL(k_emergent, dim3(grid_for((int64_t)a.S * a.A.NL, 256, 8192)), dim3(256), 0, st, a);
+        if (want_psi) {
+            if (fp32) hipLaunchKernelGGL((k_sweep<float, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
+            else hipLaunchKernelGGL((k_sweep<double, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
+            const unsigned gb = grid_for((int64_t)a.S * a.ND * a.A.T, 256, 16384);
+            if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3(gb), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_psi_gather<double>, dim3(gb), dim3(256), 0, st, a);
+        }
+        if (tm) tm->mark(6, st);
+        refill_phase(tm);
+        if (tm) tm->mark(7, st);
+    }
+};
 
 }  // namespace
 
@@ -1155,9 +1308,9 @@ int rh15d_workspace_size(const rh15d_atom *atom_c, const rh15d_columns *cols, co
     if (!bytes) { set_error("null argument"); return RH15D_EINVAL; }
     DevAtom *D = nullptr;
     if ((rc = get_dev_atom(const_cast<rh15d_atom *>(atom_c), o->n_mu, &D)) != RH15D_OK) return rc;
-    const int S = chunk_columns(*D, cols, o);
-    const int64_t TD = std::max<int64_t>(chunk_max_depth(cols, S), 2);
-    *bytes = make_layout(*D, cols->n_columns, TD, S, o->precision == RH15D_FP32, o->ng_order == 2).total;
+    const int ND = max_depth(cols);
+    const int S = slot_count(*D, cols, o, ND);
+    *bytes = make_layout(*D, cols->n_columns, S, ND, o->precision == RH15D_FP32, o->ng_order == 2).total;
     return RH15D_OK;
 }
 
@@ -1168,133 +1321,123 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     if (!out || (cols->n_columns > 0 && (!out->pops || !out->n_iter || !out->status))) {
         set_error("null output array"); return RH15D_EINVAL;
     }
+    g_stats = rh15d_stats{};
     if (cols->n_columns == 0) return RH15D_OK;
     rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
     DevAtom *D = nullptr;
     if ((rc = get_dev_atom(atom, o->n_mu, &D)) != RH15D_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool fp32 = o->precision == RH15D_FP32;
-    const int S = chunk_columns(*D, cols, o);
-    const int64_t TDmax = std::max<int64_t>(chunk_max_depth(cols, S), 2);
-    const Layout lay = make_layout(*D, cols->n_columns, TDmax, S, fp32, o->ng_order == 2);
+    const int ND = max_depth(cols);
+    const int S = slot_count(*D, cols, o, ND);
+    const Layout lay = make_layout(*D, cols->n_columns, S, ND, fp32, o->ng_order == 2);
+    if (workspace && workspace_bytes < lay.total) {
+        set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total);
+        return RH15D_ENOMEM;
+    }
     void *own = nullptr;
     if (!workspace) {
         HIP_TRY(hipMalloc(&own, lay.total));
         workspace = own;
-        workspace_bytes = lay.total;
     }
-    if (workspace_bytes < lay.total) { set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total); return RH15D_ENOMEM; }
     char *ws = static_cast<char *>(workspace);
-    int *h_counter = nullptr;
+    int *h_ctr = nullptr;
     int result = RH15D_OK;
     auto fail = [&](hipError_t e, const char *what) {
-        set_error("%s: %s", what, hipGetErrorString(e));
+        if (result == RH15D_OK) set_error("%s: %s", what, hipGetErrorString(e));
         result = RH15D_EDEVICE;
     };
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h_counter), sizeof(int), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h_ctr), CTR_COUNT * sizeof(int), hipHostMallocDefault);
     if (e != hipSuccess) { fail(e, "hipHostMalloc"); if (own) (void)hipFree(own); return result; }
 
-    ChunkArgs a{};
+    RunArgs a{};
     a.A = *D;
     a.doff = reinterpret_cast<const int64_t *>(ws + lay.off_doff);
+    a.n_columns = cols->n_columns;
+    a.S = S; a.ND = ND;
+    a.chunked = o->scheduler == RH15D_SCHED_CHUNKED;
+    a.rec_w = rec_width(D->n_cont);
     a.z = cols->z; a.T = cols->T; a.ne = cols->n_e; a.nH = cols->n_H; a.vz = cols->v_z; a.vt = cols->v_turb;
     a.init = cols->init_pops;
     a.pops = out->pops; a.history = out->history; a.spectrum = out->spectrum; a.psi = out->psi_star;
     a.n_iter = out->n_iter; a.status = out->status;
+    int *slots = reinterpret_cast<int *>(ws + lay.off_slots);
+    a.slot_col = slots; a.slot_state = slots + S; a.slot_it = slots + 2 * S; a.ng_count = slots + 3 * S;
+    a.ng_head = slots + 4 * S;
+    a.ctr = reinterpret_cast<int *>(ws + lay.off_ctr);
+    a.retire_list = reinterpret_cast<int *>(ws + lay.off_lists);
+    a.refill_list = a.retire_list + S;
     a.lnr = reinterpret_cast<double *>(ws + lay.off_lnr);
     a.kbg = reinterpret_cast<double *>(ws + lay.off_kbg);
     a.gr = reinterpret_cast<double *>(ws + lay.off_gr);
     a.norm = reinterpret_cast<double *>(ws + lay.off_norm);
     a.phi = ws + lay.off_phi;
     a.part = ws + lay.off_part;
+    a.rec = ws + lay.off_rec;
+    a.popsf = fp32 ? reinterpret_cast<float *>(ws + lay.off_popsf) : nullptr;
     a.nse = reinterpret_cast<double *>(ws + lay.off_nse);
     a.dk = reinterpret_cast<double *>(ws + lay.off_dk);
     a.flag = reinterpret_cast<int *>(ws + lay.off_flag);
     a.ring = reinterpret_cast<double *>(ws + lay.off_ring);
-    a.rec = ws + lay.off_rec;
-    a.rec_w = rec_width(D->n_cont);
-    a.popsf = fp32 ? reinterpret_cast<float *>(ws + lay.off_popsf) : nullptr;
-    int *colbuf = reinterpret_cast<int *>(ws + lay.off_cols);
-    a.col_done = colbuf; a.col_it = colbuf + S; a.ng_count = colbuf + 2 * S; a.ng_head = colbuf + 3 * S;
-    a.done_counter = reinterpret_cast<int *>(ws + lay.off_counter);
     a.max_iter = o->max_iter; a.ng_order = o->ng_order; a.ng_delay = o->ng_delay; a.ng_period = o->ng_period;
     a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale;
 
-    g_stats = rh15d_stats{};
+    Launcher run{a, fp32, o->start == RH15D_START_ZERO_RADIATION, out->spectrum != nullptr, out->psi_star != nullptr,
+                 st, dim3((D->n_groups + 3) / 4, S)};
     Timer tm;
-    if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_counter); if (own) (void)hipFree(own); return rc; }
+    if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
+    Timer *tp = tm.on ? &tm : nullptr;
     tm.mark(0, st);
     e = hipMemcpyAsync(const_cast<int64_t *>(a.doff), cols->depth_offset, (cols->n_columns + 1) * sizeof(int64_t),
                        hipMemcpyHostToDevice, st);
     if (e != hipSuccess) fail(e, "copy depth offsets");
+    hipLaunchKernelGGL(k_setup, dim3(grid_for(S, 256, 1024)), dim3(256), 0, st, run.a);
+    run.refill_phase(nullptr);
 
-    for (int64_t c0 = 0; result == RH15D_OK && c0 < cols->n_columns; c0 += S) {
-        const int64_t c1 = std::min<int64_t>(cols->n_columns, c0 + S);
-        a.c_first = (int)c0;
-        a.S = (int)(c1 - c0);
-        a.G0 = cols->depth_offset[c0];
-        a.TD = cols->depth_offset[c1] - a.G0;
-        const int tdb = (int)((a.TD + 255) / 256);
-        tm.mark(2, st);
-        if (fp32) hipLaunchKernelGGL(k_prep_depth<float>, dim3(tdb), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL(k_prep_depth<double>, dim3(tdb), dim3(256), 0, st, a);
-        const int64_t pairs = a.TD * D->n_lines;
-        if (pairs > 0) {
-            const int pb = (int)((pairs + 3) / 4);
-            if (fp32) hipLaunchKernelGGL(k_prep_profile<float>, dim3(pb), dim3(256), 0, st, a);
-            else hipLaunchKernelGGL(k_prep_profile<double>, dim3(pb), dim3(256), 0, st, a);
+    // One iteration is a fixed sequence of launches whose amounts of work
+    // live on the device; the slot scheduler captures it once as a graph.
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const bool try_graph = o->scheduler == RH15D_SCHED_SLOTS && !tm.on && st != nullptr;
+    if (try_graph && result == RH15D_OK) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            run.iteration(nullptr);
+            if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph ||
+                hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                exec = nullptr;
         }
-        if (o->start == RH15D_START_ZERO_RADIATION) se_dispatch(a, fp32, true, st);
-        hipLaunchKernelGGL(k_init_columns, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
-        e = hipMemsetAsync(a.done_counter, 0, sizeof(int), st);
-        if (e != hipSuccess) { fail(e, "memset"); break; }
-        tm.mark(3, st);
-        const dim3 sweep_grid((D->n_groups + 3) / 4, a.S);
-        for (int it = 1; it <= o->max_iter; it++) {
-            tm.mark(4, st);
-            if (fp32) hipLaunchKernelGGL((k_raysweep<float, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_raysweep<double, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
-            tm.mark(5, st);
-            se_dispatch(a, fp32, false, st);
-            tm.mark(6, st);
-            hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
-            tm.mark(7, st);
-            e = hipMemcpyAsync(h_counter, a.done_counter, sizeof(int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) { fail(e, "iteration"); break; }
-            if (tm.on) {
-                if (it == 1) g_stats.prep_ms += tm.ms(2, 3);
-                g_stats.sweep_ms += tm.ms(4, 5);
-                g_stats.se_ms += tm.ms(5, 6);
-                g_stats.converge_ms += tm.ms(6, 7);
-                g_stats.sweep_launches++;
-            }
-            if (*h_counter >= a.S) break;
-        }
-        if (result != RH15D_OK) break;
-        tm.mark(2, st);
-        if (out->spectrum) {
-            const int64_t n = (int64_t)a.S * D->NL;
-            hipLaunchKernelGGL(k_emergent, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, a);
-        }
-        if (out->psi_star) {
-            // Psi* of the final populations: one more sweep, averaging Psi*
-            // per transition instead of accumulating rates
-            if (fp32) hipLaunchKernelGGL((k_raysweep<float, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_raysweep<double, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
-            const int64_t n = a.TD * D->T;
-            if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
-            else hipLaunchKernelGGL(k_psi_gather<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
-        }
-        tm.mark(3, st);
-        e = hipGetLastError();
-        if (e != hipSuccess) { fail(e, "kernel launch"); break; }
-        if (tm.on) {
-            e = hipStreamSynchronize(st);
-            if (e != hipSuccess) { fail(e, "synchronize"); break; }
-            g_stats.final_ms += tm.ms(2, 3);
-        }
+        (void)hipGetLastError();
     }
+    const int64_t rounds = (cols->n_columns + S - 1) / S;
+    const int64_t bound = (rounds + 1) * ((int64_t)o->max_iter + 2) + 4;
+    const int per_check = tm.on ? 1 : (exec ? 4 : 2);
+    int64_t iters = 0;
+    while (result == RH15D_OK) {
+        for (int r = 0; r < per_check; r++, iters++) {
+            if (exec) {
+                e = hipGraphLaunch(exec, st);
+                if (e != hipSuccess) { fail(e, "graph launch"); break; }
+            } else {
+                run.iteration(tp);
+            }
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h_ctr, a.ctr, CTR_COUNT * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { fail(e, "iteration"); break; }
+        if (tm.on) {
+            g_stats.sweep_ms += tm.ms(2, 3);
+            g_stats.se_ms += tm.ms(3, 4);
+            g_stats.converge_ms += tm.ms(4, 5);
+            g_stats.final_ms += tm.ms(5, 6);
+            g_stats.prep_ms += tm.ms(6, 7);
+            g_stats.sweep_launches++;
+        }
+        if (h_ctr[CTR_EMITTED] >= cols->n_columns) break;
+        if (iters > bound) { set_error("iteration loop did not drain the column queue"); result = RH15D_EDEVICE; break; }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     tm.mark(1, st);
     if (result == RH15D_OK) {
         e = hipStreamSynchronize(st);
@@ -1317,10 +1460,9 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
             }
         }
     }
-    (void)hipHostFree(h_counter);
+    (void)hipHostFree(h_ctr);
     if (own) (void)hipFree(own);
     return result;
 }
 
 }  // extern "C"
-
