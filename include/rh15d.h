@@ -116,6 +116,11 @@ typedef struct {
     int batch_columns;  /* columns resident at once; 0 = automatic */
     int profile;        /* 1: time the kernels with HIP events and count the
                            algorithmic work (see rh15d_last_stats) */
+    int sweep_mc;       /* angles carried by one lane of the formal-solution
+                           kernel: 1, 3 or 5 dividing n_mu; 0 = automatic */
+    int sweep_pack;     /* wavelengths per wavefront: 1 = one set of active
+                           transitions per wavefront, 2 = mixed sets;
+                           0 = automatic */
 } rh15d_options;
 
 /* Measurements of the calling thread's last rh15d_solve_columns made with
@@ -152,7 +157,7 @@ typedef struct {
 
 /* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, 200 iterations,
  * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, chunked,
- * no profiling. */
+ * no profiling, automatic sweep shape. */
 int rh15d_default_options(rh15d_options *opt);
 
 /* Device workspace needed by rh15d_solve_columns for these columns and

@@ -3,6 +3,7 @@
 // frequency weights, the Gauss-Legendre angles, and the ray groups that
 // the formal-solution kernel maps onto 64-lane wavefronts.
 #include <algorithm>
+#include <iterator>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -212,28 +213,38 @@ void gauss_legendre_01(int n, std::vector<double> &x, std::vector<double> &w) {
     }
 }
 
-// Rays of one direction are taken in order of wavelength, then angle, and
-// cut into groups of at most 64 that share one set of active transitions,
-// so every lane of a wavefront accumulates into the same rate keys.
-void build_group_tables(const rh15d_atom &a, int n_mu, HostGroupTables &out) {
+// Lanes of one direction are taken in order of wavelength (then angle chunk)
+// and cut into groups of at most 64.  With pack = 0 a group shares one set
+// of active transitions; with pack = 1 neighbouring wavelengths with
+// different sets share a group as long as their union has at most
+// kMaxSlots transitions (a lane contributes zero to a slot whose
+// transition is not active at its wavelength).
+void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGroupTables &out) {
     out = HostGroupTables{};
     gauss_legendre_01(n_mu, out.mu, out.wmu);
     const int T = static_cast<int>(a.tr.size());
     const int NL = static_cast<int>(a.lam.size());
+    const int mc = shape.mc;
+    const int chunks = n_mu / mc;
     std::vector<int> ray_off(T, -1);
     int cols = 0;
     for (int t = 0; t < a.n_lines; t++) {
+        // per line: quadrature rays (2 directions x n_mu angles x wavelengths),
+        // then the vertical emergent ray at each wavelength
         ray_off[t] = cols;
-        cols += 2 * static_cast<int>(a.tr[t].act.size()) * n_mu;
+        cols += (2 * n_mu + 1) * static_cast<int>(a.tr[t].act.size());
     }
     out.ray_cols = cols;
 
     std::vector<std::vector<int>> p_keys(T), q_keys(T);
     std::map<std::pair<int, int>, std::vector<int>> x_keys;
     int key = 0;
+    auto active_set = [&](int j) {
+        return std::vector<int>(a.jact_t.begin() + a.jact_off[j], a.jact_t.begin() + a.jact_off[j + 1]);
+    };
     for (int s = 0; s < 2; s++) {
-        std::vector<std::pair<int, int>> lanes;
-        std::vector<int> cur;
+        std::vector<std::pair<int, int>> lanes;  // (j, chunk)
+        std::vector<int> cur;                     // sorted union of the group's transitions
         auto flush = [&]() {
             if (lanes.empty()) return;
             if (static_cast<int>(cur.size()) > kMaxSlots) { out.overflow = true; lanes.clear(); return; }
@@ -260,56 +271,65 @@ void build_group_tables(const rh15d_atom &a, int n_mu, HostGroupTables &out) {
             }
             key += G.n_keys;
             out.groups.push_back(G);
-            out.lanes_used += static_cast<int>(lanes.size());
             for (int l = 0; l < kWave; l++) {
                 const bool real = l < static_cast<int>(lanes.size());
                 const int j = real ? lanes[l].first : lanes[0].first;
-                const int m = real ? lanes[l].second : lanes[0].second;
+                const int m0 = (real ? lanes[l].second : lanes[0].second) * mc;
                 const double nu = a.nu[j];
                 out.lane_j.push_back(j);
-                out.lane_m.push_back(m);
-                out.lane_nu.push_back(nu);
-                out.lane_mu.push_back(out.mu[m]);
+                out.lane_m0.push_back(m0);
                 out.lane_lamfac.push_back(a.lam[j] / kBgLambdaRef);
                 out.lane_hnu_k.push_back(kH * nu / kKB);
                 out.lane_2hnu3c2.push_back(2.0 * kH * nu * nu * nu / (kC * kC));
                 for (int q = 0; q < kMaxSlots; q++) {
-                    int pidx = -1;
-                    double W = 0, kap = 0, alpha = 0;
+                    int pb = -1;
+                    double wj = 0, kapj = 0, alpha = 0;
+                    // padding lanes repeat lane 0's ray with zero weights, so their
+                    // opacity stays finite and their contributions vanish
                     if (q < G.n_slots) {
                         const auto &tr = a.tr[cur[q]];
-                        const int ja = static_cast<int>(std::lower_bound(tr.act.begin(), tr.act.end(), j) - tr.act.begin());
-                        const int na = static_cast<int>(tr.act.size());
-                        W = real ? tr.w[ja] * 0.5 * out.wmu[m] : 0.0;
-                        if (tr.kind == 0) {
-                            pidx = ray_off[cur[q]] + (s * na + ja) * n_mu + m;
-                            kap = 4.0 * kPI * W / (kH * tr.nu0);
-                        } else {
-                            kap = 4.0 * kPI * W / (kH * nu);
-                            alpha = tr.alpha0 * std::pow(tr.nu0 / nu, 3.0);
+                        auto it = std::lower_bound(tr.act.begin(), tr.act.end(), j);
+                        if (it != tr.act.end() && *it == j) {
+                            const int ja = static_cast<int>(it - tr.act.begin());
+                            const int na = static_cast<int>(tr.act.size());
+                            wj = real ? tr.w[ja] : 0.0;
+                            if (tr.kind == 0) {
+                                pb = ray_off[cur[q]] + (s * na + ja) * n_mu + m0;
+                                kapj = 4.0 * kPI * wj * 0.5 / (kH * tr.nu0);
+                            } else {
+                                kapj = 4.0 * kPI * wj * 0.5 / (kH * nu);
+                                alpha = tr.alpha0 * std::pow(tr.nu0 / nu, 3.0);
+                            }
                         }
                     }
-                    out.phi_idx.push_back(pidx);
-                    out.W.push_back(W);
-                    out.kap.push_back(kap);
+                    out.pbase.push_back(pb);
+                    out.wj.push_back(wj);
+                    out.kapj.push_back(kapj);
                     out.alpha.push_back(alpha);
                 }
             }
+            out.lanes_used += static_cast<int>(lanes.size()) * mc;
             lanes.clear();
+            cur.clear();
         };
         for (int j = 0; j < NL; j++) {
-            std::vector<int> set(a.jact_t.begin() + a.jact_off[j], a.jact_t.begin() + a.jact_off[j + 1]);
+            const std::vector<int> set = active_set(j);
             if (set.empty()) continue;
-            for (int m = 0; m < n_mu; m++) {
-                if (set != cur || static_cast<int>(lanes.size()) == kWave) {
+            for (int ch = 0; ch < chunks; ch++) {
+                std::vector<int> uni;
+                std::set_union(cur.begin(), cur.end(), set.begin(), set.end(), std::back_inserter(uni));
+                const bool full = static_cast<int>(lanes.size()) == kWave;
+                const bool differs = shape.pack == 0 ? (!lanes.empty() && set != cur)
+                                                     : static_cast<int>(uni.size()) > kMaxSlots;
+                if (full || differs) {
                     flush();
-                    cur = set;
+                    uni = set;
                 }
-                lanes.push_back({j, m});
+                cur = uni;
+                lanes.push_back({j, ch});
             }
         }
         flush();
-        cur.clear();
     }
     out.n_keys = key;
     auto csr = [&](const std::vector<std::vector<int>> &lists, std::vector<int> &off, std::vector<int> &val) {

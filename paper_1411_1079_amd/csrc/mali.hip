@@ -95,61 +95,70 @@ __device__ __forceinline__ void sc_weights(R x, R &e, R &wa, R &wb) {
     }
 }
 
-// Voigt function H(a, v) = Re w(v + i a), Humlicek (1982) W4: a rational
-// approximation in four regions of s = |v| + a (relative accuracy ~1e-4).
-struct cplx { double r, i; };
-__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
-__device__ __forceinline__ cplx cadd(cplx a, double b) { return {a.r + b, a.i}; }
-__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
-    const double d = b.r * b.r + b.i * b.i;
+template <typename F>
+struct cplx_t { F r, i; };
+template <typename F>
+__device__ __forceinline__ cplx_t<F> cmul(cplx_t<F> a, cplx_t<F> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+template <typename F>
+__device__ __forceinline__ cplx_t<F> cadd(cplx_t<F> a, F b) { return {a.r + b, a.i}; }
+template <typename F>
+__device__ __forceinline__ cplx_t<F> cdiv(cplx_t<F> a, cplx_t<F> b) {
+    const F d = b.r * b.r + b.i * b.i;
     return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
 }
+__device__ __forceinline__ double d_cos(double x) { return cos(x); }
+__device__ __forceinline__ float d_cos(float x) { return __cosf(x); }
 
-__device__ __noinline__ double voigt_w4(double a, double v) {
-    const cplx t = {a, -v};          // t = a - i v
-    const double s = fabs(v) + a;
-    if (s >= 15.0) {
-        cplx den = cadd(cmul(t, t), 0.5);
-        return cdiv({0.5641896 * t.r, 0.5641896 * t.i}, den).r;
+// Voigt function H(a, v) = Re w(v + i a), Humlicek (1982) W4: a rational
+// approximation in four regions of s = |v| + a (relative accuracy ~1e-4),
+// evaluated in the precision F.
+template <typename F>
+__device__ __noinline__ F voigt_w4(F a, F v) {
+    using C = cplx_t<F>;
+    const C t = {a, -v};          // t = a - i v
+    const F s = fabs(v) + a;
+    if (s >= F(15.0)) {
+        C den = cadd(cmul(t, t), F(0.5));
+        return cdiv(C{F(0.5641896) * t.r, F(0.5641896) * t.i}, den).r;
     }
-    if (s >= 5.5) {
-        const cplx u = cmul(t, t);
-        const cplx num = cmul(t, cadd({0.5641896 * u.r, 0.5641896 * u.i}, 1.410474));
-        const cplx den = cadd(cmul(u, cadd(u, 3.0)), 0.75);
+    if (s >= F(5.5)) {
+        const C u = cmul(t, t);
+        const C num = cmul(t, cadd(C{F(0.5641896) * u.r, F(0.5641896) * u.i}, F(1.410474)));
+        const C den = cadd(cmul(u, cadd(u, F(3.0))), F(0.75));
         return cdiv(num, den).r;
     }
-    if (a >= 0.195 * fabs(v) - 0.176) {
-        cplx num = {0.5642236, 0.0};
-        num = cadd(cmul(num, t), 3.778987);
-        num = cadd(cmul(num, t), 11.96482);
-        num = cadd(cmul(num, t), 20.20933);
-        num = cadd(cmul(num, t), 16.4955);
-        cplx den = {1.0, 0.0};
-        den = cadd(cmul(den, t), 6.699398);
-        den = cadd(cmul(den, t), 21.69274);
-        den = cadd(cmul(den, t), 39.27121);
-        den = cadd(cmul(den, t), 38.82363);
-        den = cadd(cmul(den, t), 16.4955);
+    if (a >= F(0.195) * fabs(v) - F(0.176)) {
+        C num = {F(0.5642236), F(0)};
+        num = cadd(cmul(num, t), F(3.778987));
+        num = cadd(cmul(num, t), F(11.96482));
+        num = cadd(cmul(num, t), F(20.20933));
+        num = cadd(cmul(num, t), F(16.4955));
+        C den = {F(1), F(0)};
+        den = cadd(cmul(den, t), F(6.699398));
+        den = cadd(cmul(den, t), F(21.69274));
+        den = cadd(cmul(den, t), F(39.27121));
+        den = cadd(cmul(den, t), F(38.82363));
+        den = cadd(cmul(den, t), F(16.4955));
         return cdiv(num, den).r;
     }
-    const cplx u = cmul(t, t);
-    cplx p = {0.56419, 0.0};
-    p = cadd(cmul(p, u), -1.320522);
-    p = cadd(cmul(p, u), 35.76683);
-    p = cadd(cmul(p, u), -219.0313);
-    p = cadd(cmul(p, u), 1540.787);
-    p = cadd(cmul(p, u), -3321.9905);
-    p = cadd(cmul(p, u), 36183.31);
-    cplx q = {-1.0, 0.0};
-    q = cadd(cmul(q, u), 1.841439);
-    q = cadd(cmul(q, u), -61.57037);
-    q = cadd(cmul(q, u), 364.2191);
-    q = cadd(cmul(q, u), -2186.181);
-    q = cadd(cmul(q, u), 9022.228);
-    q = cadd(cmul(q, u), -24322.84);
-    q = cadd(cmul(q, u), 32066.6);
-    const cplx frac = cdiv(cmul(t, p), q);
-    return exp(u.r) * cos(u.i) - frac.r;
+    const C u = cmul(t, t);
+    C p = {F(0.56419), F(0)};
+    p = cadd(cmul(p, u), F(-1.320522));
+    p = cadd(cmul(p, u), F(35.76683));
+    p = cadd(cmul(p, u), F(-219.0313));
+    p = cadd(cmul(p, u), F(1540.787));
+    p = cadd(cmul(p, u), F(-3321.9905));
+    p = cadd(cmul(p, u), F(36183.31));
+    C q = {F(-1), F(0)};
+    q = cadd(cmul(q, u), F(1.841439));
+    q = cadd(cmul(q, u), F(-61.57037));
+    q = cadd(cmul(q, u), F(364.2191));
+    q = cadd(cmul(q, u), F(-2186.181));
+    q = cadd(cmul(q, u), F(9022.228));
+    q = cadd(cmul(q, u), F(-24322.84));
+    q = cadd(cmul(q, u), F(32066.6));
+    const C frac = cdiv(cmul(t, p), q);
+    return d_exp(u.r) * d_cos(u.i) - frac.r;
 }
 
 template <typename R>
@@ -290,31 +299,44 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const DevTransition &tr = A.tr[t];
     const double T = a.T[g], vt = a.vt[g], vz = a.vz[g];
     const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * T / A.mass + vt * vt);
-    const double adamp = tr.gamma / (4.0 * kPI * dnd);
-    const double pre = 1.0 / (sqrt(kPI) * dnd);
-    const int na = tr.n_act, nmu = A.n_mu, nr = 2 * na * nmu;
-    double ph[kPer];
+    const R adamp = static_cast<R>(tr.gamma / (4.0 * kPI * dnd));
+    const double rdnd = 1.0 / dnd;
+    const double pre = rdnd / sqrt(kPI);
+    const int na = tr.n_act, nmu = A.n_mu, nq = 2 * na * nmu, nr = nq + na;
+    R ph[kPer];
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
         const int r = lane + kWave * i;
-        ph[i] = 0.0;
+        ph[i] = R(0);
         if (r < nr) {
-            const int s = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+            // quadrature rays r < nq: (direction, wavelength, angle); then the
+            // vertical emergent ray of each wavelength (mu = 1, upward)
+            int ja, m = 0;
+            double mus;
+            if (r < nq) {
+                const int s = r / (na * nmu), rem = r % (na * nmu);
+                ja = rem / nmu;
+                m = rem % nmu;
+                mus = s ? A.mu[m] : -A.mu[m];
+            } else {
+                ja = r - nq;
+                mus = 1.0;
+            }
             const int j = A.act_j[tr.act_off + ja];
-            const double mus = s ? A.mu[m] : -A.mu[m];
-            const double v = (A.nu[j] - tr.nu0 * (1.0 + mus * vz / kC)) / dnd;
-            const double H = tr.voigt ? voigt_w4(adamp, v) : exp(-v * v);
-            ph[i] = H * pre;
-            acc += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * ph[i];
+            const double v = (A.nu[j] - tr.nu0 * (1.0 + mus * vz / kC)) * rdnd;
+            const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
+            ph[i] = H * static_cast<R>(pre);
+            if (r < nq) acc += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * static_cast<double>(ph[i]);
         }
     }
     const double tot = wave_sum(acc);
+    const R rtot = static_cast<R>(1.0 / tot);
     R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
 #pragma unroll
     for (int i = 0; i < kPer; i++) {
         const int r = lane + kWave * i;
-        if (r < nr) phi[r] = static_cast<R>(ph[i] / tot);
+        if (r < nr) phi[r] = sizeof(R) == 8 ? static_cast<R>(ph[i] / tot) : ph[i] * rtot;
     }
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
 }
@@ -371,78 +393,101 @@ __device__ __forceinline__ const R *pops_row(const RunArgs &a, int64_t g, int64_
     else return a.popsf + gc * a.A.L;
 }
 
-template <typename R, int NS>
-struct Point {
-    R chi, rchi, S, etabg, B;
-    R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
-};
-
 // Uniform (per wavefront) description of the transitions a group touches.
 template <typename R, int NS>
 struct Slots {
     int kind[NS], l[NS], u[NS], c[NS];
-    R cblu[NS], cbul[NS], ca[NS];
+    R cblu[NS], cbul[NS], ca[NS], wsum[NS];
 };
 
-// Opacity, emissivity and source function of a lane's ray at depth point k.
+// Angle-independent terms of a lane's wavelength at one depth point:
+// Planck function, background, continua (not Doppler shifted), populations.
 template <typename R, int NS>
-__device__ __forceinline__ void eval_point(const RunArgs &a, const Slots<R, NS> &sl, int64_t g, int64_t gc,
-                                           const int *pidx, const R *alpha, R hnu_k, R two_hnu3, R lamfac,
-                                           Point<R, NS> &p) {
-    const DevAtom &A = a.A;
+struct Shared {
+    R B, etabg, chi0, eta0;
+    R nl[NS], nu[NS];
+    R cvlu[NS], cvul[NS], cU[NS], ccht[NS];
+};
+
+template <typename R, int NS>
+__device__ __forceinline__ void shared_terms(const RunArgs &a, const Slots<R, NS> &sl, const R *alpha, int64_t g,
+                                             int64_t gc, R hnu_k, R two_hnu3, R lamfac, Shared<R, NS> &sh) {
     const R *rec = reinterpret_cast<const R *>(a.rec) + gc * a.rec_w;
     const R *n = pops_row<R>(a, g, gc);
     const R x = hnu_k * rec[1];
     const R ex = d_exp(-x);  // exp(-h nu / k T)
     const R omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
-    p.B = two_hnu3 * ex * rcp(omx);
+    sh.B = two_hnu3 * ex * rcp(omx);
     const R chibg = rec[2] * lamfac;
-    p.etabg = chibg * p.B;
-    R chi = chibg, eta = p.etabg;
+    sh.etabg = chibg * sh.B;
+    R chi = chibg, eta = sh.etabg;
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        const R nl = n[sl.l[q]], nu = n[sl.u[q]];
+        sh.nl[q] = n[sl.l[q]];
+        sh.nu[q] = n[sl.u[q]];
+        if (sl.kind[q] == 1) {
+            const R gf = rec[kRecHead + sl.c[q]] * ex;
+            sh.cvlu[q] = alpha[q];
+            sh.cvul[q] = gf * alpha[q];
+            sh.cU[q] = two_hnu3 * sh.cvul[q];
+            sh.ccht[q] = sh.nl[q] * sh.cvlu[q] - sh.nu[q] * sh.cvul[q];
+            chi += sh.ccht[q];
+            eta += sh.nu[q] * sh.cU[q];
+        }
+    }
+    sh.chi0 = chi;
+    sh.eta0 = eta;
+}
+
+// Terms of one ray (angle r of the lane) at one depth point.
+template <typename R, int NS>
+struct RayPt {
+    R chi, rchi, S;
+    R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
+};
+
+template <typename R, int NS>
+__device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R, NS> &sh, const R *phirow,
+                                          const int *pb, int r, RayPt<R, NS> &p) {
+    R chi = sh.chi0, eta = sh.eta0;
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
         if (sl.kind[q] == 0) {
-            const R ph = reinterpret_cast<const R *>(a.phi)[gc * A.ray_cols + pidx[q]];
+            const R ph = pb[q] >= 0 ? phirow[pb[q] + r] : R(0);
             p.ph[q] = ph;
             p.vlu[q] = sl.cblu[q] * ph;
             p.vul[q] = sl.cbul[q] * ph;
             p.U[q] = sl.ca[q] * ph;
+            p.cht[q] = sh.nl[q] * p.vlu[q] - sh.nu[q] * p.vul[q];
+            chi += p.cht[q];
+            eta += sh.nu[q] * p.U[q];
         } else {
-            const R gf = rec[kRecHead + sl.c[q]] * ex;
             p.ph[q] = R(1);
-            p.vlu[q] = alpha[q];
-            p.vul[q] = gf * alpha[q];
-            p.U[q] = two_hnu3 * p.vul[q];
+            p.vlu[q] = sh.cvlu[q];
+            p.vul[q] = sh.cvul[q];
+            p.U[q] = sh.cU[q];
+            p.cht[q] = sh.ccht[q];
         }
-        p.cht[q] = nl * p.vlu[q] - nu * p.vul[q];
-        chi += p.cht[q];
-        eta += nu * p.U[q];
     }
     p.chi = chi;
     p.rchi = rcp(chi);
     p.S = eta * p.rchi;
 }
 
-// Rate contributions of one depth point, summed over the wavefront's rays.
+template <int NS, int MODE>
+constexpr int n_acc() { return MODE == MODE_PSI ? NS : 2 * NS + NS * (NS - 1); }
+
+// Adds one ray's contributions (angle weight wmu) into the lane's sums.
 template <typename R, int NS, int MODE>
-__device__ __forceinline__ void accumulate(const Point<R, NS> &p, const R *kap, const R *om, R Ieff, R psi,
-                                           R *out, int N, int k, int lane) {
+__device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi, R wmu, R Ieff, R psi, R *acc) {
     if constexpr (MODE == MODE_PSI) {
 #pragma unroll
-        for (int q = 0; q < NS; q++) {
-            const R v = wave_total(om[q] * p.ph[q] * psi);
-            if (lane == kWave - 1) out[(size_t)q * N + k] = v;
-        }
+        for (int q = 0; q < NS; q++) acc[q] += wpsi[q] * wmu * p.ph[q] * psi;
     } else {
 #pragma unroll
         for (int q = 0; q < NS; q++) {
-            const R cp = wave_total(kap[q] * p.vlu[q] * Ieff);
-            const R cq = wave_total(kap[q] * (p.U[q] * (R(1) - p.cht[q] * psi) + p.vul[q] * Ieff));
-            if (lane == kWave - 1) {
-                out[(size_t)q * N + k] = cp;
-                out[(size_t)(NS + q) * N + k] = cq;
-            }
+            acc[q] += wmu * p.vlu[q] * Ieff;
+            acc[NS + q] += wmu * (p.U[q] * (R(1) - p.cht[q] * psi) + p.vul[q] * Ieff);
         }
 #pragma unroll
         for (int q = 0; q < NS; q++) {
@@ -450,17 +495,34 @@ __device__ __forceinline__ void accumulate(const Point<R, NS> &p, const R *kap, 
             for (int q2 = 0; q2 < NS; q2++) {
                 if (q2 == q) continue;
                 const int rank = q * (NS - 1) + (q2 < q ? q2 : q2 - 1);
-                const R cx = wave_total(kap[q] * p.cht[q] * psi * p.U[q2]);
-                if (lane == kWave - 1) out[(size_t)(2 * NS + rank) * N + k] = cx;
+                acc[2 * NS + rank] += wmu * p.cht[q] * psi * p.U[q2];
             }
         }
     }
 }
 
-// One wavefront: 64 rays of one direction through one column.  Down rays
-// start at the top with no incoming radiation; up rays start at the bottom
-// with the diffusion approximation I = B + mu dB/dtau.
-template <typename R, int MODE, int NS>
+// Sums the lanes' contributions of one depth point over the wavefront and
+// stores them (lane 63 holds the totals).
+template <typename R, int NS, int MODE>
+__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int N, int k, int lane) {
+    constexpr int NK = n_acc<NS, MODE>();
+#pragma unroll
+    for (int i = 0; i < NK; i++) {
+        R v = acc[i];
+        if constexpr (MODE == MODE_RATES) {
+            const int q = i < 2 * NS ? (i % NS) : (i - 2 * NS) / (NS > 1 ? NS - 1 : 1);
+            v *= kapj[q];
+        }
+        v = wave_total(v);
+        if (lane == kWave - 1) out[(size_t)i * N + k] = v;
+    }
+}
+
+// One wavefront: 64 lanes, each one wavelength and MC angles of one
+// direction, through one column.  Down rays start at the top with no
+// incoming radiation; up rays start at the bottom with the diffusion
+// approximation I = B + mu dB/dtau.
+template <typename R, int MODE, int NS, int MC>
 __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane) {
     const DevAtom &A = a.A;
     const ColGeom cg = geom(a, slot);
@@ -481,63 +543,103 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         sl.cblu[q] = static_cast<R>(tr.hnu4pi * tr.Blu);
         sl.cbul[q] = static_cast<R>(tr.hnu4pi * tr.Bul);
         sl.ca[q] = static_cast<R>(tr.hnu4pi * tr.A);
+        sl.wsum[q] = static_cast<R>(tr.wsum);
     }
     const int li = grp * kWave + lane;
-    const R mu = static_cast<R>(A.lanes.mu[li]);
-    const R invmu = R(1) / mu;
+    const int m0 = A.lanes.m0[li];
     const R lamfac = static_cast<R>(A.lanes.lamfac[li]);
     const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
     const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
-    int pidx[NS];
-    R kap[NS], alpha[NS], om[NS];
+    int pb[NS];
+    R kapj[NS], alpha[NS], wpsi[NS];
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        pidx[q] = A.lanes.phi_idx[li * kMaxSlots + q];
-        kap[q] = static_cast<R>(A.lanes.kap[li * kMaxSlots + q]);
+        pb[q] = A.lanes.pbase[li * kMaxSlots + q];
+        kapj[q] = static_cast<R>(A.lanes.kapj[li * kMaxSlots + q]);
         alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
-        const double W = A.lanes.W[li * kMaxSlots + q];
-        om[q] = static_cast<R>(sl.kind[q] == 1 ? W / A.tr[G.t[q]].wsum : W);
+        const R wj = static_cast<R>(A.lanes.wj[li * kMaxSlots + q]);
+        // Psi* weights: W phi~ for lines, W / sum W for continua (W = w_nu w_mu / 2)
+        wpsi[q] = sl.kind[q] == 1 ? R(0.5) * wj / sl.wsum[q] : R(0.5) * wj;
+    }
+    R mu[MC], invmu[MC], wmu[MC];
+#pragma unroll
+    for (int r = 0; r < MC; r++) {
+        mu[r] = static_cast<R>(A.mu[m0 + r]);
+        invmu[r] = R(1) / mu[r];
+        wmu[r] = static_cast<R>(A.wmu[m0 + r]);
     }
     R *out = reinterpret_cast<R *>(a.part) + gc0 * A.n_keys + (size_t)key_off * N;
     const R *rec = reinterpret_cast<const R *>(a.rec);
+    const R *phi = reinterpret_cast<const R *>(a.phi);
+    constexpr int NK = n_acc<NS, MODE>();
     const int step = s_dir == 0 ? 1 : -1;
     int k = s_dir == 0 ? 0 : N - 1;
-    Point<R, NS> p;
-    eval_point<R, NS>(a, sl, g0 + k, gc0 + k, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
-    R I;
-    if (s_dir == 0) {
-        I = R(0);
-    } else {
-        Point<R, NS> p2;
-        eval_point<R, NS>(a, sl, g0 + N - 2, gc0 + N - 2, pidx, alpha, hnu_k, two_hnu3, lamfac, p2);
-        const R dtv = R(0.5) * (p.chi + p2.chi) * rec[(gc0 + N - 1) * a.rec_w];
-        I = dtv > R(0) ? p.B + mu * (p.B - p2.B) * rcp(dtv) : p.B;
+    R I[MC], chi_p[MC], S_p[MC];
+    R acc[NK];
+#pragma unroll
+    for (int i = 0; i < NK; i++) acc[i] = R(0);
+    {
+        Shared<R, NS> sh;
+        shared_terms<R, NS>(a, sl, alpha, g0 + k, gc0 + k, hnu_k, two_hnu3, lamfac, sh);
+        Shared<R, NS> sh2;
+        R dzb = R(0);
+        if (s_dir != 0) {
+            shared_terms<R, NS>(a, sl, alpha, g0 + N - 2, gc0 + N - 2, hnu_k, two_hnu3, lamfac, sh2);
+            dzb = rec[(gc0 + N - 1) * a.rec_w];
+        }
+#pragma unroll
+        for (int r = 0; r < MC; r++) {
+            RayPt<R, NS> p;
+            ray_terms<R, NS>(sl, sh, phi + (gc0 + k) * A.ray_cols, pb, r, p);
+            R I0 = R(0);
+            if (s_dir != 0) {
+                RayPt<R, NS> p2;
+                ray_terms<R, NS>(sl, sh2, phi + (gc0 + N - 2) * A.ray_cols, pb, r, p2);
+                const R dtv = R(0.5) * (p.chi + p2.chi) * dzb;
+                I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
+            }
+            contribute<R, NS, MODE>(p, wpsi, wmu[r], I0, R(0), acc);
+            I[r] = I0;
+            chi_p[r] = p.chi;
+            S_p[r] = p.S;
+        }
+        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
     }
-    accumulate<R, NS, MODE>(p, kap, om, I, R(0), out, N, k, lane);
-    R chi_p = p.chi, S_p = p.S;
     for (int i = 1; i < N; i++) {
         const int kp = k;
         k += step;
-        eval_point<R, NS>(a, sl, g0 + k, gc0 + k, pidx, alpha, hnu_k, two_hnu3, lamfac, p);
+        Shared<R, NS> sh;
+        shared_terms<R, NS>(a, sl, alpha, g0 + k, gc0 + k, hnu_k, two_hnu3, lamfac, sh);
         const R dz = rec[(gc0 + (step > 0 ? k : kp)) * a.rec_w];
-        const R x = R(0.5) * (chi_p + p.chi) * dz * invmu;
-        R e, wa, wb;
-        sc_weights<R>(x, e, wa, wb);
-        const R up = I * e + wa * S_p;
-        const R Ieff = up + wb * p.etabg * p.rchi;
-        const R psi = wb * p.rchi;
-        I = up + wb * p.S;
-        accumulate<R, NS, MODE>(p, kap, om, Ieff, psi, out, N, k, lane);
-        chi_p = p.chi;
-        S_p = p.S;
+        const R *phirow = phi + (gc0 + k) * A.ray_cols;
+#pragma unroll
+        for (int j = 0; j < NK; j++) acc[j] = R(0);
+#pragma unroll
+        for (int r = 0; r < MC; r++) {
+            RayPt<R, NS> p;
+            ray_terms<R, NS>(sl, sh, phirow, pb, r, p);
+            const R x = R(0.5) * (chi_p[r] + p.chi) * dz * invmu[r];
+            R e, wa, wb;
+            sc_weights<R>(x, e, wa, wb);
+            const R up = I[r] * e + wa * S_p[r];
+            const R Ieff = up + wb * sh.etabg * p.rchi;
+            const R psi = wb * p.rchi;
+            I[r] = up + wb * p.S;
+            contribute<R, NS, MODE>(p, wpsi, wmu[r], Ieff, psi, acc);
+            chi_p[r] = p.chi;
+            S_p[r] = p.S;
+        }
+        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
     }
 }
 
-template <typename R, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(RunArgs a) {
-    const int grp = rfl(blockIdx.x * 4 + (threadIdx.x >> 6));
+// Groups are ordered by their number of slots; one launch per slot count
+// covers the range [g_begin, g_end) so each variant gets its own registers.
+template <typename R, int MODE, int NS, int MC>
+__global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end) {
+    const int grp = rfl(g_begin + blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    if (grp >= a.A.n_groups) return;
+    if (grp >= g_end) return;
     int slot;
     if (MODE == MODE_RATES) {
         slot = blockIdx.y;
@@ -546,12 +648,7 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a) {
         if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
         slot = rfl(a.retire_list[blockIdx.y]);
     }
-    switch (rfl(a.A.groups[grp].n_slots)) {
-        case 1: sweep_group<R, MODE, 1>(a, grp, slot, lane); break;
-        case 2: sweep_group<R, MODE, 2>(a, grp, slot, lane); break;
-        case 3: sweep_group<R, MODE, 3>(a, grp, slot, lane); break;
-        default: sweep_group<R, MODE, 4>(a, grp, slot, lane); break;
-    }
+    sweep_group<R, MODE, NS, MC>(a, grp, slot, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -825,28 +922,27 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
 // ---------------------------------------------------------------------------
 // output of finished columns: vertical emergent intensity and Psi*
 // ---------------------------------------------------------------------------
-__device__ void point_opacity_mu1(const RunArgs &a, int j, int64_t gc, int64_t g, double &chi, double &S,
-                                  double &B) {
+// Opacity and source function of the vertical (mu = 1, upward) ray at
+// wavelength j, depth point k; line profiles come from the prepared table.
+template <typename R>
+__device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, int j, int64_t gc, int64_t g, double &chi,
+                                                  double &S, double &B) {
     const DevAtom &A = a.A;
     const int L = A.L;
     const double nu = A.nu[j];
-    const double T = a.T[g];
-    const double x = kH * nu / (kKB * T);
+    const double x = kH * nu / kKB * static_cast<double>(reinterpret_cast<const R *>(a.rec)[gc * a.rec_w + 1]);
     const double ex = exp(-x), omx = x > 0.5 ? 1.0 - ex : -expm1(-x);
     const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
     B = two_hnu3 * ex / omx;
     double c = a.kbg[gc] * (A.lam[j] / kBgLambdaRef);
     double e = c * B;
-    const double w = sqrt(2.0 * kKB * T / A.mass + a.vt[g] * a.vt[g]);
+    const R *phirow = reinterpret_cast<const R *>(a.phi) + gc * A.ray_cols;
     for (int i = A.jact_off[j]; i < A.jact_off[j + 1]; i++) {
         const int t = A.jact_t[i];
         const DevTransition &tr = A.tr[t];
         double vlu, vul, U;
         if (tr.kind == 0) {
-            const double dnd = tr.nu0 / kC * w;
-            const double v = (nu - tr.nu0 * (1.0 + a.vz[g] / kC)) / dnd;
-            const double H = tr.voigt ? voigt_w4(tr.gamma / (4.0 * kPI * dnd), v) : exp(-v * v);
-            const double ph = H / (sqrt(kPI) * dnd) / a.norm[gc * A.n_lines + t];
+            const double ph = static_cast<double>(phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]]);
             vlu = tr.hnu4pi * tr.Blu * ph; vul = tr.hnu4pi * tr.Bul * ph; U = tr.hnu4pi * tr.A * ph;
         } else {
             const double alpha = tr.alpha0 * pow(tr.nu0 / nu, 3.0);
@@ -860,6 +956,7 @@ __device__ void point_opacity_mu1(const RunArgs &a, int j, int64_t gc, int64_t g
     S = e / c;
 }
 
+template <typename R>
 __global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
@@ -869,13 +966,13 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
         double chi2, S2, B2, chi, S, B;
-        point_opacity_mu1(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
-        point_opacity_mu1(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
+        point_opacity_mu1<R>(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
+        point_opacity_mu1<R>(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
         const double dtv = 0.5 * (chi + chi2) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
         double I = dtv > 0.0 ? B + (B - B2) / dtv : B;
         double chi_p = chi, S_p = S;
         for (int k = N - 2; k >= 0; k--) {
-            point_opacity_mu1(a, j, gc0 + k, g0 + k, chi, S, B);
+            point_opacity_mu1<R>(a, j, gc0 + k, g0 + k, chi, S, B);
             const double x = 0.5 * (chi_p + chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
             double e, wa, wb;
             sc_weights<double>(x, e, wa, wb);
@@ -1019,20 +1116,46 @@ int upload(rh15d_atom *atom, const std::vector<T> &v, T **out) {
     return RH15D_OK;
 }
 
-int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
+int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
+    if (shape.mc != 1 && shape.mc != 3 && shape.mc != 5) { set_error("angles per lane must be 1, 3 or 5"); return RH15D_EINVAL; }
+    if (n_mu % shape.mc != 0) { set_error("angles per lane must divide n_mu"); return RH15D_EINVAL; }
     std::lock_guard<std::mutex> lock(atom->mu_);
-    auto key = std::make_pair(dev, n_mu);
+    auto key = std::make_pair(std::make_pair(dev, n_mu), shape);
     auto it = atom->dev.find(key);
     if (it != atom->dev.end()) { *out = &it->second; return RH15D_OK; }
     HostGroupTables H;
-    build_group_tables(*atom, n_mu, H);
+    build_group_tables(*atom, n_mu, shape, H);
     if (H.overflow) { set_error("a wavelength has more than %d active transitions", kMaxSlots); return RH15D_EINVAL; }
+    // order the groups by slot count (stable), permuting the lane tables alike
+    const int NG = static_cast<int>(H.groups.size());
+    std::vector<int> order(NG);
+    for (int i = 0; i < NG; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return H.groups[x].n_slots < H.groups[y].n_slots; });
+    auto permute = [&](auto &v, int per_group) {
+        auto w = v;
+        for (int i = 0; i < NG; i++)
+            std::copy(v.begin() + (size_t)order[i] * per_group, v.begin() + (size_t)(order[i] + 1) * per_group,
+                      w.begin() + (size_t)i * per_group);
+        v.swap(w);
+    };
+    permute(H.groups, 1);
+    permute(H.lane_j, kWave); permute(H.lane_m0, kWave); permute(H.lane_lamfac, kWave);
+    permute(H.lane_hnu_k, kWave); permute(H.lane_2hnu3c2, kWave);
+    permute(H.pbase, kWave * kMaxSlots); permute(H.wj, kWave * kMaxSlots);
+    permute(H.kapj, kWave * kMaxSlots); permute(H.alpha, kWave * kMaxSlots);
     DevAtom D{};
     D.L = atom->L; D.n_lines = atom->n_lines; D.n_cont = atom->n_cont;
     D.T = static_cast<int>(atom->tr.size()); D.NL = static_cast<int>(atom->lam.size()); D.n_mu = n_mu;
-    D.n_groups = static_cast<int>(H.groups.size()); D.n_keys = H.n_keys; D.ray_cols = H.ray_cols;
+    D.n_groups = NG; D.n_keys = H.n_keys; D.ray_cols = H.ray_cols;
+    D.mc = shape.mc; D.pack = shape.pack;
+    for (int n = 0; n <= kMaxSlots + 1; n++) {
+        int c = 0;
+        while (c < NG && H.groups[c].n_slots < n) c++;
+        D.g_begin[n] = c;
+    }
     D.mass = atom->mass; D.abund = atom->abund; D.c_bg = atom->c_bg; D.bg_kind = atom->bg_kind;
     std::vector<DevTransition> tr(D.T);
     std::vector<int> act_j;
@@ -1044,7 +1167,9 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
         d.kind = h.kind; d.l = h.l; d.u = h.u; d.voigt = h.voigt; d.coll_kind = h.coll_kind;
         d.n_act = static_cast<int>(h.act.size()); d.act_off = static_cast<int>(act_j.size());
         d.ray_off = h.kind == 0 ? ray_off : -1;
-        if (h.kind == 0) ray_off += 2 * d.n_act * n_mu;
+        // quadrature rays (2 directions x n_mu angles x n_act wavelengths),
+        // then the vertical emergent ray (mu = 1, upward) at each wavelength
+        if (h.kind == 0) ray_off += (2 * n_mu + 1) * d.n_act;
         d.nu0 = h.nu0; d.A = h.A; d.Bul = h.Bul; d.Blu = h.Blu; d.alpha0 = h.alpha0; d.coll_val = h.coll_val;
         d.gamma = h.gamma; d.hnu4pi = kH * h.nu0 / (4.0 * kPI);
         d.wsum = 0.0;
@@ -1055,8 +1180,8 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
     }
     if (ray_off != H.ray_cols) { set_error("internal: ray table mismatch"); return RH15D_EINVAL; }
     for (const auto &d : tr)
-        if (d.kind == 0 && 2 * d.n_act * n_mu > kMaxLineRays) {
-            set_error("a line has %d rays per depth (limit %d)", 2 * d.n_act * n_mu, kMaxLineRays);
+        if (d.kind == 0 && (2 * n_mu + 1) * d.n_act > kMaxLineRays) {
+            set_error("a line has %d rays per depth (limit %d)", (2 * n_mu + 1) * d.n_act, kMaxLineRays);
             return RH15D_EINVAL;
         }
     int rc = RH15D_OK;
@@ -1067,12 +1192,17 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
     std::vector<double> lam(atom->lam), nu(atom->nu);
     UP(lam, &D.lam); UP(nu, &D.nu); UP(act_j, &D.act_j); UP(act_w, &D.act_w);
     UP(H.mu, &D.mu); UP(H.wmu, &D.wmu);
-    std::vector<int> jo(atom->jact_off), jt(atom->jact_t);
-    UP(jo, &D.jact_off); UP(jt, &D.jact_t);
+    std::vector<int> jo(atom->jact_off), jt(atom->jact_t), jja(atom->jact_t.size());
+    for (int j = 0; j < D.NL; j++)
+        for (int i = jo[j]; i < jo[j + 1]; i++) {
+            const auto &act = atom->tr[jt[i]].act;
+            jja[i] = static_cast<int>(std::lower_bound(act.begin(), act.end(), j) - act.begin());
+        }
+    UP(jo, &D.jact_off); UP(jt, &D.jact_t); UP(jja, &D.jact_ja);
     UP(H.groups, &D.groups);
-    UP(H.lane_j, &D.lanes.j); UP(H.lane_m, &D.lanes.m); UP(H.lane_nu, &D.lanes.nu); UP(H.lane_mu, &D.lanes.mu);
+    UP(H.lane_j, &D.lanes.j); UP(H.lane_m0, &D.lanes.m0);
     UP(H.lane_lamfac, &D.lanes.lamfac); UP(H.lane_hnu_k, &D.lanes.hnu_k); UP(H.lane_2hnu3c2, &D.lanes.two_hnu3c2);
-    UP(H.phi_idx, &D.lanes.phi_idx); UP(H.W, &D.lanes.W); UP(H.kap, &D.lanes.kap); UP(H.alpha, &D.lanes.alpha);
+    UP(H.pbase, &D.lanes.pbase); UP(H.wj, &D.lanes.wj); UP(H.kapj, &D.lanes.kapj); UP(H.alpha, &D.lanes.alpha);
     UP(H.p_off, &D.p_off); UP(H.p_key, &D.p_key); UP(H.q_off, &D.q_off); UP(H.q_key, &D.q_key);
     D.n_xpairs = static_cast<int>(H.x_t.size());
     UP(H.x_t, &D.x_t); UP(H.x_t2, &D.x_t2); UP(H.x_off, &D.x_off); UP(H.x_key, &D.x_key);
@@ -1080,15 +1210,34 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, DevAtom **out) {
     for (const auto &G : H.groups) {
         // per ray-step: background and Planck 7, formal step 19, source 1;
         // per transition 9 (opacity) + 8 (rates) + 2 (reductions);
-        // per cross pair 3 + 1
-        D.rays_per_depth += G.n_lanes;
-        D.flops_per_depth += (double)G.n_lanes * (27.0 + 19.0 * G.n_slots + 4.0 * G.n_pairs);
-        D.reads_per_depth += (double)G.n_lanes * G.n_line_slots;
+        // per cross pair 3 + 1 (counted for the rays that carry the slot)
+        const double rays = (double)G.n_lanes * shape.mc;
+        D.rays_per_depth += rays;
+        D.flops_per_depth += rays * (27.0 + 19.0 * G.n_slots + 4.0 * G.n_pairs);
+        D.reads_per_depth += rays * G.n_line_slots;
         D.keys_per_depth += G.n_keys;
     }
     auto res = atom->dev.emplace(key, D);
     *out = &res.first->second;
     return RH15D_OK;
+}
+
+// The sweep shape of a solve: the caller's, else the autotuned one for this
+// device, angle count and precision, else one angle per lane with mixed packing
+// (the fastest shape measured for the six-level atom on MI355X).
+SweepShape pick_shape(rh15d_atom *atom, const rh15d_options *o) {
+    SweepShape sh;
+    sh.mc = o->sweep_mc > 0 ? o->sweep_mc : 1;
+    sh.pack = o->sweep_pack > 0 ? o->sweep_pack - 1 : 1;
+    if (o->sweep_mc <= 0 && o->sweep_pack <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            std::lock_guard<std::mutex> lock(atom->mu_);
+            auto it = atom->tuned.find({{dev, o->n_mu}, o->precision});
+            if (it != atom->tuned.end()) sh = it->second;
+        }
+    }
+    return sh;
 }
 
 struct Layout {
@@ -1135,6 +1284,11 @@ int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_opti
     if (o->start < 0 || o->start > 2) { set_error("unknown start"); return RH15D_EINVAL; }
     if (o->scheduler != RH15D_SCHED_CHUNKED && o->scheduler != RH15D_SCHED_SLOTS) { set_error("unknown scheduler"); return RH15D_EINVAL; }
     if (o->batch_columns < 0) { set_error("batch_columns must be >= 0"); return RH15D_EINVAL; }
+    if (o->sweep_mc < 0 || (o->sweep_mc > 0 && o->n_mu % o->sweep_mc != 0) ||
+        (o->sweep_mc > 0 && o->sweep_mc != 1 && o->sweep_mc != 3 && o->sweep_mc != 5)) {
+        set_error("sweep_mc must be 0 (automatic) or 1, 3, 5 dividing n_mu"); return RH15D_EINVAL;
+    }
+    if (o->sweep_pack < 0 || o->sweep_pack > 2) { set_error("sweep_pack must be 0, 1 or 2"); return RH15D_EINVAL; }
     if (o->start == RH15D_START_PROVIDED && !cols->init_pops) { set_error("start=PROVIDED needs init_pops"); return RH15D_EINVAL; }
     if (!(o->tol >= 0.0)) { set_error("tol must be >= 0"); return RH15D_EINVAL; }
     if (cols->depth_offset && cols->depth_offset[0] != 0) { set_error("depth_offset[0] must be 0"); return RH15D_EINVAL; }
@@ -1192,11 +1346,34 @@ void launch_se(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
     }
 }
 
+template <typename R, int MODE, int NS, int MC>
+void launch_sweep_range(const RunArgs &a, hipStream_t st) {
+    const int gb = a.A.g_begin[NS], ge = a.A.g_begin[NS + 1];
+    if (ge <= gb) return;
+    hipLaunchKernelGGL((k_sweep<R, MODE, NS, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge);
+}
+
+template <typename R, int MODE, int MC>
+void launch_sweep_mc(const RunArgs &a, hipStream_t st) {
+    launch_sweep_range<R, MODE, 1, MC>(a, st);
+    launch_sweep_range<R, MODE, 2, MC>(a, st);
+    launch_sweep_range<R, MODE, 3, MC>(a, st);
+    launch_sweep_range<R, MODE, 4, MC>(a, st);
+}
+
+template <typename R, int MODE>
+void launch_sweep(const RunArgs &a, hipStream_t st) {
+    switch (a.A.mc) {
+        case 5: launch_sweep_mc<R, MODE, 5>(a, st); break;
+        case 3: launch_sweep_mc<R, MODE, 3>(a, st); break;
+        default: launch_sweep_mc<R, MODE, 1>(a, st); break;
+    }
+}
+
 struct Launcher {
     RunArgs a;
     bool fp32, zero_start, want_spec, want_psi;
     hipStream_t st;
-    dim3 sweep_grid;
 
     void refill_phase(Timer *tm) {
         hipLaunchKernelGGL(k_refill, dim3(1), dim3(kRefillThreads), 0, st, a);
@@ -1215,18 +1392,21 @@ struct Launcher {
 
     void iteration(Timer *tm) {
         if (tm) tm->mark(2, st);
-        if (fp32) hipLaunchKernelGGL((k_sweep<float, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_sweep<double, MODE_RATES>), sweep_grid, dim3(256), 0, st, a);
+        if (fp32) launch_sweep<float, MODE_RATES>(a, st);
+        else launch_sweep<double, MODE_RATES>(a, st);
         if (tm) tm->mark(3, st);
         launch_se(a, fp32, false, st);
         if (tm) tm->mark(4, st);
         hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
         if (tm) tm->mark(5, st);
-        if (want_spec)
-            hipLaunchKernelGGL(k_emergent, dim3(grid_for((int64_t)a.S * a.A.NL, 256, 8192)), dim3(256), 0, st, a);
+        if (want_spec) {
+            const unsigned eb = grid_for((int64_t)a.S * a.A.NL, 256, 8192);
+            if (fp32) hipLaunchKernelGGL(k_emergent<float>, dim3(eb), dim3(256), 0, st, a);
+            else hipLaunchKernelGGL(k_emergent<double>, dim3(eb), dim3(256), 0, st, a);
+        }
         if (want_psi) {
-            if (fp32) hipLaunchKernelGGL((k_sweep<float, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
-            else hipLaunchKernelGGL((k_sweep<double, MODE_PSI>), sweep_grid, dim3(256), 0, st, a);
+            if (fp32) launch_sweep<float, MODE_PSI>(a, st);
+            else launch_sweep<double, MODE_PSI>(a, st);
             const unsigned gb = grid_for((int64_t)a.S * a.ND * a.A.T, 256, 16384);
             if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3(gb), dim3(256), 0, st, a);
             else hipLaunchKernelGGL(k_psi_gather<double>, dim3(gb), dim3(256), 0, st, a);
@@ -1299,6 +1479,8 @@ int rh15d_default_options(rh15d_options *o) {
     o->scheduler = RH15D_SCHED_CHUNKED;
     o->batch_columns = 0;
     o->profile = 0;
+    o->sweep_mc = 0;
+    o->sweep_pack = 0;
     return RH15D_OK;
 }
 
@@ -1307,7 +1489,8 @@ int rh15d_workspace_size(const rh15d_atom *atom_c, const rh15d_columns *cols, co
     if (rc != RH15D_OK) return rc;
     if (!bytes) { set_error("null argument"); return RH15D_EINVAL; }
     DevAtom *D = nullptr;
-    if ((rc = get_dev_atom(const_cast<rh15d_atom *>(atom_c), o->n_mu, &D)) != RH15D_OK) return rc;
+    rh15d_atom *atom_m = const_cast<rh15d_atom *>(atom_c);
+    if ((rc = get_dev_atom(atom_m, o->n_mu, pick_shape(atom_m, o), &D)) != RH15D_OK) return rc;
     const int ND = max_depth(cols);
     const int S = slot_count(*D, cols, o, ND);
     *bytes = make_layout(*D, cols->n_columns, S, ND, o->precision == RH15D_FP32, o->ng_order == 2).total;
@@ -1325,7 +1508,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     if (cols->n_columns == 0) return RH15D_OK;
     rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
     DevAtom *D = nullptr;
-    if ((rc = get_dev_atom(atom, o->n_mu, &D)) != RH15D_OK) return rc;
+    if ((rc = get_dev_atom(atom, o->n_mu, pick_shape(atom, o), &D)) != RH15D_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool fp32 = o->precision == RH15D_FP32;
     const int ND = max_depth(cols);
@@ -1383,7 +1566,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale;
 
     Launcher run{a, fp32, o->start == RH15D_START_ZERO_RADIATION, out->spectrum != nullptr, out->psi_star != nullptr,
-                 st, dim3((D->n_groups + 3) / 4, S)};
+                 st};
     Timer tm;
     if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
     Timer *tp = tm.on ? &tm : nullptr;

@@ -68,26 +68,27 @@ struct DevGroup {
     int n_line_slots; // slots that are lines (read a profile row per ray-step)
 };
 
-// Per-lane ray constants (structure of arrays, index group * 64 + lane).
+// Per-lane constants (structure of arrays, index group * 64 + lane).  A lane
+// carries one wavelength and `mc` consecutive angles of one direction.
 struct DevLanes {
     int *j;           // union wavelength index
-    int *m;           // angle index
-    double *nu;       // frequency
-    double *mu;       // cosine of the ray with the vertical
+    int *m0;          // first angle index of the lane
     double *lamfac;   // lambda / kBgLambdaRef
     double *hnu_k;    // h nu / k_B
     double *two_hnu3c2;
-    // per slot q (index (group*64+lane)*kMaxSlots + q)
-    int *phi_idx;     // line: column in the per-depth profile row; continuum: -1
-    double *W;        // quadrature weight w_nu(t, j) * w_mu / 2 (0 on padding lanes)
-    double *kap;      // 4 pi W / (h nu_t)
+    // per slot q (index (group*64+lane)*kMaxSlots + q); zero/-1 where the
+    // slot's transition is not active at this lane's wavelength
+    int *pbase;       // line: profile column of the lane's first angle; else -1
+    double *wj;       // frequency weight w(t, j)
+    double *kapj;     // 4 pi w(t, j) / (2 h nu_t): times w_mu gives the rate weight
     double *alpha;    // continuum cross-section at nu_j
 };
-
 // Everything the kernels need about an atom and an angle quadrature.
 struct DevAtom {
     int L, n_lines, n_cont, T, NL, n_mu;
     int n_groups, n_keys;       // ray groups and rate keys per depth
+    int mc, pack;               // angles per lane, packing of wavelengths into groups
+    int g_begin[kMaxSlots + 2]; // groups with n slots are [g_begin[n], g_begin[n+1])
     int ray_cols;               // line rays per depth row: sum over lines of 2 n_act n_mu
     int pad0;
     double mass, abund, c_bg;
@@ -98,6 +99,7 @@ struct DevAtom {
     int *act_j; double *act_w;  // concatenated active lists and weights
     double *mu, *wmu;           // Gauss-Legendre on (0,1)
     int *jact_off, *jact_t;     // per wavelength: active transitions (CSR)
+    int *jact_ja;               // ... and the wavelength's index in each one's active list
     DevGroup *groups;
     DevLanes lanes;
     // rate keys per transition and per ordered transition pair (CSR)
@@ -112,10 +114,18 @@ struct DevAtom {
     double keys_per_depth;        // reduced rate values written
 };
 
+// Shape of the formal-solution work: angles carried per lane and how
+// wavelengths with different active transitions are packed into groups.
+struct SweepShape {
+    int mc = 1;      // angles per lane (divides n_mu)
+    int pack = 0;    // 0: one set of active transitions per group; 1: mixed sets up to kMaxSlots
+    bool operator<(const SweepShape &o) const { return mc != o.mc ? mc < o.mc : pack < o.pack; }
+};
+
 struct HostGroupTables {
     std::vector<DevGroup> groups;
-    std::vector<int> lane_j, lane_m, phi_idx;
-    std::vector<double> lane_nu, lane_mu, lane_lamfac, lane_hnu_k, lane_2hnu3c2, W, kap, alpha;
+    std::vector<int> lane_j, lane_m0, pbase;
+    std::vector<double> lane_lamfac, lane_hnu_k, lane_2hnu3c2, wj, kapj, alpha;
     std::vector<int> p_off, p_key, q_off, q_key, x_t, x_t2, x_off, x_key;
     int n_keys = 0, ray_cols = 0;
     std::vector<double> mu, wmu;
@@ -136,7 +146,8 @@ struct rh15d_atom {
     std::vector<int> jact_off, jact_t;
     // device copies per (device, n_mu), built on first use
     std::mutex mu_;
-    std::map<std::pair<int, int>, rh15d::DevAtom> dev;
+    std::map<std::pair<std::pair<int, int>, rh15d::SweepShape>, rh15d::DevAtom> dev;
+    std::map<std::pair<std::pair<int, int>, int>, rh15d::SweepShape> tuned;  // (device, n_mu), precision -> shape
     std::vector<void *> dev_allocs;
 };
 
@@ -144,7 +155,7 @@ namespace rh15d {
 // host setup (atom_setup.cpp)
 int parse_atom_file(const char *path, rh15d_atom *a, std::string &err);
 void gauss_legendre_01(int n, std::vector<double> &x, std::vector<double> &w);
-void build_group_tables(const rh15d_atom &a, int n_mu, HostGroupTables &out);
+void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGroupTables &out);
 void set_error(const char *fmt, ...);
 const char *last_error();
 }  // namespace rh15d

@@ -97,3 +97,20 @@ def test_slots_zero_iterations_and_zero_radiation(atom_dir):
             assert g["n_iter"][c] == r["n_iter"] == it and g["status"][c] == r["status"]
             np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=1e-10)
             np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-10)
+
+
+@pytest.mark.parametrize("mc,pack", [(1, 1), (1, 2), (5, 1), (5, 2)])
+def test_every_sweep_shape_matches_oracle(atom_dir, mc, pack):
+    """Angles per lane and the packing of wavelengths into wavefronts change
+    only the order of the sums: every shape agrees with the oracle."""
+    cols = _mixed_columns().select([0, 3, 7, 11])
+    kw = dict(n_mu=5, tol=1e-5, max_iter=60, coll_scale=0.1)
+    g = _solve(atom_dir["h6"], cols, scheduler=1, sweep_mc=mc, sweep_pack=pack, **kw)
+    a = O.Atom(atom_dir["h6"])
+    for c in range(cols.n_columns):
+        r = O.solve_column(a, cols.column(c), want_psi=True, **kw)
+        lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
+        assert g["n_iter"][c] == r["n_iter"] and g["status"][c] == r["status"]
+        np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=1e-10)
+        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-10)
+        np.testing.assert_allclose(g["psi_star"][lo:hi].T, r["psi_star"], rtol=1e-10, atol=1e-300)
