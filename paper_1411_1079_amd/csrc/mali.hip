@@ -654,6 +654,72 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
 // ---------------------------------------------------------------------------
 // statistical equilibrium per depth point
 // ---------------------------------------------------------------------------
+// Collisional rate coefficient u -> l of transition t at this point.
+__device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransition &tr, double T, double ne) {
+    double Cul;
+    if (tr.coll_kind == 0) {
+        Cul = ne * kCollC0 * tr.coll_val / (a.A.g[tr.u] * sqrt(T));
+    } else {
+        const double x = kH * tr.nu0 / (kKB * T);
+        Cul = tr.coll_val / (1.0 - tr.coll_val) * tr.A / (-expm1(-x));
+    }
+    return Cul * a.coll_scale;
+}
+
+template <typename R>
+__device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e, int N, int k) {
+    double v = 0.0;
+    for (int i = b; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
+    return v;
+}
+
+// Rate matrix entry (i, j), i != j: radiative and collisional rates from j
+// into i, plus the cross terms of overlapping transitions.
+template <typename R, bool ZERO_RAD>
+__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int N, int k,
+                                             int64_t gc, double T, double ne) {
+    const DevAtom &A = a.A;
+    double v = 0.0;
+    const int tu = A.up_t[i * L + j];
+    if (tu >= 0) {  // j = l, i = u: excitation / ionisation
+        const DevTransition &tr = A.tr[tu];
+        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1], N, k);
+        v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]);
+    }
+    const int td = A.dn_t[i * L + j];
+    if (td >= 0) {  // j = u, i = l: de-excitation / recombination
+        const DevTransition &tr = A.tr[td];
+        if (ZERO_RAD) {
+            if (tr.kind == 0) {
+                v += tr.A;
+            } else {
+                const double G0 = a.gr[gc * A.n_cont + (td - A.n_lines)];
+                double q = 0.0;
+                for (int ja = 0; ja < tr.n_act; ja++) {
+                    const double nu = A.nu[A.act_j[tr.act_off + ja]];
+                    const double G = G0 * exp(-kH * nu / (kKB * T));
+                    const double r = tr.nu0 / nu;
+                    const double alpha = tr.alpha0 * r * r * r;
+                    q += 4.0 * kPI * A.act_w[tr.act_off + ja] / (kH * nu) * 2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha;
+                }
+                v += q;
+            }
+        } else {
+            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1], N, k);
+        }
+        v += coll_down(a, tr, T, ne);
+    }
+    if (!ZERO_RAD) {
+        for (int x = A.xe_off[i * L + j]; x < A.xe_off[i * L + j + 1]; x++) {
+            const int e = A.xe_val[x];
+            const int xp = (e > 0 ? e : -e) - 1;
+            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1], N, k);
+            v += e > 0 ? X : -X;
+        }
+    }
+    return v;
+}
+
 template <typename R, int L, bool ZERO_RAD>
 __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const ColGeom cg = geom(a, slot);
@@ -662,71 +728,24 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
     const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
+    const double T = a.T[g], ne = a.ne[g];
     double M[L][L];
     double nold[L], b[L];
 #pragma unroll
-    for (int i = 0; i < L; i++) {
-        nold[i] = a.pops[g * L + i];
+    for (int i = 0; i < L; i++) nold[i] = a.pops[g * L + i];
+    // off-diagonal entries; every column of the rate matrix sums to zero, so
+    // the diagonal is minus the rest of its column
 #pragma unroll
-        for (int j = 0; j < L; j++) M[i][j] = 0.0;
-    }
-    const double T = a.T[g], ne = a.ne[g];
-    for (int t = 0; t < A.T; t++) {
-        const DevTransition &tr = A.tr[t];
-        const int l = tr.l, u = tr.u;
-        double P = 0.0, Q = 0.0;
-        if (ZERO_RAD) {
-            // no radiation: only spontaneous de-excitation / recombination
-            if (tr.kind == 0) {
-                Q = tr.A;
-            } else {
-                const double G0 = a.gr[gc * A.n_cont + (t - A.n_lines)];
-                for (int ja = 0; ja < tr.n_act; ja++) {
-                    const double nu = A.nu[A.act_j[tr.act_off + ja]];
-                    const double G = G0 * exp(-kH * nu / (kKB * T));
-                    const double alpha = tr.alpha0 * pow(tr.nu0 / nu, 3.0);
-                    Q += 4.0 * kPI * A.act_w[tr.act_off + ja] / (kH * nu) * 2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha;
-                }
-            }
-        } else {
-            for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) P += static_cast<double>(part[(size_t)A.p_key[i] * N + k]);
-            for (int i = A.q_off[t]; i < A.q_off[t + 1]; i++) Q += static_cast<double>(part[(size_t)A.q_key[i] * N + k]);
-        }
+    for (int i = 0; i < L; i++)
 #pragma unroll
-        for (int i = 0; i < L; i++) {
-            if (i == u) { M[i][l] += P; M[i][i] -= Q; }
-            if (i == l) { M[i][i] -= P; M[i][u] += Q; }
-        }
-        // electron collisions, detailed balance between the two levels
-        double Cul;
-        if (tr.coll_kind == 0) {
-            Cul = ne * kCollC0 * tr.coll_val / (A.g[u] * sqrt(T));
-        } else {
-            const double x = kH * tr.nu0 / (kKB * T);
-            Cul = tr.coll_val / (1.0 - tr.coll_val) * tr.A / (-expm1(-x));
-        }
-        Cul *= a.coll_scale;
-        const double Clu = Cul * exp(a.lnr[gc * L + u] - a.lnr[gc * L + l]);
+        for (int j = 0; j < L; j++)
+            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, N, k, gc, T, ne);
 #pragma unroll
-        for (int i = 0; i < L; i++) {
-            if (i == l) { M[i][u] += Cul; M[i][i] -= Clu; }
-            if (i == u) { M[i][l] += Clu; M[i][i] -= Cul; }
-        }
-    }
-    if (!ZERO_RAD) {
-        for (int x = 0; x < A.n_xpairs; x++) {
-            double X = 0.0;
-            for (int i = A.x_off[x]; i < A.x_off[x + 1]; i++) X += static_cast<double>(part[(size_t)A.x_key[i] * N + k]);
-            const int l = A.tr[A.x_t[x]].l, u = A.tr[A.x_t[x]].u, u2 = A.tr[A.x_t2[x]].u;
+    for (int j = 0; j < L; j++) {
+        double c = 0.0;
 #pragma unroll
-            for (int i = 0; i < L; i++) {
-#pragma unroll
-                for (int j = 0; j < L; j++) {
-                    if (j == u2 && i == u) M[i][j] += X;
-                    if (j == u2 && i == l) M[i][j] -= X;
-                }
-            }
-        }
+        for (int i = 0; i < L; i++) if (i != j) c += M[i][j];
+        M[j][j] = -c;
     }
     // particle conservation replaces the equation of the most populated level
     int istar = 0;
@@ -925,32 +944,45 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
 // Opacity and source function of the vertical (mu = 1, upward) ray at
 // wavelength j, depth point k; line profiles come from the prepared table.
 template <typename R>
-__device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, int j, int64_t gc, int64_t g, double &chi,
-                                                  double &S, double &B) {
+struct EmergentRay {
+    int j;
+    R hnu_k, two_hnu3, lamfac, nu;
+};
+
+// In the sweep's precision R (FP64 for the plain path, FP32 for the
+// precision form); the spectrum is stored in FP64.
+template <typename R>
+__device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const EmergentRay<R> &ray, int64_t gc, int64_t g,
+                                                  R &chi, R &S, R &B) {
     const DevAtom &A = a.A;
     const int L = A.L;
-    const double nu = A.nu[j];
-    const double x = kH * nu / kKB * static_cast<double>(reinterpret_cast<const R *>(a.rec)[gc * a.rec_w + 1]);
-    const double ex = exp(-x), omx = x > 0.5 ? 1.0 - ex : -expm1(-x);
-    const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
-    B = two_hnu3 * ex / omx;
-    double c = a.kbg[gc] * (A.lam[j] / kBgLambdaRef);
-    double e = c * B;
+    const R *rec = reinterpret_cast<const R *>(a.rec) + gc * a.rec_w;
+    const R x = ray.hnu_k * rec[1];
+    const R ex = d_exp(-x), omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
+    B = ray.two_hnu3 * ex / omx;
+    R c = rec[2] * ray.lamfac;
+    R e = c * B;
     const R *phirow = reinterpret_cast<const R *>(a.phi) + gc * A.ray_cols;
-    for (int i = A.jact_off[j]; i < A.jact_off[j + 1]; i++) {
+    const double *n = a.pops + g * L;
+    for (int i = A.jact_off[ray.j]; i < A.jact_off[ray.j + 1]; i++) {
         const int t = A.jact_t[i];
         const DevTransition &tr = A.tr[t];
-        double vlu, vul, U;
+        const R nl = static_cast<R>(n[tr.l]), nu = static_cast<R>(n[tr.u]);
+        R vlu, vul, U;
         if (tr.kind == 0) {
-            const double ph = static_cast<double>(phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]]);
-            vlu = tr.hnu4pi * tr.Blu * ph; vul = tr.hnu4pi * tr.Bul * ph; U = tr.hnu4pi * tr.A * ph;
+            const R ph = phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]];
+            const R c0 = static_cast<R>(tr.hnu4pi);
+            vlu = c0 * static_cast<R>(tr.Blu) * ph;
+            vul = c0 * static_cast<R>(tr.Bul) * ph;
+            U = c0 * static_cast<R>(tr.A) * ph;
         } else {
-            const double alpha = tr.alpha0 * pow(tr.nu0 / nu, 3.0);
-            const double G = a.gr[gc * A.n_cont + (t - A.n_lines)] * ex;
-            vlu = alpha; vul = G * alpha; U = two_hnu3 * G * alpha;
+            const R r = static_cast<R>(tr.nu0) / ray.nu;
+            const R alpha = static_cast<R>(tr.alpha0) * r * r * r;
+            const R G = rec[kRecHead + (t - A.n_lines)] * ex;
+            vlu = alpha; vul = G * alpha; U = ray.two_hnu3 * G * alpha;
         }
-        c += a.pops[g * L + tr.l] * vlu - a.pops[g * L + tr.u] * vul;
-        e += a.pops[g * L + tr.u] * U;
+        c += nl * vlu - nu * vul;
+        e += nu * U;
     }
     chi = c;
     S = e / c;
@@ -961,25 +993,33 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
-        const int slot = a.retire_list[w / A.NL], j = (int)(w % A.NL);
+        const int slot = a.retire_list[w / A.NL];
+        EmergentRay<R> ray;
+        ray.j = (int)(w % A.NL);
+        const double nu = A.nu[ray.j];
+        ray.nu = static_cast<R>(nu);
+        ray.hnu_k = static_cast<R>(kH * nu / kKB);
+        ray.two_hnu3 = static_cast<R>(2.0 * kH * nu * nu * nu / (kC * kC));
+        ray.lamfac = static_cast<R>(A.lam[ray.j] / kBgLambdaRef);
         const ColGeom cg = geom(a, slot);
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
-        double chi2, S2, B2, chi, S, B;
-        point_opacity_mu1<R>(a, j, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
-        point_opacity_mu1<R>(a, j, gc0 + N - 1, g0 + N - 1, chi, S, B);
-        const double dtv = 0.5 * (chi + chi2) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
-        double I = dtv > 0.0 ? B + (B - B2) / dtv : B;
-        double chi_p = chi, S_p = S;
+        const R *rec = reinterpret_cast<const R *>(a.rec);
+        R chi2, S2, B2, chi, S, B;
+        point_opacity_mu1<R>(a, ray, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
+        point_opacity_mu1<R>(a, ray, gc0 + N - 1, g0 + N - 1, chi, S, B);
+        const R dtv = R(0.5) * (chi + chi2) * rec[(gc0 + N - 1) * a.rec_w];
+        R I = dtv > R(0) ? B + (B - B2) / dtv : B;
+        R chi_p = chi, S_p = S;
         for (int k = N - 2; k >= 0; k--) {
-            point_opacity_mu1<R>(a, j, gc0 + k, g0 + k, chi, S, B);
-            const double x = 0.5 * (chi_p + chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
-            double e, wa, wb;
-            sc_weights<double>(x, e, wa, wb);
+            point_opacity_mu1<R>(a, ray, gc0 + k, g0 + k, chi, S, B);
+            const R x = R(0.5) * (chi_p + chi) * rec[(gc0 + k + 1) * a.rec_w];
+            R e, wa, wb;
+            sc_weights<R>(x, e, wa, wb);
             I = I * e + wa * S_p + wb * S;
             chi_p = chi; S_p = S;
         }
-        a.spectrum[(size_t)cg.col * A.NL + j] = I;
+        a.spectrum[(size_t)cg.col * A.NL + ray.j] = static_cast<double>(I);
     }
 }
 
@@ -1206,6 +1246,32 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     UP(H.p_off, &D.p_off); UP(H.p_key, &D.p_key); UP(H.q_off, &D.q_off); UP(H.q_key, &D.q_key);
     D.n_xpairs = static_cast<int>(H.x_t.size());
     UP(H.x_t, &D.x_t); UP(H.x_t2, &D.x_t2); UP(H.x_off, &D.x_off); UP(H.x_key, &D.x_key);
+    {
+        const int L = D.L;
+        std::vector<int> up(L * L, -1), dn(L * L, -1);
+        for (int t = 0; t < D.T; t++) {
+            const int l = atom->tr[t].l, u = atom->tr[t].u;
+            if (up[u * L + l] >= 0 || dn[l * L + u] >= 0) {
+                set_error("two transitions connect levels %d and %d", l, u);
+                return RH15D_EINVAL;
+            }
+            up[u * L + l] = t;   // l -> u (excitation / ionisation)
+            dn[l * L + u] = t;   // u -> l (de-excitation / recombination)
+        }
+        std::vector<std::vector<int>> xe(L * L);
+        for (size_t x = 0; x < H.x_t.size(); x++) {
+            const int lt = atom->tr[H.x_t[x]].l, ut = atom->tr[H.x_t[x]].u, u2 = atom->tr[H.x_t2[x]].u;
+            xe[ut * L + u2].push_back((int)x + 1);
+            xe[lt * L + u2].push_back(-((int)x + 1));
+        }
+        std::vector<int> xo(L * L + 1, 0), xv;
+        for (int e = 0; e < L * L; e++) {
+            xv.insert(xv.end(), xe[e].begin(), xe[e].end());
+            xo[e + 1] = static_cast<int>(xv.size());
+        }
+        if (xv.empty()) xv.push_back(0);
+        UP(up, &D.up_t); UP(dn, &D.dn_t); UP(xo, &D.xe_off); UP(xv, &D.xe_val);
+    }
 #undef UP
     for (const auto &G : H.groups) {
         // per ray-step: background and Planck 7, formal step 19, source 1;

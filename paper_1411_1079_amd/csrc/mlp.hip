@@ -1,0 +1,535 @@
+// Learned start solution for MALI: a small MLP that predicts the natural-log
+// departure coefficients ln(n_i / n*_i) of every level at a depth point from
+// the local thermodynamic stencil.  The paper (Sec. 2.3) shows that the
+// start solution decides how many iterations a column needs; the network
+// only supplies that start, MALI still iterates to convergence.
+//
+// Network: 36 inputs (a 9-point depth stencil of ln T, ln n_e, ln n_H and
+// v_z / 10 km/s, z-scored) -> n_layers x n_hidden (SiLU) -> n_out.
+// Dense layers run on CDNA matrix cores: v_mfma_f32_16x16x16 with BF16
+// operands (weights and activations rounded to BF16 when staged in LDS) and
+// FP32 accumulation; master weights, gradients and Adam moments are FP32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rh15d_internal.h"
+
+using namespace rh15d;
+
+namespace {
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                  \
+            return RH15D_EDEVICE;                                                      \
+        }                                                                              \
+    } while (0)
+
+constexpr int kStencil = 9;
+constexpr int kFeat = 4 * kStencil;   // 36
+constexpr int64_t kChunk = 1 << 18;   // samples per forward pass of a long inference
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    unsigned int u = __builtin_bit_cast(unsigned int, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (unsigned short)(u >> 16);
+}
+
+// C[M x N] = op(A)[M x K] op(B)[K x N] (+ C if accumulate); FP32 in HBM,
+// BF16 in LDS, FP32 accumulation.  op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k],
+// op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  A 64 x 64 tile per
+// workgroup of four wavefronts, each a 32 x 32 block of 2 x 2 MFMA tiles.
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb,
+                                              float *C, int ldc, int accumulate) {
+    __shared__ unsigned short As[kBM][kBK + 4];
+    __shared__ unsigned short Bs[kBK][kBN + 4];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += kBK) {
+        for (int e = tid; e < kBM * kBK; e += 256) {
+            const int r = e / kBK, c = e % kBK;
+            const int m = m0 + r, k = k0 + c;
+            float v = 0.f;
+            if (m < M && k < K) v = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+            As[r][c] = to_bf16(v);
+        }
+        for (int e = tid; e < kBK * kBN; e += 256) {
+            const int r = e / kBN, c = e % kBN;
+            const int k = k0 + r, n = n0 + c;
+            float v = 0.f;
+            if (k < K && n < N) v = TB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+            Bs[r][c] = to_bf16(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 16) {
+            const int kb = kk + 4 * (lane >> 4);
+            bf16x4 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const int row = wm + i * 16 + (lane & 15);
+                af[i] = bf16x4{(short)As[row][kb], (short)As[row][kb + 1], (short)As[row][kb + 2], (short)As[row][kb + 3]};
+                const int col = wn + i * 16 + (lane & 15);
+                bfr[i] = bf16x4{(short)Bs[kb][col], (short)Bs[kb + 1][col], (short)Bs[kb + 2][col], (short)Bs[kb + 3][col]};
+            }
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (m < M && n < N) {
+                    float *c = C + (size_t)m * ldc + n;
+                    *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+                }
+            }
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
+
+// Z += b; H = silu(Z) (or H = Z for the output layer).
+__global__ void k_bias_act(float *Z, const float *b, float *H, int64_t n, int N, int silu) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * N; i += (int64_t)gridDim.x * blockDim.x) {
+        const float z = Z[i] + b[i % N];
+        Z[i] = z;
+        if (H) H[i] = silu ? z * sigmoid(z) : z;
+    }
+}
+
+// dZ = dH * silu'(Z)
+__global__ void k_silu_back(const float *Z, float *dH, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float s = sigmoid(Z[i]);
+        dH[i] *= s * (1.f + Z[i] * (1.f - s));
+    }
+}
+
+// dY = 2 (Y - T) / (n N); per-block partial sums of the squared error
+__global__ void k_mse(const float *Y, const float *T, float *dY, int64_t n, int N, double *partial) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    const double scale = 2.0 / ((double)n * N);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * N; i += (int64_t)gridDim.x * blockDim.x) {
+        const float d = Y[i] - T[i];
+        dY[i] = (float)(scale * d);
+        s += (double)d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// db[j] = sum over rows of dZ[:, j] (one thread per column, rows in order)
+__global__ void k_colsum(const float *dZ, float *db, int64_t n, int N) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += dZ[i * N + j];
+    db[j] = (float)s;
+}
+
+__global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Raw stencil features of sample points (global depth indices; NULL = all
+// points in order), columns ragged with offsets doff: ln T, ln n_e, ln n_H and
+// v_z / 10 km/s at k-4 .. k+4, clamped to the column (edge replication).
+__global__ void k_features(const int64_t *doff, int64_t n_columns, const double *T, const double *ne,
+                           const double *nH, const double *vz, const int64_t *samples, int64_t n, float *out) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = samples ? samples[s] : s;
+        int64_t lo = 0, hi = n_columns - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (doff[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const int64_t g0 = doff[lo], N = doff[lo + 1] - g0, k = g - g0;
+        for (int d = -4; d <= 4; d++) {
+            int64_t kk = k + d;
+            kk = kk < 0 ? 0 : (kk >= N ? N - 1 : kk);
+            const int64_t q = g0 + kk;
+            float *f = out + s * kFeat + (d + 4) * 4;
+            f[0] = (float)log(T[q]);
+            f[1] = (float)log(ne[q]);
+            f[2] = (float)log(nH[q]);
+            f[3] = (float)(vz[q] * 1e-4);
+        }
+    }
+}
+
+// (x - mean) / std per feature
+__global__ void k_normalize(const float *x, const float *mean, const float *istd, float *y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kFeat; i += (int64_t)gridDim.x * blockDim.x) {
+        const int f = (int)(i % kFeat);
+        y[i] = (x[i] - mean[f]) * istd[f];
+    }
+}
+
+// Per-feature sums and sums of squares: block partials, then one block in order.
+__global__ void k_feat_partial(const float *x, int64_t n, double *partial) {
+    __shared__ double sh[256];
+    for (int f = 0; f < kFeat; f++) {
+        double s = 0.0, q = 0.0;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+            const double v = x[i * kFeat + f];
+            s += v;
+            q += v * v;
+        }
+        for (int pass = 0; pass < 2; pass++) {
+            sh[threadIdx.x] = pass ? q : s;
+            __syncthreads();
+            for (int o = 128; o > 0; o >>= 1) {
+                if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) partial[((size_t)blockIdx.x * kFeat + f) * 2 + pass] = sh[0];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_feat_finish(const double *partial, int nblocks, int64_t n, float *mean, float *stdv) {
+    const int f = threadIdx.x;
+    if (f >= kFeat) return;
+    double s = 0.0, q = 0.0;
+    for (int b = 0; b < nblocks; b++) {
+        s += partial[((size_t)b * kFeat + f) * 2];
+        q += partial[((size_t)b * kFeat + f) * 2 + 1];
+    }
+    const double m = s / n;
+    const double var = q / n - m * m;
+    mean[f] = (float)m;
+    stdv[f] = (float)sqrt(var > 1e-12 ? var : 1e-12);
+}
+
+unsigned blocks_for(int64_t n, unsigned cap = 65535) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap));
+}
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+struct rh15d_mlp {
+    int n_hidden = 256, n_layers = 3, n_out = 6;
+    std::vector<int> dims;             // n_in, hidden..., n_out
+    std::vector<size_t> w_off, b_off;  // offsets into the flat parameter vector
+    size_t n_params = 0;
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;  // device, FP32
+    float *mean = nullptr, *istd = nullptr;                                 // device [36]
+    std::vector<float> h_mean, h_std;
+    int64_t step = 0;
+    // activations for up to `cap` samples
+    int64_t cap = 0;
+    float *x = nullptr;                     // normalised inputs [cap][36]
+    std::vector<float *> Z, H, dH;          // per layer
+    double *partial = nullptr;              // reductions
+    int dev = 0;
+};
+
+namespace {
+
+void free_acts(rh15d_mlp *p) {
+    (void)hipFree(p->x);
+    for (auto *q : p->Z) (void)hipFree(q);
+    for (auto *q : p->H) (void)hipFree(q);
+    for (auto *q : p->dH) (void)hipFree(q);
+    p->Z.clear(); p->H.clear(); p->dH.clear();
+    p->x = nullptr;
+    p->cap = 0;
+}
+
+int ensure_cap(rh15d_mlp *p, int64_t n) {
+    if (n <= p->cap) return RH15D_OK;
+    free_acts(p);
+    const int L = (int)p->dims.size() - 1;
+    HIP_TRY(hipMalloc(&p->x, n * kFeat * sizeof(float)));
+    p->Z.assign(L, nullptr); p->H.assign(L, nullptr); p->dH.assign(L, nullptr);
+    for (int l = 0; l < L; l++) {
+        const size_t bytes = (size_t)n * p->dims[l + 1] * sizeof(float);
+        HIP_TRY(hipMalloc(&p->Z[l], bytes));
+        HIP_TRY(hipMalloc(&p->H[l], bytes));
+        HIP_TRY(hipMalloc(&p->dH[l], bytes));
+    }
+    p->cap = n;
+    return RH15D_OK;
+}
+
+void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
+          bool acc, hipStream_t st) {
+    const dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
+    if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
+    else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
+    else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
+    else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
+}
+
+// Forward pass of n samples (raw features in HBM) into p->Z / p->H; the last
+// layer's output lands in p->Z.back().
+void forward(rh15d_mlp *p, const float *feat, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n * kFeat)), dim3(256), 0, st, feat, p->mean, p->istd, p->x, n);
+    const int L = (int)p->dims.size() - 1;
+    const float *in = p->x;
+    for (int l = 0; l < L; l++) {
+        const int K = p->dims[l], N = p->dims[l + 1];
+        gemm(false, false, (int)n, N, K, in, K, p->params + p->w_off[l], N, p->Z[l], N, false, st);
+        const bool last = l == L - 1;
+        hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(n * N)), dim3(256), 0, st, p->Z[l], p->params + p->b_off[l],
+                           last ? nullptr : p->H[l], n, N, last ? 0 : 1);
+        in = p->H[l];
+    }
+}
+
+int backward(rh15d_mlp *p, const float *target, int64_t n, float *loss, hipStream_t st) {
+    const int L = (int)p->dims.size() - 1;
+    const int nout = p->dims[L];
+    const int nb = 256;
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, p->Z[L - 1], target, p->dH[L - 1], n, nout, p->partial);
+    for (int l = L - 1; l >= 0; l--) {
+        const int K = p->dims[l], N = p->dims[l + 1];
+        float *dZ = p->dH[l];
+        if (l < L - 1) hipLaunchKernelGGL(k_silu_back, dim3(blocks_for(n * N)), dim3(256), 0, st, p->Z[l], dZ, n * N);
+        const float *in = l == 0 ? p->x : p->H[l - 1];
+        // dW = in^T dZ, db = column sums of dZ
+        gemm(true, false, K, N, (int)n, in, K, dZ, N, p->grads + p->w_off[l], N, false, st);
+        hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, dZ, p->grads + p->b_off[l], n, N);
+        if (l > 0) gemm(false, true, (int)n, K, N, dZ, N, p->params + p->w_off[l], N, p->dH[l - 1], K, false, st);
+    }
+    if (loss) {
+        std::vector<double> part(nb);
+        HIP_TRY(hipMemcpyAsync(part.data(), p->partial, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double s = 0.0;
+        for (double x : part) s += x;
+        *loss = (float)(s / ((double)n * nout));
+    }
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rh15d_mlp_create(int n_hidden, int n_layers, int n_out, uint64_t seed, rh15d_mlp **out) {
+    if (!out || n_hidden < 1 || n_hidden > 4096 || n_layers < 1 || n_layers > 8 || n_out < 1 || n_out > 64) {
+        set_error("bad MLP shape"); return RH15D_EINVAL;
+    }
+    *out = nullptr;
+    auto *p = new rh15d_mlp();
+    p->n_hidden = n_hidden; p->n_layers = n_layers; p->n_out = n_out;
+    p->dims.push_back(kFeat);
+    for (int l = 0; l < n_layers; l++) p->dims.push_back(n_hidden);
+    p->dims.push_back(n_out);
+    for (size_t l = 0; l + 1 < p->dims.size(); l++) {
+        p->w_off.push_back(p->n_params);
+        p->n_params += (size_t)p->dims[l] * p->dims[l + 1];
+        p->b_off.push_back(p->n_params);
+        p->n_params += p->dims[l + 1];
+    }
+    // He-uniform weights (bound sqrt(6 / fan_in)), zero biases, from a seeded splitmix64
+    std::vector<float> h(p->n_params, 0.f);
+    uint64_t s = seed;
+    for (size_t l = 0; l + 1 < p->dims.size(); l++) {
+        const double bound = std::sqrt(6.0 / p->dims[l]);
+        for (size_t i = 0; i < (size_t)p->dims[l] * p->dims[l + 1]; i++) {
+            const double u = (splitmix(s) >> 11) * (1.0 / 9007199254740992.0);
+            h[p->w_off[l] + i] = (float)((2.0 * u - 1.0) * bound);
+        }
+    }
+    p->h_mean.assign(kFeat, 0.f);
+    p->h_std.assign(kFeat, 1.f);
+    std::vector<float> ones(kFeat, 1.f), zeros(kFeat, 0.f);
+    hipError_t e = hipGetDevice(&p->dev);
+    auto bytes = p->n_params * sizeof(float);
+    if (e == hipSuccess) e = hipMalloc(&p->params, bytes);
+    if (e == hipSuccess) e = hipMalloc(&p->grads, bytes);
+    if (e == hipSuccess) e = hipMalloc(&p->m, bytes);
+    if (e == hipSuccess) e = hipMalloc(&p->v, bytes);
+    if (e == hipSuccess) e = hipMalloc(&p->mean, kFeat * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&p->istd, kFeat * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&p->partial, 256 * kFeat * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(p->params, h.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->grads, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(p->m, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(p->v, 0, bytes);
+    if (e == hipSuccess) e = hipMemcpy(p->mean, zeros.data(), kFeat * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->istd, ones.data(), kFeat * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("MLP allocation failed: %s", hipGetErrorString(e));
+        rh15d_mlp_free(p);
+        return RH15D_EDEVICE;
+    }
+    *out = p;
+    return RH15D_OK;
+}
+
+void rh15d_mlp_free(rh15d_mlp *p) {
+    if (!p) return;
+    free_acts(p);
+    (void)hipFree(p->params); (void)hipFree(p->grads); (void)hipFree(p->m); (void)hipFree(p->v);
+    (void)hipFree(p->mean); (void)hipFree(p->istd); (void)hipFree(p->partial);
+    delete p;
+}
+
+int rh15d_mlp_n_params(const rh15d_mlp *p, int64_t *n) {
+    if (!p || !n) { set_error("null argument"); return RH15D_EINVAL; }
+    *n = (int64_t)p->n_params;
+    return RH15D_OK;
+}
+
+int rh15d_mlp_get_params(const rh15d_mlp *p, float *host) {
+    if (!p || !host) { set_error("null argument"); return RH15D_EINVAL; }
+    HIP_TRY(hipMemcpy(host, p->params, p->n_params * sizeof(float), hipMemcpyDeviceToHost));
+    return RH15D_OK;
+}
+
+int rh15d_mlp_set_params(rh15d_mlp *p, const float *host) {
+    if (!p || !host) { set_error("null argument"); return RH15D_EINVAL; }
+    HIP_TRY(hipMemcpy(p->params, host, p->n_params * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(p->m, 0, p->n_params * sizeof(float)));
+    HIP_TRY(hipMemset(p->v, 0, p->n_params * sizeof(float)));
+    p->step = 0;
+    return RH15D_OK;
+}
+
+int rh15d_mlp_get_grads(const rh15d_mlp *p, float *host) {
+    if (!p || !host) { set_error("null argument"); return RH15D_EINVAL; }
+    HIP_TRY(hipMemcpy(host, p->grads, p->n_params * sizeof(float), hipMemcpyDeviceToHost));
+    return RH15D_OK;
+}
+
+int rh15d_mlp_get_normalization(const rh15d_mlp *p, float *mean, float *stdv) {
+    if (!p || !mean || !stdv) { set_error("null argument"); return RH15D_EINVAL; }
+    std::memcpy(mean, p->h_mean.data(), kFeat * sizeof(float));
+    std::memcpy(stdv, p->h_std.data(), kFeat * sizeof(float));
+    return RH15D_OK;
+}
+
+int rh15d_mlp_set_normalization(rh15d_mlp *p, const float *mean, const float *stdv) {
+    if (!p || !mean || !stdv) { set_error("null argument"); return RH15D_EINVAL; }
+    std::vector<float> is(kFeat);
+    for (int f = 0; f < kFeat; f++) {
+        if (!(stdv[f] > 0.f)) { set_error("feature scale must be positive"); return RH15D_EINVAL; }
+        is[f] = 1.f / stdv[f];
+    }
+    p->h_mean.assign(mean, mean + kFeat);
+    p->h_std.assign(stdv, stdv + kFeat);
+    HIP_TRY(hipMemcpy(p->mean, mean, kFeat * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->istd, is.data(), kFeat * sizeof(float), hipMemcpyHostToDevice));
+    return RH15D_OK;
+}
+
+int rh15d_mlp_features(const rh15d_columns *cols, const int64_t *samples, int64_t n, float *feat, void *stream) {
+    if (!cols || !feat || n < 0 || !cols->depth_offset || !cols->T || !cols->n_e || !cols->n_H || !cols->v_z) {
+        set_error("null argument"); return RH15D_EINVAL;
+    }
+    if (n == 0) return RH15D_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int64_t *doff = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&doff), (cols->n_columns + 1) * sizeof(int64_t), st));
+    HIP_TRY(hipMemcpyAsync(doff, cols->depth_offset, (cols->n_columns + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(n)), dim3(256), 0, st, doff, cols->n_columns, cols->T, cols->n_e,
+                       cols->n_H, cols->v_z, samples, n, feat);
+    HIP_TRY(hipFreeAsync(doff, st));
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+int rh15d_mlp_fit_normalization(rh15d_mlp *p, const float *feat, int64_t n, void *stream) {
+    if (!p || !feat || n < 2) { set_error("bad argument"); return RH15D_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float *dm = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&dm), 2 * kFeat * sizeof(float), st));
+    hipLaunchKernelGGL(k_feat_partial, dim3(256), dim3(256), 0, st, feat, n, p->partial);
+    hipLaunchKernelGGL(k_feat_finish, dim3(1), dim3(64), 0, st, p->partial, 256, n, dm, dm + kFeat);
+    std::vector<float> h(2 * kFeat);
+    HIP_TRY(hipMemcpyAsync(h.data(), dm, 2 * kFeat * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipFreeAsync(dm, st));
+    return rh15d_mlp_set_normalization(p, h.data(), h.data() + kFeat);
+}
+
+int rh15d_mlp_forward(rh15d_mlp *p, const float *feat, int64_t n, float *out, void *stream) {
+    if (!p || !feat || !out || n < 0) { set_error("null argument"); return RH15D_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = ensure_cap(p, std::min<int64_t>(std::max<int64_t>(n, 1), kChunk));
+    if (rc != RH15D_OK) return rc;
+    const int nout = p->dims.back();
+    for (int64_t s0 = 0; s0 < n; s0 += kChunk) {
+        const int64_t m = std::min<int64_t>(kChunk, n - s0);
+        forward(p, feat + s0 * kFeat, m, st);
+        HIP_TRY(hipMemcpyAsync(out + s0 * nout, p->Z.back(), m * nout * sizeof(float), hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+int rh15d_mlp_gradients(rh15d_mlp *p, const float *feat, const float *target, int64_t n, float *loss, void *stream) {
+    if (!p || !feat || !target || n < 1 || n > kChunk) { set_error("bad argument (1 <= n <= %lld)", (long long)kChunk); return RH15D_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = ensure_cap(p, n);
+    if (rc != RH15D_OK) return rc;
+    forward(p, feat, n, st);
+    return backward(p, target, n, loss, st);
+}
+
+int rh15d_mlp_train_step(rh15d_mlp *p, const float *feat, const float *target, int64_t n, float lr, float *loss,
+                         void *stream) {
+    int rc = rh15d_mlp_gradients(p, feat, target, n, loss, stream);
+    if (rc != RH15D_OK) return rc;
+    if (!(lr >= 0.f)) { set_error("learning rate must be >= 0"); return RH15D_EINVAL; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    p->step++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)p->step), c2 = 1.f - std::pow(b2, (float)p->step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for((int64_t)p->n_params)), dim3(256), 0, st, p->params, p->grads, p->m, p->v,
+                       (int64_t)p->n_params, lr, b1, b2, 1e-8f, c1, c2);
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+}  // extern "C"

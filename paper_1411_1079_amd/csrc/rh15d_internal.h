@@ -107,6 +107,12 @@ struct DevAtom {
     int *q_off, *q_key;         // [T+1], keys of Q'_t
     int n_xpairs;
     int *x_t, *x_t2, *x_off, *x_key;  // [n_xpairs], [n_xpairs+1]
+    // rate-matrix entry (i, j), i != j (rate from level j into level i):
+    // the transition whose upward (l = j, u = i) or downward (u = j, l = i)
+    // rates land there, or -1; and the cross terms landing there (CSR over
+    // i * L + j, +xpair+1 adds, -(xpair+1) subtracts)
+    int *up_t, *dn_t;           // [L * L]
+    int *xe_off, *xe_val;       // [L * L + 1], [...]
     // algorithmic work of one rate-mode sweep per depth point of a column
     double rays_per_depth;        // rays (wavelength x angle x direction)
     double flops_per_depth;       // see k_raysweep: 27 + 19 n_slots + 4 n_pairs per ray-step
