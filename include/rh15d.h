@@ -184,6 +184,77 @@ int rh15d_solve_columns(const rh15d_atom *atom, const rh15d_columns *cols,
                         const rh15d_options *opt, const rh15d_outputs *out,
                         void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Learned start solution.  The start populations decide how many MALI
+ * iterations a column needs (Sec. 2.3, "Different starting solutions").
+ * A small network predicts each depth point's natural-log departure
+ * coefficients ln(n_i / n*_i) from the local thermodynamic stencil; the
+ * prediction only seeds the iteration (start = RH15D_START_PROVIDED), MALI
+ * still decides convergence.  The dense layers run on the matrix cores
+ * with BF16 weights and FP32 accumulation (forward activations as two BF16
+ * terms, backward operands in BF16); master weights, gradients and Adam
+ * moments are kept in FP32 on the device.
+ * ------------------------------------------------------------------------ */
+
+/* Departure coefficients ln(n_i / n*_i) of the populations pops (DEVICE
+ * [total_depth][n_levels]) against the Saha-Boltzmann populations of the
+ * columns' T, n_e, n_H; written to log_b (DEVICE float [total_depth][n_levels]).
+ * Asynchronous on hip_stream. */
+int rh15d_departures(const rh15d_atom *atom, const rh15d_columns *cols, const double *pops, float *log_b,
+                     void *hip_stream);
+
+/* Start populations from departure coefficients: n_i = exp(l_i) n*_i,
+ * renormalised to the point's total population (DEVICE in/out as above),
+ * where l_i = sign(x) max(|x| - shrink, 0) and x = log_b_i clamped to
+ * [-50, 50], or 0 (LTE) if log_b_i is not finite.  shrink >= 0 moves
+ * predictions smaller than the network's error toward LTE. */
+int rh15d_pops_from_departures(const rh15d_atom *atom, const rh15d_columns *cols, const float *log_b,
+                               double shrink, double *pops, void *hip_stream);
+
+typedef struct rh15d_mlp rh15d_mlp;
+
+/* Network of 36 inputs (9-point depth stencil at k + {-128, -32, -8, -2, 0,
+ * 2, 8, 32, 128}, clamped at the column ends, of ln T, ln n_e, ln n_H and
+ * v_z / 10 km/s, in that order per stencil point), n_layers hidden
+ * layers of n_hidden SiLU units and n_out linear outputs.  Weights are
+ * He-uniform from a splitmix64 stream seeded by seed, biases zero.  The
+ * handle (device buffers on the current device) is owned by the library. */
+int rh15d_mlp_create(int n_hidden, int n_layers, int n_out, uint64_t seed, rh15d_mlp **out);
+void rh15d_mlp_free(rh15d_mlp *mlp);
+
+/* Parameters as one FP32 vector (HOST): for each layer the weight matrix
+ * [fan_in][fan_out] row-major, then its bias [fan_out]. */
+int rh15d_mlp_n_params(const rh15d_mlp *mlp, int64_t *n);
+int rh15d_mlp_get_params(const rh15d_mlp *mlp, float *host);
+int rh15d_mlp_set_params(rh15d_mlp *mlp, const float *host);   /* also resets Adam */
+int rh15d_mlp_get_grads(const rh15d_mlp *mlp, float *host);    /* of the last gradient call */
+
+/* Feature scaling (HOST [36] each): inputs enter as (x - mean) / std. */
+int rh15d_mlp_get_normalization(const rh15d_mlp *mlp, float *mean, float *std_);
+int rh15d_mlp_set_normalization(rh15d_mlp *mlp, const float *mean, const float *std_);
+/* Fit the scaling to n raw feature rows (DEVICE float [n][36]); synchronises. */
+int rh15d_mlp_fit_normalization(rh15d_mlp *mlp, const float *features, int64_t n, void *hip_stream);
+
+/* Raw features of n sample points given by global depth index (DEVICE
+ * int64 [n], or NULL for every point in order) into features (DEVICE float
+ * [n][36]).  Asynchronous. */
+int rh15d_mlp_features(const rh15d_columns *cols, const int64_t *samples, int64_t n, float *features,
+                       void *hip_stream);
+
+/* Outputs (DEVICE float [n][n_out]) of n feature rows.  Asynchronous. */
+int rh15d_mlp_forward(rh15d_mlp *mlp, const float *features, int64_t n, float *out, void *hip_stream);
+
+/* Mean squared error against target (DEVICE float [n][n_out]) and its
+ * gradient with respect to every parameter (kept in the handle); *loss
+ * (HOST, may be NULL) synchronises the stream.  1 <= n <= 262144. */
+int rh15d_mlp_gradients(rh15d_mlp *mlp, const float *features, const float *target, int64_t n, float *loss,
+                        void *hip_stream);
+
+/* rh15d_mlp_gradients, then one Adam step (beta 0.9 / 0.999, eps 1e-8) with
+ * learning rate lr. */
+int rh15d_mlp_train_step(rh15d_mlp *mlp, const float *features, const float *target, int64_t n, float lr,
+                         float *loss, void *hip_stream);
+
 /* Text of the calling thread's last failure ("" if none). */
 const char *rh15d_last_error(void);
 

@@ -270,6 +270,7 @@ int orc_atom_info(const orc_atom *a, int *L, int *n_lines, int *n_cont, int *NL)
     *L = a->L; *n_lines = a->n_lines; *n_cont = a->n_cont; *NL = a->NL;
     return 0;
 }
+double orc_atom_abundance(const orc_atom *a) { return a->abund; }
 int orc_atom_lambda(const orc_atom *a, double *lam) { memcpy(lam, a->lam, sizeof(double) * a->NL); return 0; }
 /* per transition: l, u, kind, n_active; weights copied if w != NULL (size n_active) */
 int orc_atom_transition(const orc_atom *a, int t, int *l, int *u, int *kind, int *n_act, int *act, double *w) {

@@ -46,6 +46,8 @@ def lib():
         L.orc_atom_transition.argtypes = [C.c_void_p, C.c_int, ip, ip, ip, ip, ip, dp]
         L.orc_atom_einstein_A.argtypes = [C.c_void_p, C.c_int]
         L.orc_atom_einstein_A.restype = C.c_double
+        L.orc_atom_abundance.argtypes = [C.c_void_p]
+        L.orc_atom_abundance.restype = C.c_double
         L.orc_last_error.restype = C.c_char_p
         L.orc_gauss_legendre.argtypes = [C.c_int, dp, dp]
         L.orc_voigt_H.argtypes = [C.c_double, C.c_double]
@@ -79,6 +81,7 @@ class Atom:
         lib().orc_atom_info(h, C.byref(L), C.byref(nl), C.byref(nc), C.byref(NL))
         self.n_levels, self.n_lines, self.n_cont, self.n_lambda = L.value, nl.value, nc.value, NL.value
         self.n_trans = self.n_lines + self.n_cont
+        self.abundance = lib().orc_atom_abundance(h)
         self.lam = np.empty(self.n_lambda)
         lib().orc_atom_lambda(h, _p(self.lam))
 

@@ -949,20 +949,23 @@ struct EmergentRay {
     R hnu_k, two_hnu3, lamfac, nu;
 };
 
-// In the sweep's precision R (FP64 for the plain path, FP32 for the
-// precision form); the spectrum is stored in FP64.
-template <typename R>
+// The prepared tables (per-depth records, line profiles) are read in the
+// sweep's precision TB; the arithmetic runs in FP64 for both forms: the
+// emergent intensity spans far more decades than FP32 can hold (the Planck
+// function's Wien tail in the far ultraviolet), and this one ray per
+// wavelength costs a few percent of one iteration.
+template <typename TB, typename R>
 __device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const EmergentRay<R> &ray, int64_t gc, int64_t g,
                                                   R &chi, R &S, R &B) {
     const DevAtom &A = a.A;
     const int L = A.L;
-    const R *rec = reinterpret_cast<const R *>(a.rec) + gc * a.rec_w;
-    const R x = ray.hnu_k * rec[1];
+    const TB *rec = reinterpret_cast<const TB *>(a.rec) + gc * a.rec_w;
+    const R x = ray.hnu_k * static_cast<R>(rec[1]);
     const R ex = d_exp(-x), omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
     B = ray.two_hnu3 * ex / omx;
-    R c = rec[2] * ray.lamfac;
+    R c = static_cast<R>(rec[2]) * ray.lamfac;
     R e = c * B;
-    const R *phirow = reinterpret_cast<const R *>(a.phi) + gc * A.ray_cols;
+    const TB *phirow = reinterpret_cast<const TB *>(a.phi) + gc * A.ray_cols;
     const double *n = a.pops + g * L;
     for (int i = A.jact_off[ray.j]; i < A.jact_off[ray.j + 1]; i++) {
         const int t = A.jact_t[i];
@@ -970,7 +973,7 @@ __device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const Emerge
         const R nl = static_cast<R>(n[tr.l]), nu = static_cast<R>(n[tr.u]);
         R vlu, vul, U;
         if (tr.kind == 0) {
-            const R ph = phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]];
+            const R ph = static_cast<R>(phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]]);
             const R c0 = static_cast<R>(tr.hnu4pi);
             vlu = c0 * static_cast<R>(tr.Blu) * ph;
             vul = c0 * static_cast<R>(tr.Bul) * ph;
@@ -978,7 +981,7 @@ __device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const Emerge
         } else {
             const R r = static_cast<R>(tr.nu0) / ray.nu;
             const R alpha = static_cast<R>(tr.alpha0) * r * r * r;
-            const R G = rec[kRecHead + (t - A.n_lines)] * ex;
+            const R G = static_cast<R>(rec[kRecHead + (t - A.n_lines)]) * ex;
             vlu = alpha; vul = G * alpha; U = ray.two_hnu3 * G * alpha;
         }
         c += nl * vlu - nu * vul;
@@ -988,8 +991,9 @@ __device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const Emerge
     S = e / c;
 }
 
-template <typename R>
+template <typename TB>
 __global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
+    using R = double;
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
@@ -1004,16 +1008,16 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
         const ColGeom cg = geom(a, slot);
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
-        const R *rec = reinterpret_cast<const R *>(a.rec);
+        const TB *rec = reinterpret_cast<const TB *>(a.rec);
         R chi2, S2, B2, chi, S, B;
-        point_opacity_mu1<R>(a, ray, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
-        point_opacity_mu1<R>(a, ray, gc0 + N - 1, g0 + N - 1, chi, S, B);
-        const R dtv = R(0.5) * (chi + chi2) * rec[(gc0 + N - 1) * a.rec_w];
+        point_opacity_mu1<TB, R>(a, ray, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
+        point_opacity_mu1<TB, R>(a, ray, gc0 + N - 1, g0 + N - 1, chi, S, B);
+        const R dtv = R(0.5) * (chi + chi2) * static_cast<R>(rec[(gc0 + N - 1) * a.rec_w]);
         R I = dtv > R(0) ? B + (B - B2) / dtv : B;
         R chi_p = chi, S_p = S;
         for (int k = N - 2; k >= 0; k--) {
-            point_opacity_mu1<R>(a, ray, gc0 + k, g0 + k, chi, S, B);
-            const R x = R(0.5) * (chi_p + chi) * rec[(gc0 + k + 1) * a.rec_w];
+            point_opacity_mu1<TB, R>(a, ray, gc0 + k, g0 + k, chi, S, B);
+            const R x = R(0.5) * (chi_p + chi) * static_cast<R>(rec[(gc0 + k + 1) * a.rec_w]);
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
             I = I * e + wa * S_p + wb * S;
@@ -1118,6 +1122,59 @@ __global__ void k_setup(RunArgs a) {
         a.slot_col[s] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x < CTR_COUNT) a.ctr[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// departure coefficients (learned start solution)
+// ---------------------------------------------------------------------------
+// ln of the Saha-Boltzmann populations of one point (sum = n_total).
+__device__ __forceinline__ void lte_log_pops(const DevAtom &A, double T, double ne, double nH, double *lnstar) {
+    const int L = A.L;
+    const double kT = kKB * T;
+    const double saha = log(2.0 / ne) + 1.5 * log(2.0 * kPI * kME * kT / (kH * kH));
+    double mx = -1e300;
+    for (int i = 0; i < L; i++) {
+        lnstar[i] = log(A.g[i] / A.g[0]) - (A.E[i] - A.E[0]) / kT + (A.stage[i] - A.stage[0]) * saha;
+        mx = fmax(mx, lnstar[i]);
+    }
+    double sum = 0.0;
+    for (int i = 0; i < L; i++) sum += exp(lnstar[i] - mx);
+    const double lnorm = log(A.abund * nH) - mx - log(sum);
+    for (int i = 0; i < L; i++) lnstar[i] += lnorm;
+}
+
+// log_b[g][i] = ln(n_i / n*_i)
+__global__ void k_departures(DevAtom A, int64_t n, const double *T, const double *ne, const double *nH,
+                             const double *pops, float *log_b) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        double ls[RH15D_MAX_LEVELS];
+        lte_log_pops(A, T[g], ne[g], nH[g], ls);
+        for (int i = 0; i < A.L; i++) log_b[g * A.L + i] = (float)(log(pops[g * A.L + i]) - ls[i]);
+    }
+}
+
+// n_i = b_i n*_i, renormalised to the total population of the point, with
+// ln b_i first shrunk toward 0 (LTE) by `shrink`: predictions smaller than
+// the network's error level are better replaced by the LTE value.
+constexpr double kMaxLogB = 50.0;
+__global__ void k_pops_from_departures(DevAtom A, int64_t n, const double *T, const double *ne, const double *nH,
+                                       const float *log_b, double shrink, double *pops) {
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        double ls[RH15D_MAX_LEVELS];
+        lte_log_pops(A, T[g], ne[g], nH[g], ls);
+        double mx = -1e300;
+        for (int i = 0; i < A.L; i++) {
+            // a non-finite prediction falls back to LTE; others are clamped to |ln b| <= 50
+            const float lb = log_b[g * A.L + i];
+            const double v = isfinite(lb) ? fmin(fmax((double)lb, -kMaxLogB), kMaxLogB) : 0.0;
+            ls[i] += copysign(fmax(fabs(v) - shrink, 0.0), v);
+            mx = fmax(mx, ls[i]);
+        }
+        double sum = 0.0;
+        for (int i = 0; i < A.L; i++) sum += exp(ls[i] - mx);
+        const double ntot = A.abund * nH[g];
+        for (int i = 0; i < A.L; i++) pops[g * A.L + i] = ntot * exp(ls[i] - mx) / sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1712,6 +1769,45 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     (void)hipHostFree(h_ctr);
     if (own) (void)hipFree(own);
     return result;
+}
+
+int rh15d_departures(const rh15d_atom *atom_c, const rh15d_columns *cols, const double *pops, float *log_b,
+                     void *hip_stream) {
+    if (!atom_c || !cols || !pops || !log_b || cols->n_columns < 0 || !cols->depth_offset || !cols->T || !cols->n_e ||
+        !cols->n_H) {
+        set_error("null argument or negative column count"); return RH15D_EINVAL;
+    }
+    rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
+    DevAtom *D = nullptr;
+    int rc = get_dev_atom(atom, 1, SweepShape{}, &D);
+    if (rc != RH15D_OK) return rc;
+    const int64_t n = cols->depth_offset[cols->n_columns];
+    if (n == 0) return RH15D_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(k_departures, dim3(grid_for(n, 256, 65535)), dim3(256), 0, st, *D, n, cols->T, cols->n_e,
+                       cols->n_H, pops, log_b);
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+int rh15d_pops_from_departures(const rh15d_atom *atom_c, const rh15d_columns *cols, const float *log_b, double shrink,
+                               double *pops, void *hip_stream) {
+    if (!(shrink >= 0.0)) { set_error("shrink must be >= 0"); return RH15D_EINVAL; }
+    if (!atom_c || !cols || !pops || !log_b || cols->n_columns < 0 || !cols->depth_offset || !cols->T || !cols->n_e ||
+        !cols->n_H) {
+        set_error("null argument or negative column count"); return RH15D_EINVAL;
+    }
+    rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
+    DevAtom *D = nullptr;
+    int rc = get_dev_atom(atom, 1, SweepShape{}, &D);
+    if (rc != RH15D_OK) return rc;
+    const int64_t n = cols->depth_offset[cols->n_columns];
+    if (n == 0) return RH15D_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(k_pops_from_departures, dim3(grid_for(n, 256, 65535)), dim3(256), 0, st, *D, n, cols->T,
+                       cols->n_e, cols->n_H, log_b, shrink, pops);
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
 }
 
 }  // extern "C"

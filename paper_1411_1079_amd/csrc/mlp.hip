@@ -4,11 +4,13 @@
 // start solution decides how many iterations a column needs; the network
 // only supplies that start, MALI still iterates to convergence.
 //
-// Network: 36 inputs (a 9-point depth stencil of ln T, ln n_e, ln n_H and
-// v_z / 10 km/s, z-scored) -> n_layers x n_hidden (SiLU) -> n_out.
+// Network: 36 inputs (a 9-point depth stencil, offsets 0, +-2, +-8, +-32,
+// +-128, of ln T, ln n_e, ln n_H and v_z / 10 km/s, z-scored) -> n_layers x n_hidden (SiLU) -> n_out.
 // Dense layers run on CDNA matrix cores: v_mfma_f32_16x16x16 with BF16
-// operands (weights and activations rounded to BF16 when staged in LDS) and
-// FP32 accumulation; master weights, gradients and Adam moments are FP32.
+// operands and FP32 accumulation.  Weights are rounded to BF16 when staged
+// in LDS; forward activations enter as two BF16 terms (hi + lo), backward
+// products round both operands to BF16.  Master weights, gradients and Adam
+// moments are FP32.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -33,6 +35,7 @@ namespace {
 constexpr int kStencil = 9;
 constexpr int kFeat = 4 * kStencil;   // 36
 constexpr int64_t kChunk = 1 << 18;   // samples per forward pass of a long inference
+constexpr int kMaxSplit = 64;         // most sample chunks of a weight-gradient product
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -43,55 +46,88 @@ __device__ __forceinline__ unsigned short to_bf16(float f) {
     return (unsigned short)(u >> 16);
 }
 
-// C[M x N] = op(A)[M x K] op(B)[K x N] (+ C if accumulate); FP32 in HBM,
-// BF16 in LDS, FP32 accumulation.  op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k],
-// op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n].  A 64 x 64 tile per
-// workgroup of four wavefronts, each a 32 x 32 block of 2 x 2 MFMA tiles.
+__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
+
+// Z = op(A)[M x K] op(B)[K x N] (+ bias[n]) (* silu'(D[m][n]) if D); H =
+// silu(Z) if act.  FP32 in HBM, BF16 in LDS, FP32 accumulation.
+// op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k], op(B)[k][n] = TB ?
+// B[n ldb + k] : B[k ldb + n].  Z and H (leading dimension ldc) are each
+// optional.  Split K: workgroup z of the grid takes k in [z kchunk,
+// (z + 1) kchunk) and writes its partial product at Z + z zstride.  A
+// 64 x 64 tile per workgroup of four wavefronts, each a 32 x 32 block of
+// 2 x 2 MFMA tiles.
 constexpr int kBM = 64, kBN = 64, kBK = 32;
 
-template <bool TA, bool TB>
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = sigmoid(z);
+    return s * (1.f + z * (1.f - s));
+}
+
+__device__ __forceinline__ float from_bf16(unsigned short h) {
+    return __builtin_bit_cast(float, (unsigned int)h << 16);
+}
+
+// SA: op(A) enters as two BF16 terms, hi = bf16(a) and lo = bf16(a - hi),
+// multiplied by the same BF16 B tile (two MFMAs): about 16 significant bits
+// for the activations of the forward pass, whose rounding noise would
+// otherwise set the floor of the network's output error; the weights (B)
+// stay BF16.
+template <bool TA, bool TB, bool SA>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *A, int lda, const float *B, int ldb,
-                                              float *C, int ldc, int accumulate) {
+                                              const float *bias, const float *D, float *Z, float *H, int ldc, int act,
+                                              int kchunk, int64_t zstride) {
     __shared__ unsigned short As[kBM][kBK + 4];
+    __shared__ unsigned short Al[SA ? kBM : 1][kBK + 4];
     __shared__ unsigned short Bs[kBK][kBN + 4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    if (Z) Z += blockIdx.z * zstride;
     f32x4 acc[2][2];
     for (int i = 0; i < 2; i++)
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += kBK) {
+    for (int k0 = kbeg; k0 < kend; k0 += kBK) {
         for (int e = tid; e < kBM * kBK; e += 256) {
-            const int r = e / kBK, c = e % kBK;
+            // TA: consecutive threads take consecutive m (A is k-major)
+            const int r = TA ? e % kBM : e / kBK, c = TA ? e / kBM : e % kBK;
             const int m = m0 + r, k = k0 + c;
             float v = 0.f;
-            if (m < M && k < K) v = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
-            As[r][c] = to_bf16(v);
+            if (m < M && k < kend) v = TA ? A[(size_t)k * lda + m] : A[(size_t)m * lda + k];
+            const unsigned short hi = to_bf16(v);
+            As[r][c] = hi;
+            if (SA) Al[r][c] = to_bf16(v - from_bf16(hi));
         }
         for (int e = tid; e < kBK * kBN; e += 256) {
-            const int r = e / kBN, c = e % kBN;
+            // TB: consecutive threads take consecutive k (B is n-major)
+            const int r = TB ? e % kBK : e / kBN, c = TB ? e / kBK : e % kBN;
             const int k = k0 + r, n = n0 + c;
             float v = 0.f;
-            if (k < K && n < N) v = TB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
+            if (k < kend && n < N) v = TB ? B[(size_t)n * ldb + k] : B[(size_t)k * ldb + n];
             Bs[r][c] = to_bf16(v);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kBK; kk += 16) {
             const int kb = kk + 4 * (lane >> 4);
-            bf16x4 af[2], bfr[2];
+            bf16x4 af[2], al[2], bfr[2];
 #pragma unroll
             for (int i = 0; i < 2; i++) {
                 const int row = wm + i * 16 + (lane & 15);
                 af[i] = bf16x4{(short)As[row][kb], (short)As[row][kb + 1], (short)As[row][kb + 2], (short)As[row][kb + 3]};
+                if (SA)
+                    al[i] = bf16x4{(short)Al[row][kb], (short)Al[row][kb + 1], (short)Al[row][kb + 2],
+                                   (short)Al[row][kb + 3]};
                 const int col = wn + i * 16 + (lane & 15);
                 bfr[i] = bf16x4{(short)Bs[kb][col], (short)Bs[kb + 1][col], (short)Bs[kb + 2][col], (short)Bs[kb + 3][col]};
             }
 #pragma unroll
             for (int i = 0; i < 2; i++)
 #pragma unroll
-                for (int j = 0; j < 2; j++)
+                for (int j = 0; j < 2; j++) {
+                    if (SA) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bfr[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
@@ -104,29 +140,12 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
                 const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
                 const int n = n0 + wn + j * 16 + (lane & 15);
                 if (m < M && n < N) {
-                    float *c = C + (size_t)m * ldc + n;
-                    *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+                    float z = acc[i][j][r] + (bias ? bias[n] : 0.f);
+                    if (D) z *= silu_grad(D[(size_t)m * ldc + n]);
+                    if (Z) Z[(size_t)m * ldc + n] = z;
+                    if (H) H[(size_t)m * ldc + n] = act ? z * sigmoid(z) : z;
                 }
             }
-}
-
-__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
-
-// Z += b; H = silu(Z) (or H = Z for the output layer).
-__global__ void k_bias_act(float *Z, const float *b, float *H, int64_t n, int N, int silu) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * N; i += (int64_t)gridDim.x * blockDim.x) {
-        const float z = Z[i] + b[i % N];
-        Z[i] = z;
-        if (H) H[i] = silu ? z * sigmoid(z) : z;
-    }
-}
-
-// dZ = dH * silu'(Z)
-__global__ void k_silu_back(const float *Z, float *dH, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float s = sigmoid(Z[i]);
-        dH[i] *= s * (1.f + Z[i] * (1.f - s));
-    }
 }
 
 // dY = 2 (Y - T) / (n N); per-block partial sums of the squared error
@@ -148,13 +167,23 @@ __global__ void k_mse(const float *Y, const float *T, float *dY, int64_t n, int 
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-// db[j] = sum over rows of dZ[:, j] (one thread per column, rows in order)
-__global__ void k_colsum(const float *dZ, float *db, int64_t n, int N) {
+// part[z][j] = sum of dZ[i][j] over rows i of chunk z (rows in order)
+__global__ void k_colsum_partial(const float *dZ, int64_t n, int N, int64_t chunk, float *part) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    double s = 0.0;
-    for (int64_t i = 0; i < n; i++) s += dZ[i * N + j];
-    db[j] = (float)s;
+    const int64_t i0 = blockIdx.y * chunk, i1 = min(n, i0 + chunk);
+    float s = 0.f;
+    for (int64_t i = i0; i < i1; i++) s += dZ[i * N + j];
+    part[(int64_t)blockIdx.y * N + j] = s;
+}
+
+// out[i] = sum over z of part[z stride + i], z in order
+__global__ void k_reduce_splits(const float *part, int nsplit, int64_t stride, int64_t count, float *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int z = 0; z < nsplit; z++) s += part[z * stride + i];
+        out[i] = (float)s;
+    }
 }
 
 __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
@@ -171,7 +200,12 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, 
 
 // Raw stencil features of sample points (global depth indices; NULL = all
 // points in order), columns ragged with offsets doff: ln T, ln n_e, ln n_H and
-// v_z / 10 km/s at k-4 .. k+4, clamped to the column (edge replication).
+// v_z / 10 km/s at the depth offsets kStencilOffset from the point, clamped to
+// the column (edge replication).  The offsets grow geometrically so that the
+// nine points see both the local gradients and the column's structure a few
+// hundred points away, including how far the point lies from either end.
+__constant__ int kStencilOffset[kStencil] = {-128, -32, -8, -2, 0, 2, 8, 32, 128};
+
 __global__ void k_features(const int64_t *doff, int64_t n_columns, const double *T, const double *ne,
                            const double *nH, const double *vz, const int64_t *samples, int64_t n, float *out) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
@@ -182,11 +216,11 @@ __global__ void k_features(const int64_t *doff, int64_t n_columns, const double 
             if (doff[mid] <= g) lo = mid; else hi = mid - 1;
         }
         const int64_t g0 = doff[lo], N = doff[lo + 1] - g0, k = g - g0;
-        for (int d = -4; d <= 4; d++) {
-            int64_t kk = k + d;
+        for (int j = 0; j < kStencil; j++) {
+            int64_t kk = k + kStencilOffset[j];
             kk = kk < 0 ? 0 : (kk >= N ? N - 1 : kk);
             const int64_t q = g0 + kk;
-            float *f = out + s * kFeat + (d + 4) * 4;
+            float *f = out + s * kFeat + j * 4;
             f[0] = (float)log(T[q]);
             f[1] = (float)log(ne[q]);
             f[2] = (float)log(nH[q]);
@@ -266,6 +300,7 @@ struct rh15d_mlp {
     int64_t cap = 0;
     float *x = nullptr;                     // normalised inputs [cap][36]
     std::vector<float *> Z, H, dH;          // per layer
+    float *wpart = nullptr, *bpart = nullptr;  // split-K partial gradients
     double *partial = nullptr;              // reductions
     int dev = 0;
 };
@@ -277,8 +312,11 @@ void free_acts(rh15d_mlp *p) {
     for (auto *q : p->Z) (void)hipFree(q);
     for (auto *q : p->H) (void)hipFree(q);
     for (auto *q : p->dH) (void)hipFree(q);
+    (void)hipFree(p->wpart);
+    (void)hipFree(p->bpart);
     p->Z.clear(); p->H.clear(); p->dH.clear();
     p->x = nullptr;
+    p->wpart = p->bpart = nullptr;
     p->cap = 0;
 }
 
@@ -294,31 +332,75 @@ int ensure_cap(rh15d_mlp *p, int64_t n) {
         HIP_TRY(hipMalloc(&p->H[l], bytes));
         HIP_TRY(hipMalloc(&p->dH[l], bytes));
     }
+    size_t mn = 0, nmax = 0;
+    for (int l = 0; l < L; l++) {
+        mn = std::max(mn, (size_t)p->dims[l] * p->dims[l + 1]);
+        nmax = std::max(nmax, (size_t)p->dims[l + 1]);
+    }
+    HIP_TRY(hipMalloc(&p->wpart, kMaxSplit * mn * sizeof(float)));
+    HIP_TRY(hipMalloc(&p->bpart, kMaxSplit * nmax * sizeof(float)));
     p->cap = n;
     return RH15D_OK;
 }
 
-void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, float *C, int ldc,
-          bool acc, hipStream_t st) {
-    const dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM);
-    if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
-    else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
-    else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
-    else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, (int)acc);
+struct Epilogue {
+    const float *bias = nullptr;  // + bias[n]
+    const float *dact = nullptr;  // * silu'(dact[m][n])
+    float *Z = nullptr, *H = nullptr;
+    bool act = false;             // H = silu(Z)
+    bool split_a = false;         // A as BF16 hi + lo (forward pass)
+};
+
+void gemm(bool ta, bool tb, int M, int N, int K, const float *A, int lda, const float *B, int ldb, const Epilogue &e,
+          int ldc, hipStream_t st, int nsplit = 1, int kchunk = 0, int64_t zstride = 0) {
+    const dim3 grid((N + kBN - 1) / kBN, (M + kBM - 1) / kBM, nsplit);
+    const int a = e.act ? 1 : 0;
+    if (nsplit == 1) kchunk = K;
+#define RH15D_GEMM(TA_, TB_, SA_)                                                                                \
+    hipLaunchKernelGGL((k_gemm<TA_, TB_, SA_>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, e.bias, e.dact, \
+                       e.Z, e.H, ldc, a, kchunk, zstride)
+    if (!ta && !tb) {
+        if (e.split_a) RH15D_GEMM(false, false, true);
+        else RH15D_GEMM(false, false, false);
+    } else if (ta && !tb) RH15D_GEMM(true, false, false);
+    else if (!ta && tb) RH15D_GEMM(false, true, false);
+    else RH15D_GEMM(true, true, false);
+#undef RH15D_GEMM
 }
 
-// Forward pass of n samples (raw features in HBM) into p->Z / p->H; the last
-// layer's output lands in p->Z.back().
-void forward(rh15d_mlp *p, const float *feat, int64_t n, hipStream_t st) {
+// Split of the sample dimension for the weight-gradient products, whose
+// outputs are small (fan_in x fan_out) and whose sums run over all samples:
+// enough workgroups to fill the chip, chunks a multiple of the K tile.
+void split_for(int64_t n, int M, int N, int *nsplit, int *chunk) {
+    const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    int s = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
+    s = (int)std::min<int64_t>(s, std::max<int64_t>(1, n / 128));
+    int64_t c = (n + s - 1) / s;
+    c = (c + kBK - 1) / kBK * kBK;
+    *chunk = (int)c;
+    *nsplit = (int)((n + c - 1) / c);
+}
+
+// Forward pass of n samples (raw features in HBM).  Training keeps every
+// layer's pre-activation Z and activation H for the backward pass and leaves
+// the output in p->Z.back(); inference keeps only H (the bias and SiLU are
+// applied in the GEMM epilogue) and writes the output layer to `out`.
+void forward(rh15d_mlp *p, const float *feat, int64_t n, bool training, float *out, hipStream_t st) {
     hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n * kFeat)), dim3(256), 0, st, feat, p->mean, p->istd, p->x, n);
     const int L = (int)p->dims.size() - 1;
     const float *in = p->x;
     for (int l = 0; l < L; l++) {
         const int K = p->dims[l], N = p->dims[l + 1];
-        gemm(false, false, (int)n, N, K, in, K, p->params + p->w_off[l], N, p->Z[l], N, false, st);
         const bool last = l == L - 1;
-        hipLaunchKernelGGL(k_bias_act, dim3(blocks_for(n * N)), dim3(256), 0, st, p->Z[l], p->params + p->b_off[l],
-                           last ? nullptr : p->H[l], n, N, last ? 0 : 1);
+        float *Z = training ? p->Z[l] : nullptr;
+        float *H = last ? (training ? nullptr : out) : p->H[l];
+        Epilogue e;
+        e.bias = p->params + p->b_off[l];
+        e.Z = Z;
+        e.H = H;
+        e.act = !last;
+        e.split_a = true;
+        gemm(false, false, (int)n, N, K, in, K, p->params + p->w_off[l], N, e, N, st);
         in = p->H[l];
     }
 }
@@ -330,13 +412,27 @@ int backward(rh15d_mlp *p, const float *target, int64_t n, float *loss, hipStrea
     hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, p->Z[L - 1], target, p->dH[L - 1], n, nout, p->partial);
     for (int l = L - 1; l >= 0; l--) {
         const int K = p->dims[l], N = p->dims[l + 1];
-        float *dZ = p->dH[l];
-        if (l < L - 1) hipLaunchKernelGGL(k_silu_back, dim3(blocks_for(n * N)), dim3(256), 0, st, p->Z[l], dZ, n * N);
+        const float *dZ = p->dH[l];  // includes silu'(Z[l]) for hidden layers (epilogue below)
         const float *in = l == 0 ? p->x : p->H[l - 1];
-        // dW = in^T dZ, db = column sums of dZ
-        gemm(true, false, K, N, (int)n, in, K, dZ, N, p->grads + p->w_off[l], N, false, st);
-        hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, dZ, p->grads + p->b_off[l], n, N);
-        if (l > 0) gemm(false, true, (int)n, K, N, dZ, N, p->params + p->w_off[l], N, p->dH[l - 1], K, false, st);
+        // dW = in^T dZ and db = column sums of dZ, split over the samples, then reduced in order
+        int ns, chunk;
+        split_for(n, K, N, &ns, &chunk);
+        Epilogue ew;
+        ew.Z = p->wpart;
+        gemm(true, false, K, N, (int)n, in, K, dZ, N, ew, N, st, ns, chunk, (int64_t)K * N);
+        hipLaunchKernelGGL(k_colsum_partial, dim3((N + 255) / 256, ns), dim3(256), 0, st, dZ, n, N, (int64_t)chunk,
+                           p->bpart);
+        hipLaunchKernelGGL(k_reduce_splits, dim3(blocks_for((int64_t)K * N, 4096)), dim3(256), 0, st, p->wpart, ns,
+                           (int64_t)K * N, (int64_t)K * N, p->grads + p->w_off[l]);
+        hipLaunchKernelGGL(k_reduce_splits, dim3(blocks_for(N)), dim3(256), 0, st, p->bpart, ns, (int64_t)N, (int64_t)N,
+                           p->grads + p->b_off[l]);
+        if (l > 0) {
+            // dZ[l-1] = (dZ W^T) * silu'(Z[l-1])
+            Epilogue eb;
+            eb.dact = p->Z[l - 1];
+            eb.Z = p->dH[l - 1];
+            gemm(false, true, (int)n, K, N, dZ, N, p->params + p->w_off[l], N, eb, K, st);
+        }
     }
     if (loss) {
         std::vector<double> part(nb);
@@ -464,8 +560,13 @@ int rh15d_mlp_set_normalization(rh15d_mlp *p, const float *mean, const float *st
 }
 
 int rh15d_mlp_features(const rh15d_columns *cols, const int64_t *samples, int64_t n, float *feat, void *stream) {
-    if (!cols || !feat || n < 0 || !cols->depth_offset || !cols->T || !cols->n_e || !cols->n_H || !cols->v_z) {
-        set_error("null argument"); return RH15D_EINVAL;
+    if (!cols || !feat || n < 0 || cols->n_columns < 1 || !cols->depth_offset || !cols->T || !cols->n_e || !cols->n_H ||
+        !cols->v_z) {
+        set_error("null argument or no columns"); return RH15D_EINVAL;
+    }
+    if (!samples && n != cols->depth_offset[cols->n_columns]) {
+        set_error("without sample indices n must be the total depth %lld", (long long)cols->depth_offset[cols->n_columns]);
+        return RH15D_EINVAL;
     }
     if (n == 0) return RH15D_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -501,8 +602,7 @@ int rh15d_mlp_forward(rh15d_mlp *p, const float *feat, int64_t n, float *out, vo
     const int nout = p->dims.back();
     for (int64_t s0 = 0; s0 < n; s0 += kChunk) {
         const int64_t m = std::min<int64_t>(kChunk, n - s0);
-        forward(p, feat + s0 * kFeat, m, st);
-        HIP_TRY(hipMemcpyAsync(out + s0 * nout, p->Z.back(), m * nout * sizeof(float), hipMemcpyDeviceToDevice, st));
+        forward(p, feat + s0 * kFeat, m, false, out + s0 * nout, st);
     }
     HIP_TRY(hipGetLastError());
     return RH15D_OK;
@@ -513,7 +613,7 @@ int rh15d_mlp_gradients(rh15d_mlp *p, const float *feat, const float *target, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = ensure_cap(p, n);
     if (rc != RH15D_OK) return rc;
-    forward(p, feat, n, st);
+    forward(p, feat, n, true, nullptr, st);
     return backward(p, target, n, loss, st);
 }
 

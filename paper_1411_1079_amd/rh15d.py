@@ -24,6 +24,10 @@ CONVERGED, MAX_ITER, NONFINITE, SINGULAR = 0, 1, 2, 3
 EXPORTS = (
     "rh15d_load_atom", "rh15d_free_atom", "rh15d_atom_get_info", "rh15d_atom_lambda", "rh15d_default_options",
     "rh15d_workspace_size", "rh15d_solve_columns", "rh15d_last_error", "rh15d_last_stats",
+    "rh15d_departures", "rh15d_pops_from_departures", "rh15d_mlp_create", "rh15d_mlp_free", "rh15d_mlp_n_params",
+    "rh15d_mlp_get_params", "rh15d_mlp_set_params", "rh15d_mlp_get_grads", "rh15d_mlp_get_normalization",
+    "rh15d_mlp_set_normalization", "rh15d_mlp_fit_normalization", "rh15d_mlp_features", "rh15d_mlp_forward",
+    "rh15d_mlp_gradients", "rh15d_mlp_train_step",
 )
 
 
@@ -77,6 +81,23 @@ def lib():
                                           C.c_void_p, C.c_size_t, C.c_void_p]
         L.rh15d_last_error.restype = C.c_char_p
         L.rh15d_last_stats.argtypes = [C.POINTER(Stats)]
+        vp, fp = C.c_void_p, C.POINTER(C.c_float)
+        L.rh15d_departures.argtypes = [vp, C.POINTER(Columns), vp, vp, vp]
+        L.rh15d_pops_from_departures.argtypes = [vp, C.POINTER(Columns), vp, C.c_double, vp, vp]
+        L.rh15d_mlp_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.rh15d_mlp_free.argtypes = [vp]
+        L.rh15d_mlp_free.restype = None
+        L.rh15d_mlp_n_params.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.rh15d_mlp_get_params.argtypes = [vp, fp]
+        L.rh15d_mlp_set_params.argtypes = [vp, fp]
+        L.rh15d_mlp_get_grads.argtypes = [vp, fp]
+        L.rh15d_mlp_get_normalization.argtypes = [vp, fp, fp]
+        L.rh15d_mlp_set_normalization.argtypes = [vp, fp, fp]
+        L.rh15d_mlp_fit_normalization.argtypes = [vp, vp, C.c_int64, vp]
+        L.rh15d_mlp_features.argtypes = [C.POINTER(Columns), vp, C.c_int64, vp, vp]
+        L.rh15d_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.rh15d_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, fp, vp]
+        L.rh15d_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, fp, vp]
         _lib = L
     return _lib
 
@@ -231,3 +252,136 @@ def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, **o
     status, spectrum, psi_star)."""
     o = default_options(**opts)
     return Solver(atom, dc, o, want_spectrum=want_spectrum, want_psi=want_psi).run().result()
+
+
+def _stream(stream=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+def departures(atom: Atom, dc: DeviceColumns, pops, out=None, stream=None):
+    """ln(n_i / n*_i) of populations pops (CUDA float64 [total_depth][L])."""
+    import torch
+    if out is None:
+        out = torch.empty((dc.total_depth, atom.n_levels), dtype=torch.float32, device=pops.device)
+    assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == dc.total_depth * atom.n_levels
+    assert pops.dtype == torch.float64 and pops.is_contiguous() and pops.numel() == out.numel()
+    _check(lib().rh15d_departures(atom._h, C.byref(_cols_struct(dc)), C.c_void_p(pops.data_ptr()),
+                                  C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def pops_from_departures(atom: Atom, dc: DeviceColumns, log_b, shrink=0.0, out=None, stream=None):
+    """Start populations n_i = exp(l_i) n*_i renormalised per point, l_i =
+    log_b_i shrunk toward 0 by `shrink` (non-finite predictions give LTE,
+    others are clamped to |ln b| <= 50 first)."""
+    import torch
+    if out is None:
+        out = torch.empty((dc.total_depth, atom.n_levels), dtype=torch.float64, device=log_b.device)
+    assert log_b.dtype == torch.float32 and log_b.is_contiguous() and log_b.numel() == dc.total_depth * atom.n_levels
+    assert out.dtype == torch.float64 and out.is_contiguous() and out.numel() == log_b.numel()
+    _check(lib().rh15d_pops_from_departures(atom._h, C.byref(_cols_struct(dc)), C.c_void_p(log_b.data_ptr()),
+                                            float(shrink), C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+N_FEATURES = 36
+
+
+class MLP:
+    """The start-solution network (rh15d_mlp_*): 36 -> n_layers x n_hidden
+    (SiLU) -> n_out, trained and evaluated by the library's kernels."""
+
+    def __init__(self, n_hidden=256, n_layers=3, n_out=6, seed=0):
+        h = C.c_void_p()
+        _check(lib().rh15d_mlp_create(n_hidden, n_layers, n_out, seed, C.byref(h)))
+        self._h = h
+        self.n_hidden, self.n_layers, self.n_out = n_hidden, n_layers, n_out
+        n = C.c_int64()
+        _check(lib().rh15d_mlp_n_params(h, C.byref(n)))
+        self.n_params = n.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.rh15d_mlp_free(self._h)
+            self._h = None
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().rh15d_mlp_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(lib().rh15d_mlp_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_grads(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().rh15d_mlp_get_grads(self._h, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def get_normalization(self):
+        m, s = np.empty(N_FEATURES, np.float32), np.empty(N_FEATURES, np.float32)
+        _check(lib().rh15d_mlp_get_normalization(self._h, m.ctypes.data_as(C.POINTER(C.c_float)),
+                                                 s.ctypes.data_as(C.POINTER(C.c_float))))
+        return m, s
+
+    def set_normalization(self, mean, std):
+        m = np.ascontiguousarray(mean, np.float32)
+        s = np.ascontiguousarray(std, np.float32)
+        _check(lib().rh15d_mlp_set_normalization(self._h, m.ctypes.data_as(C.POINTER(C.c_float)),
+                                                 s.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def fit_normalization(self, feats, stream=None):
+        _check(lib().rh15d_mlp_fit_normalization(self._h, C.c_void_p(feats.data_ptr()), feats.shape[0],
+                                                 _stream(stream)))
+
+    @staticmethod
+    def features(dc: DeviceColumns, samples=None, out=None, stream=None):
+        """Raw stencil features (CUDA float32 [n][36]) of sample points
+        (CUDA int64 global depth indices) or of every point."""
+        import torch
+        n = dc.total_depth if samples is None else samples.numel()
+        if samples is not None:
+            assert samples.dtype == torch.int64 and samples.is_contiguous()
+        if out is None:
+            out = torch.empty((n, N_FEATURES), dtype=torch.float32, device=dc.z.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == n * N_FEATURES
+        _check(lib().rh15d_mlp_features(C.byref(_cols_struct(dc)),
+                                        C.c_void_p(samples.data_ptr()) if samples is not None else None,
+                                        n, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def forward(self, feats, out=None, stream=None):
+        import torch
+        assert feats.dtype == torch.float32 and feats.is_contiguous() and feats.shape[-1] == N_FEATURES
+        n = feats.shape[0]
+        if out is None:
+            out = torch.empty((n, self.n_out), dtype=torch.float32, device=feats.device)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == n * self.n_out
+        _check(lib().rh15d_mlp_forward(self._h, C.c_void_p(feats.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                       _stream(stream)))
+        return out
+
+    def _check_batch(self, feats, target):
+        import torch
+        assert feats.dtype == torch.float32 and feats.is_contiguous() and feats.shape[-1] == N_FEATURES
+        assert target.dtype == torch.float32 and target.is_contiguous()
+        assert target.numel() == feats.shape[0] * self.n_out
+
+    def gradients(self, feats, target, stream=None) -> float:
+        self._check_batch(feats, target)
+        loss = C.c_float()
+        _check(lib().rh15d_mlp_gradients(self._h, C.c_void_p(feats.data_ptr()), C.c_void_p(target.data_ptr()),
+                                         feats.shape[0], C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def train_step(self, feats, target, lr, want_loss=False, stream=None):
+        self._check_batch(feats, target)
+        loss = C.c_float()
+        _check(lib().rh15d_mlp_train_step(self._h, C.c_void_p(feats.data_ptr()), C.c_void_p(target.data_ptr()),
+                                          feats.shape[0], float(lr), C.byref(loss) if want_loss else None,
+                                          _stream(stream)))
+        return loss.value if want_loss else None

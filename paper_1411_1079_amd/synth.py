@@ -326,7 +326,9 @@ def _grf(rng, shape, spacing, corr):
     filt = np.exp(-0.5 * k2 * corr ** 2)
     f = np.fft.ifftn(np.fft.fftn(noise) * filt).real
     f -= f.mean()
-    return f / f.std()
+    sd = f.std()
+    # a domain much smaller than the kernel keeps only the mean: no variation
+    return f / sd if sd > 1e-9 * noise.std() else np.zeros(shape)
 
 
 CUBE_DZ_KM = 7.5
@@ -395,3 +397,27 @@ def write_atoms(directory: str) -> dict:
         "two_level": write_two_level_atom(os.path.join(directory, "two_level.atom")),
         "h6": write_h6_atom(os.path.join(directory, "h6.atom"), hminus_calibration()),
     }
+
+
+def mlp_params(dims, seed: int, weight_scale: float = 1.0, bias_std: float = 0.1) -> np.ndarray:
+    """Seeded parameters of a dense network with layer widths `dims`, flat in
+    the library's layout (per layer: weights [fan_in][fan_out] row-major,
+    then biases): weights uniform within +-sqrt(6 / fan_in) * weight_scale,
+    biases normal with standard deviation bias_std.  FP32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fi, fo in zip(dims[:-1], dims[1:]):
+        parts.append(rng.uniform(-1.0, 1.0, fi * fo) * math.sqrt(6.0 / fi) * weight_scale)
+        parts.append(rng.normal(0.0, bias_std, fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_features(seed: int, n: int) -> np.ndarray:
+    """Seeded raw feature rows shaped like the stencil features of the cube:
+    ln T around 8.8, ln n_e around 28, ln n_H around 37, v_z / 10 km/s in
+    [-1, 1], repeated over the 9 stencil points with small offsets.  FP32."""
+    rng = np.random.default_rng(seed)
+    base = np.stack([rng.normal(8.8, 0.35, n), rng.normal(28.0, 2.0, n), rng.normal(37.0, 3.0, n),
+                     rng.uniform(-1.0, 1.0, n)], axis=1)
+    rows = [base + rng.normal(0.0, 0.05, (n, 4)) * np.array([1.0, 1.0, 1.0, 0.2]) for _ in range(9)]
+    return np.concatenate(rows, axis=1).astype(np.float32)

@@ -62,3 +62,22 @@ def tiny_column(n_depth=8, vz=3.0e3):
     ne = 1.0e-3 * nH
     v = vz * np.linspace(1.0, -1.0, n_depth)
     return dict(z=z, T=T, n_e=ne, n_H=nH, v_z=v, v_turb=np.full(n_depth, 1.0e3))
+
+
+def oracle_lockstep_rtol(atom, col, floor=1e-10, **kw):
+    """Relative tolerance for element-by-element parity of one column with
+    the FP64 oracle: `floor`, or ten times the oracle's own change when its
+    input temperatures are perturbed by about one unit in the last place,
+    whichever is larger.  Columns whose iteration amplifies rounding (Ng
+    steps on nearly parallel iterates, weak collisions) cannot be reproduced
+    by any other summation order more closely than that."""
+    from oracle import oracle as O
+    r = O.solve_column(atom, col, want_psi=True, **kw)
+    c2 = dict(col)
+    c2["T"] = col["T"] * (1.0 + 2e-16 * np.cos(np.arange(len(col["T"]))))
+    r2 = O.solve_column(atom, c2, want_psi=True, **kw)
+    if r2["n_iter"] != r["n_iter"]:
+        return r, 1e-6
+    s = max(float(np.max(np.abs(r2["pops"] / r["pops"] - 1.0))),
+            float(np.max(np.abs(r2["spectrum"] / r["spectrum"] - 1.0))))
+    return r, max(floor, 10.0 * s)

@@ -1,0 +1,215 @@
+"""The start-solution network's kernels (rh15d_mlp_*, departures) through
+the C ABI against the FP64 NumPy reference.
+
+Tolerances.  The forward pass multiplies BF16-rounded weights (unit
+roundoff u = 2^-8) by activations carried as two BF16 terms (error below
+u_a = 2^-16 relative) and accumulates in FP32.  For one layer z = h W + b
+the computed value differs from the exact one by at most
+    (1 + u + u_a) |W|^T |dh| + (u + 2 u_a + K 2^-24) |h|^T |W| + 2^-23 |z|,
+dh being the error already in the layer's input; SiLU has slope below 1.1.
+The forward test propagates this bound through the network from the
+oracle's own activations and requires every output to lie within it.  The
+backward products round both operands to BF16; the gradients chain up to
+2 L such products with sums over the samples, whose rounding errors are
+independent and of either sign; they are held to a
+norm-wise relative error of 5e-2 per layer and a cosine similarity of
+0.998 with the FP64 gradient."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from oracle import oracle as O
+from paper_1411_1079_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U_BF16 = 2.0 ** -8
+U_SPLIT = 2.0 ** -16
+
+
+def _rh():
+    from paper_1411_1079_amd import rh15d
+    return rh15d
+
+
+def _net(dims, seed, **kw):
+    rh = _rh()
+    print(f"[gpu] mlp dims={dims} seed={seed} {kw}", flush=True)
+    net = rh.MLP(dims[1], len(dims) - 2, dims[-1], seed=0)
+    p = synth.mlp_params(dims, seed, **kw)
+    net.set_params(p)
+    return net, p.astype(np.float64)
+
+
+def _forward_bound(p, dims, mean, std, x):
+    """Oracle output and the elementwise bound of the BF16/FP32 evaluation."""
+    layers = OM.unpack(p, dims)
+    h = (x - mean) / std
+    dh = 4 * 2.0 ** -24 * np.abs(h)
+    for li, (W, b) in enumerate(layers):
+        K = W.shape[0]
+        z = h @ W + b
+        dz = (1 + U_BF16 + U_SPLIT) * (dh @ np.abs(W)) \
+            + (U_BF16 + 2 * U_SPLIT + K * 2.0 ** -24) * (np.abs(h) @ np.abs(W)) + 2.0 ** -23 * np.abs(z) + 1e-30
+        if li == len(layers) - 1:
+            return z, dz
+        h = OM.silu(z)
+        dh = 1.1 * dz + 1e-5 * np.abs(h) + 1e-7
+
+
+@pytest.mark.parametrize("dims,n", [(OM.dims_of(256, 3, 6), 1000), (OM.dims_of(40, 2, 6), 77),
+                                    (OM.dims_of(256, 3, 6), 1), (OM.dims_of(100, 1, 3), 4099)])
+def test_forward_within_bf16_bound(dims, n):
+    net, p = _net(dims, seed=n)
+    x = synth.mlp_features(n + 1, n)
+    mean, std = OM.normalization(x.astype(np.float64))
+    mean, std = mean.astype(np.float32), std.astype(np.float32)
+    net.set_normalization(mean, std)
+    y = net.forward(torch.as_tensor(x).cuda()).cpu().numpy().astype(np.float64)
+    ref, bound = _forward_bound(p, dims, mean.astype(np.float64), std.astype(np.float64), x.astype(np.float64))
+    err = np.abs(y - ref)
+    print(f"max err/bound {np.max(err / bound):.3g}, median {np.median(err / bound):.3g}, "
+          f"rel Frobenius {np.linalg.norm(y - ref) / np.linalg.norm(ref):.3g}", flush=True)
+    assert np.all(err <= bound)
+    assert np.linalg.norm(y - ref) <= 1e-2 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("dims,n", [(OM.dims_of(256, 3, 6), 1000), (OM.dims_of(40, 2, 6), 77)])
+def test_gradients_against_fp64(dims, n):
+    rh = _rh()
+    net, p = _net(dims, seed=7 + n)
+    x = synth.mlp_features(n + 2, n)
+    mean, std = OM.normalization(x.astype(np.float64))
+    net.set_normalization(mean.astype(np.float32), std.astype(np.float32))
+    mean, std = mean.astype(np.float32).astype(np.float64), std.astype(np.float32).astype(np.float64)
+    # a smooth target (a second network) plus noise
+    teacher = synth.mlp_params(dims, seed=99).astype(np.float64)
+    t = OM.forward(teacher, dims, mean, std, x.astype(np.float64))
+    t = (t + np.random.default_rng(n).normal(0, 0.3, t.shape)).astype(np.float32)
+    loss = net.gradients(torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda())
+    g = net.get_grads().astype(np.float64)
+    lref, gref = OM.loss_and_grad(p, dims, mean, std, x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lref) <= 2e-2 * lref, (loss, lref)
+    o = 0
+    for li, (fi, fo) in enumerate(zip(dims[:-1], dims[1:])):
+        for name, sz in (("W", fi * fo), ("b", fo)):
+            a, r = g[o:o + sz], gref[o:o + sz]
+            o += sz
+            rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+            cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+            print(f"layer {li} {name}: rel {rel:.3g} cos {cos:.6f}", flush=True)
+            assert rel <= 5e-2 and cos >= 0.998, (li, name, rel, cos)
+    assert o == net.n_params == OM.n_params(dims)
+
+
+def test_adam_first_step_closed_form():
+    """From fresh moments the first Adam step moves each parameter by
+    lr g / (|g| + eps) exactly (bias correction), g being the gradient of
+    that step."""
+    dims = OM.dims_of(64, 2, 6)
+    net, p = _net(dims, seed=5)
+    x = synth.mlp_features(8, 512)
+    mean, std = OM.normalization(x.astype(np.float64))
+    net.set_normalization(mean.astype(np.float32), std.astype(np.float32))
+    t = np.random.default_rng(3).normal(size=(512, 6)).astype(np.float32)
+    lr = 1e-3
+    w0 = net.get_params().astype(np.float64)
+    net.train_step(torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda(), lr)
+    torch.cuda.synchronize()
+    w1 = net.get_params().astype(np.float64)
+    g = net.get_grads().astype(np.float64)
+    expect = -lr * g / (np.abs(g) + 1e-8)
+    tol = 4 * np.spacing(np.abs(w0).astype(np.float32)).astype(np.float64) + 1e-4 * lr
+    assert np.all(np.abs((w1 - w0) - expect) <= tol)
+    # and the gradient itself is the FP64 one (signs of the large components)
+    _, gref = OM.loss_and_grad(p, dims, mean.astype(np.float32).astype(np.float64),
+                               std.astype(np.float32).astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    big = np.abs(gref) > 0.1 * np.abs(gref).max()
+    assert np.all(np.sign(w1 - w0)[big] == -np.sign(gref)[big])
+
+
+def test_training_tracks_fp64_adam():
+    """The same full-batch Adam run on the GPU and in FP64: both reduce the
+    loss by a large factor and end at comparable losses."""
+    dims = OM.dims_of(64, 2, 6)
+    net, p = _net(dims, seed=21)
+    n = 2048
+    x = synth.mlp_features(22, n)
+    mean, std = OM.normalization(x.astype(np.float64))
+    net.set_normalization(mean.astype(np.float32), std.astype(np.float32))
+    mean, std = mean.astype(np.float32).astype(np.float64), std.astype(np.float32).astype(np.float64)
+    teacher = synth.mlp_params(dims, seed=23).astype(np.float64)
+    t = OM.forward(teacher, dims, mean, std, x.astype(np.float64)).astype(np.float32)
+    xt, tt = torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda()
+    adam = OM.Adam(p.size)
+    w = p.copy()
+    steps, lr = 300, 3e-3
+    l0 = OM.loss_and_grad(w, dims, mean, std, x.astype(np.float64), t.astype(np.float64))[0]
+    lg = None
+    for s in range(steps):
+        lr_s = lr * 0.5 * (1 + np.cos(np.pi * s / steps))
+        lg = net.train_step(xt, tt, lr_s, want_loss=(s == steps - 1))
+        _, gr = OM.loss_and_grad(w, dims, mean, std, x.astype(np.float64), t.astype(np.float64))
+        w = adam.step(w, gr, lr_s)
+    lo = OM.loss_and_grad(w, dims, mean, std, x.astype(np.float64), t.astype(np.float64))[0]
+    print(f"initial {l0:.4g}, fp64 final {lo:.4g}, gpu final {lg:.4g}", flush=True)
+    assert lo < 0.1 * l0 and lg < 0.1 * l0
+    assert 0.5 * lo - 1e-4 <= lg <= 2.0 * lo + 1e-4
+
+
+def test_features_and_normalization():
+    rh = _rh()
+    cube = synth.cube_columns(1, 64, 64)
+    cols = cube.select([0, 5, 17, 100, 255])
+    print(f"[gpu] features columns={cols.n_columns} points={int(cols.offset[-1])}", flush=True)
+    dc = rh.DeviceColumns.from_host(cols)
+    f = rh.MLP.features(dc).cpu().numpy()
+    ref = OM.features(cols.offset, cols.T, cols.n_e, cols.n_H, cols.v_z).astype(np.float32)
+    np.testing.assert_array_max_ulp(f, ref, maxulp=1)
+    s = np.array([0, 3, int(cols.offset[1]) - 1, int(cols.offset[1]), int(cols.offset[-1]) - 1], dtype=np.int64)
+    fs = rh.MLP.features(dc, torch.as_tensor(s).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(fs, f[s])
+    net = rh.MLP(16, 1, 6)
+    net.fit_normalization(torch.as_tensor(f).cuda())
+    m, sd = net.get_normalization()
+    mr, sr = OM.normalization(f.astype(np.float64))
+    np.testing.assert_allclose(m, mr, rtol=1e-6, atol=1e-6 * sr.max())
+    np.testing.assert_allclose(sd, sr, rtol=1e-5)
+
+
+def test_departures_against_oracle(atom_dir):
+    rh = _rh()
+    cols = synth.cfg2_columns(seed=5, n_columns=3)
+    a = O.Atom(atom_dir["h6"])
+    # weak collisions: departures far from zero
+    orc = [O.solve_column(a, cols.column(c), n_mu=5, tol=1e-6, max_iter=200, coll_scale=1e-3)
+           for c in range(cols.n_columns)]
+    pops = np.concatenate([r["pops"] for r in orc])
+    print(f"[gpu] departures points={pops.shape[0]}", flush=True)
+    atom = rh.Atom(atom_dir["h6"])
+    dc = rh.DeviceColumns.from_host(cols)
+    lb = rh.departures(atom, dc, torch.as_tensor(pops).cuda()).cpu().numpy()
+    ref = OM.departures(a, cols.T, cols.n_e, cols.n_H, pops)
+    assert np.abs(ref).max() > 1.0          # genuinely non-LTE
+    np.testing.assert_allclose(lb, ref, rtol=2.0 ** -23, atol=1e-11)
+    # back to populations from the same FP32 departures
+    lb_in = ref.astype(np.float32)
+    back = rh.pops_from_departures(atom, dc, torch.as_tensor(lb_in).cuda()).cpu().numpy()
+    np.testing.assert_allclose(back, OM.pops_from_departures(a, cols.T, cols.n_e, cols.n_H, lb_in), rtol=1e-12)
+    np.testing.assert_allclose(back, pops, rtol=1e-5)
+    for sh in (0.05, 0.7):
+        got = rh.pops_from_departures(atom, dc, torch.as_tensor(lb_in).cuda(), shrink=sh).cpu().numpy()
+        np.testing.assert_allclose(got, OM.pops_from_departures(a, cols.T, cols.n_e, cols.n_H, lb_in, shrink=sh),
+                                   rtol=1e-12)
+    # non-finite predictions act as LTE (ln b = 0); others are clamped to +-50
+    bad = lb_in.copy()
+    bad[0, 1], bad[3, :] = np.nan, np.inf
+    bad[5, 2], bad[6, 0] = 1e6, -1e6
+    sub = lb_in.copy()
+    sub[0, 1], sub[3, :] = 0.0, 0.0
+    sub[5, 2], sub[6, 0] = 50.0, -50.0
+    got = rh.pops_from_departures(atom, dc, torch.as_tensor(bad).cuda()).cpu().numpy()
+    want = rh.pops_from_departures(atom, dc, torch.as_tensor(sub).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    assert np.all(np.isfinite(got))

