@@ -174,6 +174,19 @@ def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols):
                        f"{dt:.1f} s wall on {threads} threads"), results
 
 
+def converged_oracle(atom_path, cols, results, n, threads):
+    """The oracle converged to 1e-10 on the first n columns of the CPU
+    sample (not timed): the reference of the 1e-3 accuracy criterion."""
+    import concurrent.futures
+
+    from oracle import oracle as O
+    a = O.Atom(atom_path)
+    picks = [c for c, _ in results[:n]]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(O.solve_column, a, cols.column(c), n_mu=5, tol=1e-10, max_iter=400) for c in picks]
+        return [(c, f.result()) for c, f in zip(picks, futs)]
+
+
 def accuracy(results, form, batches, cols):
     """Max relative difference of populations and emergent intensity between
     a GPU form and the oracle on the CPU-baseline sample."""
@@ -208,11 +221,26 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-max-columns", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--accuracy-columns", type=int, default=128,
+                    help="columns of the CPU sample also solved by the oracle to 1e-10")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES of device memory once (a reference kernel of known traffic for "
+                         "hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the columns are independent and this build runs on a single "
               "MI355X; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return
 
     import torch
 
@@ -237,6 +265,20 @@ def main():
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
 
+    tune = {}
+    if not args.no_autotune:
+        sample = cols.select(list(range(0, cols.n_columns, 8)))
+        dcs = rh.DeviceColumns.from_host(sample)
+        for f in forms:
+            key = "fp64" if FORMS[f]["precision"] == 0 else "fp32"
+            if key in tune:
+                continue
+            t = time.perf_counter()
+            tune[key] = rh.autotune(atom, dcs, n_mu=5, tol=1e-4, max_iter=200, **FORMS[f])
+            tune[key]["seconds"] = time.perf_counter() - t
+            tune[key]["sample_columns"] = sample.n_columns
+            log(f"autotune {key}: {tune[key]}")
+        del dcs
     net = train_info = None
     if "fp32w" in forms:
         log(f"train the start-solution network on cube seed {args.train_seed}")
@@ -313,14 +355,22 @@ def main():
         out["speedup_vs_plain_fp64"] = out["value"] / (res["fp64"]["converged"] / res["fp64"]["seconds"])
     if train_info is not None:
         out["network_training"] = train_info
+    if tune:
+        out["autotune"] = tune
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         base, results = cpu_baseline(atom_path, cols, batches, h["first_batch"], args.cpu_budget,
                                      args.cpu_max_columns)
         out["cpu_baseline"] = base
-        out["accuracy_vs_oracle"] = {f: accuracy(results, r, batches, cols) for f, r in res.items()}
+        out["accuracy_vs_oracle_same_stopping_rule"] = {f: accuracy(results, r, batches, cols) for f, r in res.items()}
         log(f"cpu baseline {base['value']:.2f} columns/s on {base['cores']} threads; accuracy "
-            f"{out['accuracy_vs_oracle']}")
+            f"{out['accuracy_vs_oracle_same_stopping_rule']}")
+        if args.accuracy_columns > 0:
+            t = time.perf_counter()
+            conv = converged_oracle(atom_path, cols, results, args.accuracy_columns, base["cores"])
+            out["accuracy_vs_converged_oracle"] = {f: accuracy(conv, r, batches, cols) for f, r in res.items()}
+            log(f"accuracy against the oracle converged to 1e-10 ({len(conv)} columns, "
+                f"{time.perf_counter() - t:.1f} s): {out['accuracy_vs_converged_oracle']}")
     print(json.dumps(out), flush=True)
 
 

@@ -184,6 +184,28 @@ int rh15d_solve_columns(const rh15d_atom *atom, const rh15d_columns *cols,
                         const rh15d_options *opt, const rh15d_outputs *out,
                         void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Autotuner of the formal-solution kernel's shape.  Columns are
+ * independent, so a pool of workers can take them in any grouping (Sec. 3.1,
+ * pool mode); on the GPU the grouping of rays into wavefronts is free too.
+ * For every candidate shape (sweep_mc in {1, 3, 5} dividing n_mu, times
+ * sweep_pack in {1, 2}) this solves the given columns twice with the other
+ * options of opt (the second solve timed with HIP events on hip_stream)
+ * and keeps the fastest for this device, opt->n_mu and opt->precision:
+ * later solves of the atom with sweep_mc = sweep_pack = 0 use it.  Results
+ * do not depend on the shape beyond the order of floating-point sums.
+ * Allocates its own device buffers and synchronises the stream; the
+ * columns should be a representative sample (a few thousand columns). */
+#define RH15D_TUNE_MAX 6
+typedef struct {
+    int sweep_mc, sweep_pack;                       /* the chosen shape */
+    int n_candidates;
+    int cand_mc[RH15D_TUNE_MAX], cand_pack[RH15D_TUNE_MAX];
+    double ms[RH15D_TUNE_MAX];                      /* timed solve of each candidate */
+} rh15d_tune_result;
+
+int rh15d_autotune(rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *opt, void *hip_stream,
+                   rh15d_tune_result *result);
+
 /* ------------------------------------------------------------------------
  * Learned start solution.  The start populations decide how many MALI
  * iterations a column needs (Sec. 2.3, "Different starting solutions").

@@ -1771,6 +1771,78 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     return result;
 }
 
+int rh15d_autotune(rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *opt, void *hip_stream,
+                   rh15d_tune_result *res) {
+    int rc = validate(atom, cols, opt);
+    if (rc != RH15D_OK) return rc;
+    if (!res || cols->n_columns < 1) { set_error("null result or no columns"); return RH15D_EINVAL; }
+    *res = rh15d_tune_result{};
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t P = cols->depth_offset[cols->n_columns], n = cols->n_columns;
+    const int L = atom->L;
+    double *pops = nullptr;
+    int32_t *nit = nullptr, *status = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int result = RH15D_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        if (result == RH15D_OK) set_error("%s: %s", what, hipGetErrorString(e));
+        result = RH15D_EDEVICE;
+    };
+    hipError_t e = hipMalloc(&pops, (size_t)P * L * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&nit, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&status, n * sizeof(int32_t));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) fail(e, "autotune set-up");
+    rh15d_outputs out{};
+    out.pops = pops;
+    out.n_iter = nit;
+    out.status = status;
+    double best = 1e300;
+    for (int mc : {1, 3, 5}) {
+        if (result != RH15D_OK || opt->n_mu % mc != 0) continue;
+        for (int pack : {1, 2}) {
+            if (result != RH15D_OK) break;
+            rh15d_options o = *opt;
+            o.sweep_mc = mc;
+            o.sweep_pack = pack;
+            o.profile = 0;
+            // first call builds the shape's tables and warms the caches; the second is timed
+            if ((rc = rh15d_solve_columns(atom, cols, &o, &out, nullptr, 0, hip_stream)) != RH15D_OK) { result = rc; break; }
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) { fail(e, "event"); break; }
+            if ((rc = rh15d_solve_columns(atom, cols, &o, &out, nullptr, 0, hip_stream)) != RH15D_OK) { result = rc; break; }
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) { fail(e, "event"); break; }
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) { fail(e, "event"); break; }
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { fail(e, "event"); break; }
+            const int c = res->n_candidates++;
+            res->cand_mc[c] = mc;
+            res->cand_pack[c] = pack;
+            res->ms[c] = ms;
+            if (ms < best) {
+                best = ms;
+                res->sweep_mc = mc;
+                res->sweep_pack = pack;
+            }
+        }
+    }
+    if (result == RH15D_OK) {
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) {
+            fail(e, "hipGetDevice");
+        } else {
+            std::lock_guard<std::mutex> lock(atom->mu_);
+            atom->tuned[{{dev, opt->n_mu}, opt->precision}] = SweepShape{res->sweep_mc, res->sweep_pack - 1};
+        }
+    }
+    (void)hipFree(pops);
+    (void)hipFree(nit);
+    (void)hipFree(status);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return result;
+}
+
 int rh15d_departures(const rh15d_atom *atom_c, const rh15d_columns *cols, const double *pops, float *log_b,
                      void *hip_stream) {
     if (!atom_c || !cols || !pops || !log_b || cols->n_columns < 0 || !cols->depth_offset || !cols->T || !cols->n_e ||

@@ -24,7 +24,7 @@ CONVERGED, MAX_ITER, NONFINITE, SINGULAR = 0, 1, 2, 3
 EXPORTS = (
     "rh15d_load_atom", "rh15d_free_atom", "rh15d_atom_get_info", "rh15d_atom_lambda", "rh15d_default_options",
     "rh15d_workspace_size", "rh15d_solve_columns", "rh15d_last_error", "rh15d_last_stats",
-    "rh15d_departures", "rh15d_pops_from_departures", "rh15d_mlp_create", "rh15d_mlp_free", "rh15d_mlp_n_params",
+    "rh15d_autotune", "rh15d_departures", "rh15d_pops_from_departures", "rh15d_mlp_create", "rh15d_mlp_free", "rh15d_mlp_n_params",
     "rh15d_mlp_get_params", "rh15d_mlp_set_params", "rh15d_mlp_get_grads", "rh15d_mlp_get_normalization",
     "rh15d_mlp_set_normalization", "rh15d_mlp_fit_normalization", "rh15d_mlp_features", "rh15d_mlp_forward",
     "rh15d_mlp_gradients", "rh15d_mlp_train_step",
@@ -55,6 +55,14 @@ class Stats(C.Structure):
                 ("sweep_flops", C.c_double), ("sweep_bytes", C.c_double)]
 
 
+TUNE_MAX = 6
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("sweep_mc", C.c_int), ("sweep_pack", C.c_int), ("n_candidates", C.c_int),
+                ("cand_mc", C.c_int * TUNE_MAX), ("cand_pack", C.c_int * TUNE_MAX), ("ms", C.c_double * TUNE_MAX)]
+
+
 class Outputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star")]
 
@@ -82,6 +90,7 @@ def lib():
         L.rh15d_last_error.restype = C.c_char_p
         L.rh15d_last_stats.argtypes = [C.POINTER(Stats)]
         vp, fp = C.c_void_p, C.POINTER(C.c_float)
+        L.rh15d_autotune.argtypes = [vp, C.POINTER(Columns), C.POINTER(Options), vp, C.POINTER(TuneResult)]
         L.rh15d_departures.argtypes = [vp, C.POINTER(Columns), vp, vp, vp]
         L.rh15d_pops_from_departures.argtypes = [vp, C.POINTER(Columns), vp, C.c_double, vp, vp]
         L.rh15d_mlp_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
@@ -252,6 +261,17 @@ def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, **o
     status, spectrum, psi_star)."""
     o = default_options(**opts)
     return Solver(atom, dc, o, want_spectrum=want_spectrum, want_psi=want_psi).run().result()
+
+
+def autotune(atom: Atom, dc: DeviceColumns, stream=None, **opts) -> dict:
+    """Time every formal-solution shape on the columns dc (solved twice
+    each) and keep the fastest for later solves with automatic shape."""
+    o = default_options(**opts)
+    r = TuneResult()
+    _check(lib().rh15d_autotune(atom._h, C.byref(_cols_struct(dc)), C.byref(o), _stream(stream), C.byref(r)))
+    n = r.n_candidates
+    return dict(sweep_mc=r.sweep_mc, sweep_pack=r.sweep_pack,
+                candidates=[dict(sweep_mc=r.cand_mc[i], sweep_pack=r.cand_pack[i], ms=r.ms[i]) for i in range(n)])
 
 
 def _stream(stream=None):

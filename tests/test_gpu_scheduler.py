@@ -116,3 +116,26 @@ def test_every_sweep_shape_matches_oracle(atom_dir, mc, pack):
         np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=rtol)
         np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=rtol)
         np.testing.assert_allclose(g["psi_star"][lo:hi].T, r["psi_star"], rtol=rtol, atol=1e-300)
+
+
+def test_autotune_picks_a_shape_used_by_automatic_solves(atom_dir):
+    """The autotuner times every shape, keeps the fastest, and a later
+    solve with the automatic shape gives exactly the chosen shape's
+    results."""
+    from paper_1411_1079_amd import rh15d as rh
+    cols = _mixed_columns()
+    kw = dict(n_mu=5, tol=1e-5, max_iter=60, scheduler=1, precision=1)
+    atom = rh.Atom(atom_dir["h6"])
+    dc = rh.DeviceColumns.from_host(cols)
+    print(f"[gpu] autotune on {cols.n_columns} columns", flush=True)
+    r = rh.autotune(atom, dc, **kw)
+    print(r, flush=True)
+    assert len(r["candidates"]) == 4            # mc 1 and 5 (3 does not divide n_mu = 5) x two packings
+    assert min(c["ms"] for c in r["candidates"]) == next(
+        c["ms"] for c in r["candidates"] if (c["sweep_mc"], c["sweep_pack"]) == (r["sweep_mc"], r["sweep_pack"]))
+    auto = rh.Solver(atom, dc, rh.default_options(**kw), want_spectrum=True).run().result()
+    chosen = rh.Solver(atom, dc, rh.default_options(sweep_mc=r["sweep_mc"], sweep_pack=r["sweep_pack"], **kw),
+                       want_spectrum=True).run().result()
+    torch.cuda.synchronize()
+    for k in ("pops", "spectrum", "n_iter", "status"):
+        np.testing.assert_array_equal(auto[k].cpu().numpy(), chosen[k].cpu().numpy())
