@@ -387,12 +387,6 @@ __device__ __forceinline__ R wave_total(R v) {
 }
 
 
-template <typename R>
-__device__ __forceinline__ const R *pops_row(const RunArgs &a, int64_t g, int64_t gc) {
-    if constexpr (sizeof(R) == 8) return a.pops + g * a.A.L;
-    else return a.popsf + gc * a.A.L;
-}
-
 // Uniform (per wavefront) description of the transitions a group touches.
 template <typename R, int NS>
 struct Slots {
@@ -409,24 +403,58 @@ struct Shared {
     R cvlu[NS], cvul[NS], cU[NS], ccht[NS];
 };
 
-template <typename R, int NS>
-__device__ __forceinline__ void shared_terms(const RunArgs &a, const Slots<R, NS> &sl, const R *alpha, int64_t g,
-                                             int64_t gc, R hnu_k, R two_hnu3, R lamfac, Shared<R, NS> &sh) {
-    const R *rec = reinterpret_cast<const R *>(a.rec) + gc * a.rec_w;
-    const R *n = pops_row<R>(a, g, gc);
-    const R x = hnu_k * rec[1];
+// Inputs of one depth point: per-depth record fields, populations and the
+// lane's profile values.  The sweep loads them one step ahead of their use,
+// so their latency overlaps the previous point's arithmetic.  The records
+// and populations are read through pointers the kernel receives as
+// separate restrict-qualified arguments: the compiler then knows the
+// sweep's own stores (rate sums) cannot change them, and the
+// wavefront-uniform reads become scalar loads.
+template <typename R, int NS, int MC>
+struct PointIn {
+    R invT, kbg, dz;
+    R gfac[NS];        // continuum slots: n_l*/n_u* exp(h nu / k T) of the record
+    R nl[NS], nu[NS];
+    R ph[NS][MC];      // line slots: profile values of the lane's angles
+};
+
+template <typename R, int NS, int MC>
+__device__ __forceinline__ void load_point(const R *__restrict__ recb, const R *__restrict__ popsb,
+                                           const R *__restrict__ phi, int rec_w, int L, int ray_cols,
+                                           const Slots<R, NS> &sl, const int *pb, int64_t g, int64_t gc,
+                                           int64_t gc_dz, PointIn<R, NS, MC> &p) {
+    const R *rec = recb + gc * rec_w;
+    p.invT = rec[1];
+    p.kbg = rec[2];
+    p.dz = recb[gc_dz * rec_w];
+    const R *n = popsb + (sizeof(R) == 8 ? g : gc) * L;
+    const R *phirow = phi + gc * ray_cols;
+#pragma unroll
+    for (int q = 0; q < NS; q++) {
+        p.nl[q] = n[sl.l[q]];
+        p.nu[q] = n[sl.u[q]];
+        p.gfac[q] = sl.kind[q] == 1 ? rec[kRecHead + sl.c[q]] : R(0);
+#pragma unroll
+        for (int r = 0; r < MC; r++) p.ph[q][r] = (sl.kind[q] == 0 && pb[q] >= 0) ? phirow[pb[q] + r] : R(0);
+    }
+}
+
+template <typename R, int NS, int MC>
+__device__ __forceinline__ void shared_terms(const PointIn<R, NS, MC> &in, const Slots<R, NS> &sl, const R *alpha,
+                                             R hnu_k, R two_hnu3, R lamfac, Shared<R, NS> &sh) {
+    const R x = hnu_k * in.invT;
     const R ex = d_exp(-x);  // exp(-h nu / k T)
     const R omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
     sh.B = two_hnu3 * ex * rcp(omx);
-    const R chibg = rec[2] * lamfac;
+    const R chibg = in.kbg * lamfac;
     sh.etabg = chibg * sh.B;
     R chi = chibg, eta = sh.etabg;
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        sh.nl[q] = n[sl.l[q]];
-        sh.nu[q] = n[sl.u[q]];
+        sh.nl[q] = in.nl[q];
+        sh.nu[q] = in.nu[q];
         if (sl.kind[q] == 1) {
-            const R gf = rec[kRecHead + sl.c[q]] * ex;
+            const R gf = in.gfac[q] * ex;
             sh.cvlu[q] = alpha[q];
             sh.cvul[q] = gf * alpha[q];
             sh.cU[q] = two_hnu3 * sh.cvul[q];
@@ -446,14 +474,14 @@ struct RayPt {
     R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
 };
 
-template <typename R, int NS>
-__device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R, NS> &sh, const R *phirow,
-                                          const int *pb, int r, RayPt<R, NS> &p) {
+template <typename R, int NS, int MC>
+__device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R, NS> &sh, const PointIn<R, NS, MC> &in,
+                                          int r, RayPt<R, NS> &p) {
     R chi = sh.chi0, eta = sh.eta0;
 #pragma unroll
     for (int q = 0; q < NS; q++) {
         if (sl.kind[q] == 0) {
-            const R ph = pb[q] >= 0 ? phirow[pb[q] + r] : R(0);
+            const R ph = in.ph[q][r];
             p.ph[q] = ph;
             p.vlu[q] = sl.cblu[q] * ph;
             p.vul[q] = sl.cbul[q] * ph;
@@ -502,19 +530,38 @@ __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi,
 }
 
 // Sums the lanes' contributions of one depth point over the wavefront and
-// stores them (lane 63 holds the totals).
+// stores them (lane 63 holds the totals).  Each DPP stage is applied to all
+// sums before the next, so the independent sums fill each other's DPP wait
+// states; the totals of a depth point are contiguous in `out` (point-major
+// layout [depth][key]) and lane 63 writes them under one branch.
 template <typename R, int NS, int MODE>
-__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int N, int k, int lane) {
+__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int n_keys, int k, int lane) {
     constexpr int NK = n_acc<NS, MODE>();
+    R v[NK];
 #pragma unroll
     for (int i = 0; i < NK; i++) {
-        R v = acc[i];
+        v[i] = acc[i];
         if constexpr (MODE == MODE_RATES) {
             const int q = i < 2 * NS ? (i % NS) : (i - 2 * NS) / (NS > 1 ? NS - 1 : 1);
-            v *= kapj[q];
+            v[i] *= kapj[q];
         }
-        v = wave_total(v);
-        if (lane == kWave - 1) out[(size_t)i * N + k] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x111, 0xf>(v[i]);
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x112, 0xf>(v[i]);
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x114, 0xf>(v[i]);
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x118, 0xf>(v[i]);
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x142, 0xa>(v[i]);
+#pragma unroll
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x143, 0xc>(v[i]);
+    if (lane == kWave - 1) {
+        R *o = out + (size_t)k * n_keys;
+#pragma unroll
+        for (int i = 0; i < NK; i++) o[i] = v[i];
     }
 }
 
@@ -523,7 +570,9 @@ __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out,
 // incoming radiation; up rays start at the bottom with the diffusion
 // approximation I = B + mu dB/dtau.
 template <typename R, int MODE, int NS, int MC>
-__device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane) {
+__device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane, const R *__restrict__ rec,
+                                            const R *__restrict__ phi, const R *__restrict__ popsb,
+                                            R *__restrict__ part) {
     const DevAtom &A = a.A;
     const ColGeom cg = geom(a, slot);
     const int64_t g0 = cg.g0;
@@ -568,33 +617,38 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         invmu[r] = R(1) / mu[r];
         wmu[r] = static_cast<R>(A.wmu[m0 + r]);
     }
-    R *out = reinterpret_cast<R *>(a.part) + gc0 * A.n_keys + (size_t)key_off * N;
-    const R *rec = reinterpret_cast<const R *>(a.rec);
-    const R *phi = reinterpret_cast<const R *>(a.phi);
+    R *out = part + gc0 * A.n_keys + key_off;
+    const int rec_w = a.rec_w, L = A.L, n_keys = A.n_keys;
     constexpr int NK = n_acc<NS, MODE>();
     const int step = s_dir == 0 ? 1 : -1;
     int k = s_dir == 0 ? 0 : N - 1;
     R I[MC], chi_p[MC], S_p[MC];
     R acc[NK];
+    const int ray_cols = A.ray_cols;
 #pragma unroll
     for (int i = 0; i < NK; i++) acc[i] = R(0);
     {
+        PointIn<R, NS, MC> in0;
+        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k, gc0 + k, gc0 + k, in0);
         Shared<R, NS> sh;
-        shared_terms<R, NS>(a, sl, alpha, g0 + k, gc0 + k, hnu_k, two_hnu3, lamfac, sh);
+        shared_terms<R, NS, MC>(in0, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
+        PointIn<R, NS, MC> in2;
         Shared<R, NS> sh2;
         R dzb = R(0);
         if (s_dir != 0) {
-            shared_terms<R, NS>(a, sl, alpha, g0 + N - 2, gc0 + N - 2, hnu_k, two_hnu3, lamfac, sh2);
-            dzb = rec[(gc0 + N - 1) * a.rec_w];
+            load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + N - 2, gc0 + N - 2, gc0 + N - 1,
+                                  in2);
+            shared_terms<R, NS, MC>(in2, sl, alpha, hnu_k, two_hnu3, lamfac, sh2);
+            dzb = in2.dz;
         }
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS>(sl, sh, phi + (gc0 + k) * A.ray_cols, pb, r, p);
+            ray_terms<R, NS, MC>(sl, sh, in0, r, p);
             R I0 = R(0);
             if (s_dir != 0) {
                 RayPt<R, NS> p2;
-                ray_terms<R, NS>(sl, sh2, phi + (gc0 + N - 2) * A.ray_cols, pb, r, p2);
+                ray_terms<R, NS, MC>(sl, sh2, in2, r, p2);
                 const R dtv = R(0.5) * (p.chi + p2.chi) * dzb;
                 I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
             }
@@ -603,21 +657,33 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
+        store_point<R, NS, MODE>(acc, kapj, out, n_keys, k, lane);
+    }
+    // the spacing to the previous point along the sweep is stored with the
+    // lower of the two points
+    const int dz_shift = step > 0 ? 0 : 1;
+    PointIn<R, NS, MC> nxt;
+    if (N > 1) {
+        const int k1 = k + step;
+        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k1, gc0 + k1, gc0 + k1 + dz_shift, nxt);
     }
     for (int i = 1; i < N; i++) {
-        const int kp = k;
         k += step;
+        const PointIn<R, NS, MC> cur = nxt;
+        if (i + 1 < N) {
+            const int k2 = k + step;
+            load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k2, gc0 + k2, gc0 + k2 + dz_shift,
+                                  nxt);
+        }
         Shared<R, NS> sh;
-        shared_terms<R, NS>(a, sl, alpha, g0 + k, gc0 + k, hnu_k, two_hnu3, lamfac, sh);
-        const R dz = rec[(gc0 + (step > 0 ? k : kp)) * a.rec_w];
-        const R *phirow = phi + (gc0 + k) * A.ray_cols;
+        shared_terms<R, NS, MC>(cur, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
+        const R dz = cur.dz;
 #pragma unroll
         for (int j = 0; j < NK; j++) acc[j] = R(0);
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS>(sl, sh, phirow, pb, r, p);
+            ray_terms<R, NS, MC>(sl, sh, cur, r, p);
             const R x = R(0.5) * (chi_p[r] + p.chi) * dz * invmu[r];
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
@@ -629,14 +695,16 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
+        store_point<R, NS, MODE>(acc, kapj, out, n_keys, k, lane);
     }
 }
 
 // Groups are ordered by their number of slots; one launch per slot count
 // covers the range [g_begin, g_end) so each variant gets its own registers.
 template <typename R, int MODE, int NS, int MC>
-__global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end) {
+__global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end, const R *__restrict__ rec,
+                                               const R *__restrict__ phi, const R *__restrict__ popsb,
+                                               R *__restrict__ part) {
     const int grp = rfl(g_begin + blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (grp >= g_end) return;
@@ -648,7 +716,7 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
         if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
         slot = rfl(a.retire_list[blockIdx.y]);
     }
-    sweep_group<R, MODE, NS, MC>(a, grp, slot, lane);
+    sweep_group<R, MODE, NS, MC>(a, grp, slot, lane, rec, phi, popsb, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -666,24 +734,26 @@ __device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransitio
     return Cul * a.coll_scale;
 }
 
+// Sum of the rate sums `keys[b..e)` of one depth point; `part` points at the
+// point's row of the point-major [depth][key] array.
 template <typename R>
-__device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e, int N, int k) {
+__device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e) {
     double v = 0.0;
-    for (int i = b; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
+    for (int i = b; i < e; i++) v += static_cast<double>(part[keys[i]]);
     return v;
 }
 
 // Rate matrix entry (i, j), i != j: radiative and collisional rates from j
 // into i, plus the cross terms of overlapping transitions.
 template <typename R, bool ZERO_RAD>
-__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int N, int k,
-                                             int64_t gc, double T, double ne) {
+__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int64_t gc, double T,
+                                             double ne) {
     const DevAtom &A = a.A;
     double v = 0.0;
     const int tu = A.up_t[i * L + j];
     if (tu >= 0) {  // j = l, i = u: excitation / ionisation
         const DevTransition &tr = A.tr[tu];
-        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1], N, k);
+        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1]);
         v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]);
     }
     const int td = A.dn_t[i * L + j];
@@ -705,7 +775,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                 v += q;
             }
         } else {
-            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1], N, k);
+            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1]);
         }
         v += coll_down(a, tr, T, ne);
     }
@@ -713,7 +783,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
         for (int x = A.xe_off[i * L + j]; x < A.xe_off[i * L + j + 1]; x++) {
             const int e = A.xe_val[x];
             const int xp = (e > 0 ? e : -e) - 1;
-            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1], N, k);
+            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1]);
             v += e > 0 ? X : -X;
         }
     }
@@ -724,10 +794,9 @@ template <typename R, int L, bool ZERO_RAD>
 __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const ColGeom cg = geom(a, slot);
     if (k >= cg.N) return;
-    const int N = cg.N;
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
-    const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
+    const R *part = reinterpret_cast<const R *>(a.part) + gc * A.n_keys;
     const double T = a.T[g], ne = a.ne[g];
     double M[L][L];
     double nold[L], b[L];
@@ -739,7 +808,7 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     for (int i = 0; i < L; i++)
 #pragma unroll
         for (int j = 0; j < L; j++)
-            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, N, k, gc, T, ne);
+            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, gc, T, ne);
 #pragma unroll
     for (int j = 0; j < L; j++) {
         double c = 0.0;
@@ -1037,9 +1106,9 @@ __global__ __launch_bounds__(256) void k_psi_gather(RunArgs a) {
         const int slot = a.retire_list[sk / a.ND], k = (int)(sk % a.ND);
         const ColGeom cg = geom(a, slot);
         if (k >= cg.N) continue;
-        const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
+        const R *part = reinterpret_cast<const R *>(a.part) + (cg.gc0 + k) * A.n_keys;
         double s = 0.0;
-        for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * cg.N + k]);
+        for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[A.p_key[i]]);
         a.psi[(cg.g0 + k) * A.T + t] = s;
     }
 }
@@ -1473,7 +1542,10 @@ template <typename R, int MODE, int NS, int MC>
 void launch_sweep_range(const RunArgs &a, hipStream_t st) {
     const int gb = a.A.g_begin[NS], ge = a.A.g_begin[NS + 1];
     if (ge <= gb) return;
-    hipLaunchKernelGGL((k_sweep<R, MODE, NS, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge);
+    const R *popsb = sizeof(R) == 8 ? reinterpret_cast<const R *>(a.pops) : reinterpret_cast<const R *>(a.popsf);
+    hipLaunchKernelGGL((k_sweep<R, MODE, NS, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge,
+                       reinterpret_cast<const R *>(a.rec), reinterpret_cast<const R *>(a.phi), popsb,
+                       reinterpret_cast<R *>(a.part));
 }
 
 template <typename R, int MODE, int MC>
