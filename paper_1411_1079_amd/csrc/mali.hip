@@ -532,10 +532,11 @@ __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi,
 // Sums the lanes' contributions of one depth point over the wavefront and
 // stores them (lane 63 holds the totals).  Each DPP stage is applied to all
 // sums before the next, so the independent sums fill each other's DPP wait
-// states; the totals of a depth point are contiguous in `out` (point-major
-// layout [depth][key]) and lane 63 writes them under one branch.
+// states, and lane 63 writes all totals under one branch.  `out` is
+// key-major ([key][depth] per column, N depths), which the rate-equation
+// kernel reads with consecutive depth points in consecutive lanes.
 template <typename R, int NS, int MODE>
-__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int n_keys, int k, int lane) {
+__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int N, int k, int lane) {
     constexpr int NK = n_acc<NS, MODE>();
     R v[NK];
 #pragma unroll
@@ -559,9 +560,8 @@ __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out,
 #pragma unroll
     for (int i = 0; i < NK; i++) v[i] += dpp_src<0x143, 0xc>(v[i]);
     if (lane == kWave - 1) {
-        R *o = out + (size_t)k * n_keys;
 #pragma unroll
-        for (int i = 0; i < NK; i++) o[i] = v[i];
+        for (int i = 0; i < NK; i++) out[(size_t)i * N + k] = v[i];
     }
 }
 
@@ -617,8 +617,8 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         invmu[r] = R(1) / mu[r];
         wmu[r] = static_cast<R>(A.wmu[m0 + r]);
     }
-    R *out = part + gc0 * A.n_keys + key_off;
-    const int rec_w = a.rec_w, L = A.L, n_keys = A.n_keys;
+    R *out = part + gc0 * A.n_keys + (size_t)key_off * N;
+    const int rec_w = a.rec_w, L = A.L;
     constexpr int NK = n_acc<NS, MODE>();
     const int step = s_dir == 0 ? 1 : -1;
     int k = s_dir == 0 ? 0 : N - 1;
@@ -657,7 +657,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, n_keys, k, lane);
+        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
     }
     // the spacing to the previous point along the sweep is stored with the
     // lower of the two points
@@ -695,7 +695,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, n_keys, k, lane);
+        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
     }
 }
 
@@ -734,26 +734,26 @@ __device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransitio
     return Cul * a.coll_scale;
 }
 
-// Sum of the rate sums `keys[b..e)` of one depth point; `part` points at the
-// point's row of the point-major [depth][key] array.
+// Sum of the rate sums `keys[b..e)` at depth k of a column whose key-major
+// block ([key][depth], N depths) starts at `part`.
 template <typename R>
-__device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e) {
+__device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e, int N, int k) {
     double v = 0.0;
-    for (int i = b; i < e; i++) v += static_cast<double>(part[keys[i]]);
+    for (int i = b; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
     return v;
 }
 
 // Rate matrix entry (i, j), i != j: radiative and collisional rates from j
 // into i, plus the cross terms of overlapping transitions.
 template <typename R, bool ZERO_RAD>
-__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int64_t gc, double T,
-                                             double ne) {
+__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int N, int k,
+                                             int64_t gc, double T, double ne) {
     const DevAtom &A = a.A;
     double v = 0.0;
     const int tu = A.up_t[i * L + j];
     if (tu >= 0) {  // j = l, i = u: excitation / ionisation
         const DevTransition &tr = A.tr[tu];
-        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1]);
+        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1], N, k);
         v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]);
     }
     const int td = A.dn_t[i * L + j];
@@ -775,7 +775,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                 v += q;
             }
         } else {
-            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1]);
+            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1], N, k);
         }
         v += coll_down(a, tr, T, ne);
     }
@@ -783,7 +783,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
         for (int x = A.xe_off[i * L + j]; x < A.xe_off[i * L + j + 1]; x++) {
             const int e = A.xe_val[x];
             const int xp = (e > 0 ? e : -e) - 1;
-            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1]);
+            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1], N, k);
             v += e > 0 ? X : -X;
         }
     }
@@ -794,9 +794,10 @@ template <typename R, int L, bool ZERO_RAD>
 __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const ColGeom cg = geom(a, slot);
     if (k >= cg.N) return;
+    const int N = cg.N;
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
-    const R *part = reinterpret_cast<const R *>(a.part) + gc * A.n_keys;
+    const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
     const double T = a.T[g], ne = a.ne[g];
     double M[L][L];
     double nold[L], b[L];
@@ -808,7 +809,7 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     for (int i = 0; i < L; i++)
 #pragma unroll
         for (int j = 0; j < L; j++)
-            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, gc, T, ne);
+            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, N, k, gc, T, ne);
 #pragma unroll
     for (int j = 0; j < L; j++) {
         double c = 0.0;
@@ -1012,87 +1013,138 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
 // ---------------------------------------------------------------------------
 // Opacity and source function of the vertical (mu = 1, upward) ray at
 // wavelength j, depth point k; line profiles come from the prepared table.
-template <typename R>
-struct EmergentRay {
-    int j;
-    R hnu_k, two_hnu3, lamfac, nu;
-};
-
 // The prepared tables (per-depth records, line profiles) are read in the
 // sweep's precision TB; the arithmetic runs in FP64 for both forms: the
 // emergent intensity spans far more decades than FP32 can hold (the Planck
 // function's Wien tail in the far ultraviolet), and this one ray per
-// wavelength costs a few percent of one iteration.
-template <typename TB, typename R>
-__device__ __forceinline__ void point_opacity_mu1(const RunArgs &a, const EmergentRay<R> &ray, int64_t gc, int64_t g,
-                                                  R &chi, R &S, R &B) {
-    const DevAtom &A = a.A;
-    const int L = A.L;
-    const TB *rec = reinterpret_cast<const TB *>(a.rec) + gc * a.rec_w;
-    const R x = ray.hnu_k * static_cast<R>(rec[1]);
-    const R ex = d_exp(-x), omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
-    B = ray.two_hnu3 * ex / omx;
-    R c = static_cast<R>(rec[2]) * ray.lamfac;
-    R e = c * B;
-    const TB *phirow = reinterpret_cast<const TB *>(a.phi) + gc * A.ray_cols;
-    const double *n = a.pops + g * L;
-    for (int i = A.jact_off[ray.j]; i < A.jact_off[ray.j + 1]; i++) {
-        const int t = A.jact_t[i];
-        const DevTransition &tr = A.tr[t];
-        const R nl = static_cast<R>(n[tr.l]), nu = static_cast<R>(n[tr.u]);
-        R vlu, vul, U;
-        if (tr.kind == 0) {
-            const R ph = static_cast<R>(phirow[tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i]]);
-            const R c0 = static_cast<R>(tr.hnu4pi);
-            vlu = c0 * static_cast<R>(tr.Blu) * ph;
-            vul = c0 * static_cast<R>(tr.Bul) * ph;
-            U = c0 * static_cast<R>(tr.A) * ph;
-        } else {
-            const R r = static_cast<R>(tr.nu0) / ray.nu;
-            const R alpha = static_cast<R>(tr.alpha0) * r * r * r;
-            const R G = static_cast<R>(rec[kRecHead + (t - A.n_lines)]) * ex;
-            vlu = alpha; vul = G * alpha; U = ray.two_hnu3 * G * alpha;
+// wavelength costs a few percent of one iteration.  One thread per
+// (column, wavelength); the active transitions of the wavelength are
+// unpacked once, and each depth point's inputs are loaded one step ahead of
+// their use.
+struct EmTrans {
+    int na;
+    int kind[kMaxSlots], l[kMaxSlots], u[kMaxSlots], col[kMaxSlots];  // col: profile column or continuum index
+    double cblu[kMaxSlots], cbul[kMaxSlots], ca[kMaxSlots], alpha[kMaxSlots];
+};
+
+struct EmIn {
+    double invT, kbg, dz;
+    double f[kMaxSlots];               // profile value (lines) or continuum G factor of the record
+    double nl[kMaxSlots], nu[kMaxSlots];
+};
+
+template <typename TB>
+__device__ __forceinline__ void em_load(const TB *__restrict__ rec, const TB *__restrict__ phi,
+                                        const double *__restrict__ pops, int rec_w, int ray_cols, int L,
+                                        const EmTrans &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn &p) {
+    const TB *r = rec + gc * rec_w;
+    p.invT = static_cast<double>(r[1]);
+    p.kbg = static_cast<double>(r[2]);
+    p.dz = static_cast<double>(rec[gc_dz * rec_w]);
+    const double *n = pops + g * L;
+    const TB *pr = phi + gc * ray_cols;
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) {
+        if (q < et.na) {
+            p.nl[q] = n[et.l[q]];
+            p.nu[q] = n[et.u[q]];
+            p.f[q] = static_cast<double>(et.kind[q] == 0 ? pr[et.col[q]] : r[kRecHead + et.col[q]]);
         }
-        c += nl * vlu - nu * vul;
-        e += nu * U;
+    }
+}
+
+__device__ __forceinline__ void em_point(const EmIn &in, const EmTrans &et, double hnu_k, double two_hnu3, double lamfac,
+                                         double &chi, double &S, double &B) {
+    const double x = hnu_k * in.invT;
+    const double ex = d_exp(-x), omx = x > 0.5 ? 1.0 - ex : -d_expm1(-x);
+    B = two_hnu3 * ex / omx;
+    double c = in.kbg * lamfac;
+    double e = c * B;
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) {
+        if (q < et.na) {
+            double vlu, vul, U;
+            if (et.kind[q] == 0) {
+                vlu = et.cblu[q] * in.f[q];
+                vul = et.cbul[q] * in.f[q];
+                U = et.ca[q] * in.f[q];
+            } else {
+                const double G = in.f[q] * ex;
+                vlu = et.alpha[q]; vul = G * et.alpha[q]; U = two_hnu3 * G * et.alpha[q];
+            }
+            c += in.nl[q] * vlu - in.nu[q] * vul;
+            e += in.nu[q] * U;
+        }
     }
     chi = c;
     S = e / c;
 }
 
 template <typename TB>
-__global__ __launch_bounds__(256) void k_emergent(RunArgs a) {
+__global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restrict__ rec, const TB *__restrict__ phi,
+                                                  const double *__restrict__ pops) {
     using R = double;
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
+    const int rec_w = a.rec_w, ray_cols = A.ray_cols, L = A.L;
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
         const int slot = a.retire_list[w / A.NL];
-        EmergentRay<R> ray;
-        ray.j = (int)(w % A.NL);
-        const double nu = A.nu[ray.j];
-        ray.nu = static_cast<R>(nu);
-        ray.hnu_k = static_cast<R>(kH * nu / kKB);
-        ray.two_hnu3 = static_cast<R>(2.0 * kH * nu * nu * nu / (kC * kC));
-        ray.lamfac = static_cast<R>(A.lam[ray.j] / kBgLambdaRef);
+        const int j = (int)(w % A.NL);
+        const double nu = A.nu[j];
+        const double hnu_k = kH * nu / kKB;
+        const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
+        const double lamfac = A.lam[j] / kBgLambdaRef;
+        EmTrans et;
+        et.na = A.jact_off[j + 1] - A.jact_off[j];
+#pragma unroll
+        for (int q = 0; q < kMaxSlots; q++) {
+            if (q < et.na) {
+                const int i = A.jact_off[j] + q;
+                const int t = A.jact_t[i];
+                const DevTransition &tr = A.tr[t];
+                et.kind[q] = tr.kind;
+                et.l[q] = tr.l;
+                et.u[q] = tr.u;
+                if (tr.kind == 0) {
+                    et.col[q] = tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i];
+                    const double c0 = tr.hnu4pi;
+                    et.cblu[q] = c0 * tr.Blu;
+                    et.cbul[q] = c0 * tr.Bul;
+                    et.ca[q] = c0 * tr.A;
+                } else {
+                    et.col[q] = t - A.n_lines;
+                    const double r = tr.nu0 / nu;
+                    et.alpha[q] = tr.alpha0 * r * r * r;
+                }
+            }
+        }
         const ColGeom cg = geom(a, slot);
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
-        const TB *rec = reinterpret_cast<const TB *>(a.rec);
+        EmIn in;
         R chi2, S2, B2, chi, S, B;
-        point_opacity_mu1<TB, R>(a, ray, gc0 + N - 2, g0 + N - 2, chi2, S2, B2);
-        point_opacity_mu1<TB, R>(a, ray, gc0 + N - 1, g0 + N - 1, chi, S, B);
-        const R dtv = R(0.5) * (chi + chi2) * static_cast<R>(rec[(gc0 + N - 1) * a.rec_w]);
+        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 2, in);
+        em_point(in, et, hnu_k, two_hnu3, lamfac, chi2, S2, B2);
+        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 1, gc0 + N - 1, gc0 + N - 1, in);
+        em_point(in, et, hnu_k, two_hnu3, lamfac, chi, S, B);
+        const R dtv = R(0.5) * (chi + chi2) * in.dz;
         R I = dtv > R(0) ? B + (B - B2) / dtv : B;
         R chi_p = chi, S_p = S;
+        // upward from k = N - 2 to the top; the step from k + 1 uses the
+        // spacing stored with point k + 1
+        EmIn nxt;
+        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt);
         for (int k = N - 2; k >= 0; k--) {
-            point_opacity_mu1<TB, R>(a, ray, gc0 + k, g0 + k, chi, S, B);
-            const R x = R(0.5) * (chi_p + chi) * static_cast<R>(rec[(gc0 + k + 1) * a.rec_w]);
+            const EmIn cur = nxt;
+            if (k > 0) em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + k - 1, gc0 + k - 1, gc0 + k, nxt);
+            em_point(cur, et, hnu_k, two_hnu3, lamfac, chi, S, B);
+            const R x = R(0.5) * (chi_p + chi) * cur.dz;
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
             I = I * e + wa * S_p + wb * S;
             chi_p = chi; S_p = S;
         }
-        a.spectrum[(size_t)cg.col * A.NL + ray.j] = static_cast<double>(I);
+        a.spectrum[(size_t)cg.col * A.NL + j] = static_cast<double>(I);
     }
 }
 
@@ -1106,9 +1158,9 @@ __global__ __launch_bounds__(256) void k_psi_gather(RunArgs a) {
         const int slot = a.retire_list[sk / a.ND], k = (int)(sk % a.ND);
         const ColGeom cg = geom(a, slot);
         if (k >= cg.N) continue;
-        const R *part = reinterpret_cast<const R *>(a.part) + (cg.gc0 + k) * A.n_keys;
+        const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
         double s = 0.0;
-        for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[A.p_key[i]]);
+        for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * cg.N + k]);
         a.psi[(cg.g0 + k) * A.T + t] = s;
     }
 }
@@ -1596,8 +1648,13 @@ struct Launcher {
         if (tm) tm->mark(5, st);
         if (want_spec) {
             const unsigned eb = grid_for((int64_t)a.S * a.A.NL, 256, 8192);
-            if (fp32) hipLaunchKernelGGL(k_emergent<float>, dim3(eb), dim3(256), 0, st, a);
-            else hipLaunchKernelGGL(k_emergent<double>, dim3(eb), dim3(256), 0, st, a);
+            if (fp32)
+                hipLaunchKernelGGL(k_emergent<float>, dim3(eb), dim3(256), 0, st, a,
+                                   reinterpret_cast<const float *>(a.rec), reinterpret_cast<const float *>(a.phi), a.pops);
+            else
+                hipLaunchKernelGGL(k_emergent<double>, dim3(eb), dim3(256), 0, st, a,
+                                   reinterpret_cast<const double *>(a.rec), reinterpret_cast<const double *>(a.phi),
+                                   a.pops);
         }
         if (want_psi) {
             if (fp32) launch_sweep<float, MODE_PSI>(a, st);
