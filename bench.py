@@ -35,6 +35,25 @@ sys.path.insert(0, ROOT)
 METRIC = "converged columns/s @1e-3 rel. accuracy: plain FP64 vs batched FP32+warm start"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per FP32 sweep stage from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (calibrated on a 1 GiB copy), valid only for the kernel source they were
+# taken on: the JSON line reports null once that source has changed.
+SWEEP_TRAFFIC = {
+    "source": "paper_1411_1079_amd/csrc/mali.hip",
+    "sha256": "984a508a470e43db99b287d3fee5d0065022d2c8722a3ae4e81f229044e5001f",
+    "read_bytes": 14.93e9,
+    "written_bytes": 1.52e9,
+    "summary": "profiles/k_sweep_fp32_cube256_counters.md",
+}
+
+
+def sweep_traffic():
+    import hashlib
+    path = os.path.join(ROOT, SWEEP_TRAFFIC["source"])
+    with open(path, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != SWEEP_TRAFFIC["sha256"]:
+            return None
+    return SWEEP_TRAFFIC["read_bytes"] + SWEEP_TRAFFIC["written_bytes"]
 
 
 def log(*a):
@@ -328,9 +347,14 @@ def main():
             "kernel": f"k_sweep ({'FP64' if headline == 'fp64' else 'FP32'} formal solution and rate accumulation)",
             "achieved": achieved,
             "peak": peak,
+            "peak_note": ("published vector peak of the precision; without packed FP32 instructions (kept out of "
+                          "the device code) FP32 vector code can reach 78.6 TFLOP/s"),
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": None,
+            "traffic": sweep_traffic() if headline != "fp64" else None,
+            "traffic_note": ("HBM bytes per sweep stage, rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors "
+                             "from a 1 GiB copy), counters taken on the fp32 form (same kernel and batches); null "
+                             "when the kernel source differs from the one measured"),
             "launches": hst["sweep_launches"],
             "avg_launch_ms": hst["sweep_ms"] / max(hst["sweep_launches"], 1),
             "algorithmic_flops_per_launch": hst["sweep_flops"] / max(hst["sweep_launches"], 1),
