@@ -93,7 +93,7 @@ class Columns:
         nd = np.array([len(p["z"]) for p in parts], dtype=np.int64)
         off = np.zeros(len(parts) + 1, dtype=np.int64)
         off[1:] = np.cumsum(nd)
-        cat = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts]).astype(np.float64))
+        cat = {k: np.ascontiguousarray(np.concatenate([p[k] for p in parts] or [np.zeros(0)]).astype(np.float64))
                for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
         return Columns(offset=off, **cat)
 
