@@ -157,7 +157,8 @@ def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None):
     iters = np.concatenate(iters)
     hist = {f"p{q}": float(np.percentile(iters, q)) for q in (50, 90, 99, 100)}
     out = dict(seconds=t1 - t0, columns=columns, converged=converged, stats=agg, solvers=solvers,
-               first_batch=(warmup % nb), iter_percentiles=hist, mean_iterations=float(iters.mean()))
+               first_batch=(warmup % nb), iter_percentiles=hist, mean_iterations=float(iters.mean()),
+               ran={(warmup + i) % nb for i in range(steps)})
     if form == "fp32w":
         mlp["refined_columns"] = refined
         mlp["forward_tflops"] = MLP_FLOPS_PER_SAMPLE * mlp["samples"] / (mlp["predict_ms"] / 1e3) / 1e12
@@ -193,37 +194,46 @@ def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols):
                        f"{dt:.1f} s wall on {threads} threads"), results
 
 
-def converged_oracle(atom_path, cols, results, n, threads):
-    """The oracle converged to 1e-10 on the first n columns of the CPU
-    sample (not timed): the reference of the 1e-3 accuracy criterion."""
+def converged_oracle(atom_path, cols, n, threads, seed=0):
+    """The oracle converged to 1e-10 on a seeded random sample of n columns
+    of the whole cube (not timed): the reference of the 1e-3 accuracy
+    criterion.  The sample includes slowly converging columns in their
+    proportion, on which the 1e-4 stopping rule itself leaves a larger
+    distance to the fixed point."""
     import concurrent.futures
 
     from oracle import oracle as O
     a = O.Atom(atom_path)
-    picks = [c for c, _ in results[:n]]
+    picks = sorted(np.random.default_rng(seed).choice(cols.n_columns, size=min(n, cols.n_columns), replace=False))
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        futs = [ex.submit(O.solve_column, a, cols.column(c), n_mu=5, tol=1e-10, max_iter=400) for c in picks]
-        return [(c, f.result()) for c, f in zip(picks, futs)]
+        futs = [ex.submit(O.solve_column, a, cols.column(int(c)), n_mu=5, tol=1e-10, max_iter=1000) for c in picks]
+        return [(int(c), f.result()) for c, f in zip(picks, futs)]
 
 
 def accuracy(results, form, batches, cols):
     """Max relative difference of populations and emergent intensity between
-    a GPU form and the oracle on the CPU-baseline sample."""
-    s = form["solvers"][form["first_batch"]]
-    c0 = batches[form["first_batch"]][0]
-    pops = s.pops.cpu().numpy()
-    spec = s.spectrum.cpu().numpy()
-    off = s.dc.offset
+    a GPU form and oracle results [(global column, result)], and the
+    fraction of those columns within 1e-3 in both."""
+    host = {}
     ep = es = 0.0
     within = 0
+    n = 0
     for c, r in results:
-        i = c - c0
-        a, b = int(off[i]), int(off[i + 1])
-        p = float(np.max(np.abs(pops[a:b] / r["pops"] - 1.0)))
+        b = next(i for i, (c0, c1, _) in enumerate(batches) if c0 <= c < c1)
+        if b not in form["ran"]:
+            continue        # a batch the timed steps did not solve
+        n += 1
+        if b not in host:
+            s = form["solvers"][b]
+            host[b] = (s.pops.cpu().numpy(), s.spectrum.cpu().numpy(), s.dc.offset)
+        pops, spec, off = host[b]
+        i = c - batches[b][0]
+        lo, hi = int(off[i]), int(off[i + 1])
+        p = float(np.max(np.abs(pops[lo:hi] / r["pops"] - 1.0)))
         e = float(np.max(np.abs(spec[i] / r["spectrum"] - 1.0)))
         ep, es = max(ep, p), max(es, e)
         within += int(p <= 1e-3 and e <= 1e-3)
-    return {"pops": ep, "spectrum": es, "columns": len(results), "fraction_within_1e-3": within / max(len(results), 1)}
+    return {"pops": ep, "spectrum": es, "columns": n, "fraction_within_1e-3": within / max(n, 1)}
 
 
 def main():
@@ -241,7 +251,7 @@ def main():
     ap.add_argument("--cpu-max-columns", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--accuracy-columns", type=int, default=128,
-                    help="columns of the CPU sample also solved by the oracle to 1e-10")
+                    help="seeded random columns of the cube also solved by the oracle to 1e-10")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (a reference kernel of known traffic for "
@@ -391,7 +401,7 @@ def main():
             f"{out['accuracy_vs_oracle_same_stopping_rule']}")
         if args.accuracy_columns > 0:
             t = time.perf_counter()
-            conv = converged_oracle(atom_path, cols, results, args.accuracy_columns, base["cores"])
+            conv = converged_oracle(atom_path, cols, args.accuracy_columns, base["cores"])
             out["accuracy_vs_converged_oracle"] = {f: accuracy(conv, r, batches, cols) for f, r in res.items()}
             log(f"accuracy against the oracle converged to 1e-10 ({len(conv)} columns, "
                 f"{time.perf_counter() - t:.1f} s): {out['accuracy_vs_converged_oracle']}")
