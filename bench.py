@@ -4,8 +4,9 @@
 Workload: the synthetic 3D-MHD-like cube (256 x 256 = 65,536 columns, 200-400
 depth points each, seed 1), the six-level hydrogen-like atom (10 lines, 5
 continua, 510 wavelengths), 5 angles, converged to a maximum relative
-population change of 1e-4.  A step solves one batch of columns (default
-16384) to convergence; K steps cycle through the cube's batches.
+population change of 1e-4.  A step solves one batch of columns (default:
+the whole cube, streamed through the resident slots) to convergence; K steps
+cycle through the cube's batches.
 Inputs are resident in HBM before the timed region.
 
 Three forms run on the same batches: the plain FP64 path, the precision
@@ -239,14 +240,14 @@ def accuracy(results, form, batches, cols):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=16384)
+    ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--nx", type=int, default=256)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--forms", default="fp64,fp32,fp32w")
     ap.add_argument("--train-seed", type=int, default=7)
-    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--train-steps", type=int, default=12000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-max-columns", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -1600,20 +1600,62 @@ void launch_sweep_range(const RunArgs &a, hipStream_t st) {
                        reinterpret_cast<R *>(a.part));
 }
 
+// The launches for the different slot counts touch disjoint rate sums, so
+// they may run concurrently: each goes to a side stream forked from (and
+// joined back into) the launch stream, and one launch's tail of finishing
+// wavefronts overlaps the others' work.  Inside a captured iteration the
+// fork and join become parallel branches of the graph.
+struct SideStreams {
+    bool on = false;
+    hipStream_t s[kMaxSlots] = {};
+    hipEvent_t fork = nullptr, join[kMaxSlots] = {};
+    int init() {
+        for (int i = 0; i < kMaxSlots; i++) {
+            HIP_TRY(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        on = true;
+        return RH15D_OK;
+    }
+    ~SideStreams() {
+        for (int i = 0; i < kMaxSlots; i++) {
+            if (s[i]) (void)hipStreamDestroy(s[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
+};
+
 template <typename R, int MODE, int MC>
-void launch_sweep_mc(const RunArgs &a, hipStream_t st) {
-    launch_sweep_range<R, MODE, 1, MC>(a, st);
-    launch_sweep_range<R, MODE, 2, MC>(a, st);
-    launch_sweep_range<R, MODE, 3, MC>(a, st);
-    launch_sweep_range<R, MODE, 4, MC>(a, st);
+void launch_sweep_mc(const RunArgs &a, hipStream_t st, SideStreams *side) {
+    int used = 0;
+    for (int ns = 1; ns <= kMaxSlots; ns++) used += a.A.g_begin[ns + 1] > a.A.g_begin[ns];
+    if (!side || !side->on || used < 2) {
+        launch_sweep_range<R, MODE, 1, MC>(a, st);
+        launch_sweep_range<R, MODE, 2, MC>(a, st);
+        launch_sweep_range<R, MODE, 3, MC>(a, st);
+        launch_sweep_range<R, MODE, 4, MC>(a, st);
+        return;
+    }
+    (void)hipEventRecord(side->fork, st);
+    for (int i = 0; i < kMaxSlots; i++) (void)hipStreamWaitEvent(side->s[i], side->fork, 0);
+    launch_sweep_range<R, MODE, 1, MC>(a, side->s[0]);
+    launch_sweep_range<R, MODE, 2, MC>(a, side->s[1]);
+    launch_sweep_range<R, MODE, 3, MC>(a, side->s[2]);
+    launch_sweep_range<R, MODE, 4, MC>(a, side->s[3]);
+    for (int i = 0; i < kMaxSlots; i++) {
+        (void)hipEventRecord(side->join[i], side->s[i]);
+        (void)hipStreamWaitEvent(st, side->join[i], 0);
+    }
 }
 
 template <typename R, int MODE>
-void launch_sweep(const RunArgs &a, hipStream_t st) {
+void launch_sweep(const RunArgs &a, hipStream_t st, SideStreams *side) {
     switch (a.A.mc) {
-        case 5: launch_sweep_mc<R, MODE, 5>(a, st); break;
-        case 3: launch_sweep_mc<R, MODE, 3>(a, st); break;
-        default: launch_sweep_mc<R, MODE, 1>(a, st); break;
+        case 5: launch_sweep_mc<R, MODE, 5>(a, st, side); break;
+        case 3: launch_sweep_mc<R, MODE, 3>(a, st, side); break;
+        default: launch_sweep_mc<R, MODE, 1>(a, st, side); break;
     }
 }
 
@@ -1621,6 +1663,7 @@ struct Launcher {
     RunArgs a;
     bool fp32, zero_start, want_spec, want_psi;
     hipStream_t st;
+    SideStreams *side = nullptr;
 
     void refill_phase(Timer *tm) {
         hipLaunchKernelGGL(k_refill, dim3(1), dim3(kRefillThreads), 0, st, a);
@@ -1639,8 +1682,8 @@ struct Launcher {
 
     void iteration(Timer *tm) {
         if (tm) tm->mark(2, st);
-        if (fp32) launch_sweep<float, MODE_RATES>(a, st);
-        else launch_sweep<double, MODE_RATES>(a, st);
+        if (fp32) launch_sweep<float, MODE_RATES>(a, st, side);
+        else launch_sweep<double, MODE_RATES>(a, st, side);
         if (tm) tm->mark(3, st);
         launch_se(a, fp32, false, st);
         if (tm) tm->mark(4, st);
@@ -1657,8 +1700,8 @@ struct Launcher {
                                    a.pops);
         }
         if (want_psi) {
-            if (fp32) launch_sweep<float, MODE_PSI>(a, st);
-            else launch_sweep<double, MODE_PSI>(a, st);
+            if (fp32) launch_sweep<float, MODE_PSI>(a, st, side);
+            else launch_sweep<double, MODE_PSI>(a, st, side);
             const unsigned gb = grid_for((int64_t)a.S * a.ND * a.A.T, 256, 16384);
             if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3(gb), dim3(256), 0, st, a);
             else hipLaunchKernelGGL(k_psi_gather<double>, dim3(gb), dim3(256), 0, st, a);
@@ -1821,6 +1864,9 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
                  st};
     Timer tm;
     if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
+    SideStreams side;
+    if ((rc = side.init()) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
+    run.side = &side;
     Timer *tp = tm.on ? &tm : nullptr;
     tm.mark(0, st);
     e = hipMemcpyAsync(const_cast<int64_t *>(a.doff), cols->depth_offset, (cols->n_columns + 1) * sizeof(int64_t),
