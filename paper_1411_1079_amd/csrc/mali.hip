@@ -291,7 +291,6 @@ __global__ __launch_bounds__(256) void k_prep_depth(RunArgs a) {
 // normalised so that sum over rays of W phi = 1 at this depth.
 template <typename R>
 __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int lane) {
-    constexpr int kPer = kMaxLineRays / kWave;  // rays per lane
     const ColGeom cg = geom(a, slot);
     if (k >= cg.N) return;
     const DevAtom &A = a.A;
@@ -302,42 +301,23 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const R adamp = static_cast<R>(tr.gamma / (4.0 * kPI * dnd));
     const double rdnd = 1.0 / dnd;
     const double pre = rdnd / sqrt(kPI);
-    const int na = tr.n_act, nmu = A.n_mu, nq = 2 * na * nmu, nr = nq + na;
-    R ph[kPer];
+    const int r0 = A.prof_off[t], nr = A.prof_off[t + 1] - r0;
+    const double *pnu = A.prof_nu + r0, *pmus = A.prof_mus + r0, *pw = A.prof_w + r0;
+    R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
+    // quadrature rays (direction, wavelength, angle), then the vertical
+    // emergent ray of each wavelength (mu = 1, upward, weight 0); the row is
+    // written unnormalised, then scaled once the wavefront has the sum
     double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < kPer; i++) {
-        const int r = lane + kWave * i;
-        ph[i] = R(0);
-        if (r < nr) {
-            // quadrature rays r < nq: (direction, wavelength, angle); then the
-            // vertical emergent ray of each wavelength (mu = 1, upward)
-            int ja, m = 0;
-            double mus;
-            if (r < nq) {
-                const int s = r / (na * nmu), rem = r % (na * nmu);
-                ja = rem / nmu;
-                m = rem % nmu;
-                mus = s ? A.mu[m] : -A.mu[m];
-            } else {
-                ja = r - nq;
-                mus = 1.0;
-            }
-            const int j = A.act_j[tr.act_off + ja];
-            const double v = (A.nu[j] - tr.nu0 * (1.0 + mus * vz / kC)) * rdnd;
-            const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
-            ph[i] = H * static_cast<R>(pre);
-            if (r < nq) acc += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * static_cast<double>(ph[i]);
-        }
+    for (int r = lane; r < nr; r += kWave) {
+        const double v = (pnu[r] - tr.nu0 * (1.0 + pmus[r] * vz / kC)) * rdnd;
+        const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
+        const R ph = H * static_cast<R>(pre);
+        acc += pw[r] * static_cast<double>(ph);
+        phi[r] = ph;
     }
     const double tot = wave_sum(acc);
     const R rtot = static_cast<R>(1.0 / tot);
-    R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
-#pragma unroll
-    for (int i = 0; i < kPer; i++) {
-        const int r = lane + kWave * i;
-        if (r < nr) phi[r] = sizeof(R) == 8 ? static_cast<R>(ph[i] / tot) : ph[i] * rtot;
-    }
+    for (int r = lane; r < nr; r += kWave) phi[r] = sizeof(R) == 8 ? static_cast<R>(phi[r] / tot) : phi[r] * rtot;
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
 }
 
@@ -1417,6 +1397,37 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
             jja[i] = static_cast<int>(std::lower_bound(act.begin(), act.end(), j) - act.begin());
         }
     UP(jo, &D.jact_off); UP(jt, &D.jact_t); UP(jja, &D.jact_ja);
+    // per line ray (the layout of the profile table): frequency, signed
+    // direction cosine (+ up) and quadrature weight W = w_nu w_mu / 2 (0 for
+    // the vertical emergent rays, which are not in the normalisation)
+    {
+        std::vector<double> pnu, pmus, pw;
+        std::vector<int> poff(1, 0);
+        for (int t = 0; t < D.n_lines; t++) {
+            const auto &h = atom->tr[t];
+            const int na = static_cast<int>(h.act.size()), nq = 2 * na * n_mu;
+            for (int r = 0; r < nq + na; r++) {
+                int ja, m = 0;
+                double mus, w = 0.0;
+                if (r < nq) {
+                    const int sd = r / (na * n_mu), rem = r % (na * n_mu);
+                    ja = rem / n_mu;
+                    m = rem % n_mu;
+                    mus = sd ? H.mu[m] : -H.mu[m];
+                    w = h.w[ja] * 0.5 * H.wmu[m];
+                } else {
+                    ja = r - nq;
+                    mus = 1.0;
+                }
+                pnu.push_back(atom->nu[h.act[ja]]);
+                pmus.push_back(mus);
+                pw.push_back(w);
+            }
+            poff.push_back(static_cast<int>(pnu.size()));
+        }
+        if (pnu.empty()) { pnu.push_back(0.0); pmus.push_back(0.0); pw.push_back(0.0); }
+        UP(pnu, &D.prof_nu); UP(pmus, &D.prof_mus); UP(pw, &D.prof_w); UP(poff, &D.prof_off);
+    }
     UP(H.groups, &D.groups);
     UP(H.lane_j, &D.lanes.j); UP(H.lane_m0, &D.lanes.m0);
     UP(H.lane_lamfac, &D.lanes.lamfac); UP(H.lane_hnu_k, &D.lanes.hnu_k); UP(H.lane_2hnu3c2, &D.lanes.two_hnu3c2);
