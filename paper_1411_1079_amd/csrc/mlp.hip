@@ -186,6 +186,141 @@ __global__ void k_reduce_splits(const float *part, int nsplit, int64_t stride, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// fused inference: every layer of a tile of samples in one workgroup, the
+// activations kept in LDS between layers (no round trip through HBM)
+// ---------------------------------------------------------------------------
+constexpr int kFuseRows = 32;           // samples per workgroup
+constexpr int kFuseMaxW = 256;          // widest layer the fused kernel takes
+constexpr int kFuseLd = kFuseMaxW + 8;  // LDS row stride in BF16 elements
+constexpr int kMaxDense = 10;
+
+// One dense layer of the fused kernel; the array lives in device memory
+// (written once when the network is created), so the kernel reads it with
+// scalar loads instead of indexing a by-value argument array.
+struct FusedLayer {
+    int kp, np, nout, pad;              // fan-in and fan-out padded to 16, fan-out
+    const unsigned short *w;            // weights packed as MFMA B fragments
+    const float *b;                     // biases (FP32 master copy)
+};
+
+// B fragments of a [K][N] weight matrix for v_mfma_f32_16x16x16bf16: block
+// (kb, nb) holds, for lane l, W[16 kb + 4 (l / 16) + t][16 nb + l % 16],
+// t = 0..3, as 4 consecutive BF16 values; zero outside the matrix.
+__global__ void k_pack_b(const float *W, int K, int N, int KB, int NB, unsigned short *out) {
+    const int64_t total = (int64_t)KB * NB * 256;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(e & 3), lane = (int)((e >> 2) & 63);
+        const int64_t f = e >> 8;
+        const int nb = (int)(f % NB), kb = (int)(f / NB);
+        const int k = kb * 16 + 4 * (lane >> 4) + t, c = nb * 16 + (lane & 15);
+        out[e] = (k < K && c < N) ? to_bf16(W[(size_t)k * N + c]) : (unsigned short)0;
+    }
+}
+
+// The same arithmetic as the layer-by-layer path (normalised input; per
+// 16-wide K block the LO then the HI half of the activations times the BF16
+// weights; bias, SiLU), so the outputs agree bit for bit.  Wavefront w owns
+// the output blocks of 16 columns w, w + 4, ...; the weight fragments of the
+// next K block are loaded while the current block's MFMAs run.
+__global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict__ layers, int n_layers,
+                                                   const float *feat, const float *mean, const float *istd, int64_t n,
+                                                   float *out) {
+    constexpr int RB = kFuseRows / 16;  // row blocks of 16 samples
+    __shared__ unsigned short Hh[kFuseRows][kFuseLd];
+    __shared__ unsigned short Hl[kFuseRows][kFuseLd];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
+    const int kp0 = layers[0].kp;
+    for (int e = tid; e < kFuseRows * kp0; e += 256) {
+        const int r = e / kp0, c = e % kp0;
+        float v = 0.f;
+        if (c < kFeat && row0 + r < n) v = (feat[(row0 + r) * kFeat + c] - mean[c]) * istd[c];
+        const unsigned short hi = to_bf16(v);
+        Hh[r][c] = hi;
+        Hl[r][c] = to_bf16(v - from_bf16(hi));
+    }
+    __syncthreads();
+    const int nout_last = layers[n_layers - 1].nout;
+    for (int l = 0; l < n_layers; l++) {
+        const FusedLayer &ly = layers[l];
+        const int KB = ly.kp / 16, NB = ly.np / 16, nout = ly.nout;
+        const bool last = l == n_layers - 1;
+        const uint2 *wf = reinterpret_cast<const uint2 *>(ly.w);
+        f32x4 acc[RB][4];
+#pragma unroll
+        for (int i = 0; i < RB; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        uint2 bnext[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int nb = wave + 4 * j;
+            bnext[j] = nb < NB ? wf[(int64_t)nb * 64 + lane] : uint2{0u, 0u};
+        }
+        for (int kb = 0; kb < KB; kb++) {
+            uint2 bcur[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) bcur[j] = bnext[j];
+            if (kb + 1 < KB) {
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int nb = wave + 4 * j;
+                    if (nb < NB) bnext[j] = wf[((int64_t)(kb + 1) * NB + nb) * 64 + lane];
+                }
+            }
+            const int k = kb * 16 + 4 * (lane >> 4);
+            bf16x4 ah[RB], al[RB];
+#pragma unroll
+            for (int i = 0; i < RB; i++) {
+                const int row = i * 16 + (lane & 15);
+                ah[i] = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(&Hh[row][k]));
+                al[i] = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(&Hl[row][k]));
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (wave + 4 * j < NB) {
+                    const bf16x4 bv = __builtin_bit_cast(bf16x4, bcur[j]);
+#pragma unroll
+                    for (int i = 0; i < RB; i++) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bv, acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bv, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every wavefront has read this layer's input
+        const float *bias = ly.b;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int nb = wave + 4 * j;
+            if (nb >= NB) continue;
+            const int col = nb * 16 + (lane & 15);
+            const float bc = col < nout ? bias[col] : 0.f;
+#pragma unroll
+            for (int i = 0; i < RB; i++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int row = i * 16 + 4 * (lane >> 4) + r;
+                    if (last) {
+                        if (col < nout_last && row0 + row < n) out[(row0 + row) * nout_last + col] = acc[i][j][r] + bc;
+                    } else {
+                        unsigned short hi = 0, lo = 0;
+                        if (col < nout) {
+                            const float z = acc[i][j][r] + bc;
+                            const float h = z * sigmoid(z);
+                            hi = to_bf16(h);
+                            lo = to_bf16(h - from_bf16(hi));
+                        }
+                        Hh[row][col] = hi;
+                        Hl[row][col] = lo;
+                    }
+                }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -301,6 +436,9 @@ struct rh15d_mlp {
     float *x = nullptr;                     // normalised inputs [cap][36]
     std::vector<float *> Z, H, dH;          // per layer
     float *wpart = nullptr, *bpart = nullptr;  // split-K partial gradients
+    unsigned short *packed = nullptr;          // BF16 weights as MFMA B fragments (fused inference)
+    std::vector<size_t> pk_off;
+    FusedLayer *layers = nullptr;              // device descriptors of the fused kernel
     double *partial = nullptr;              // reductions
     int dev = 0;
 };
@@ -488,6 +626,24 @@ int rh15d_mlp_create(int n_hidden, int n_layers, int n_out, uint64_t seed, rh15d
     if (e == hipSuccess) e = hipMalloc(&p->mean, kFeat * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&p->istd, kFeat * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&p->partial, 256 * kFeat * 2 * sizeof(double));
+    size_t pk = 0;
+    for (size_t l = 0; l + 1 < p->dims.size(); l++) {
+        p->pk_off.push_back(pk);
+        pk += (size_t)((p->dims[l] + 15) / 16 * 16) * ((p->dims[l + 1] + 15) / 16 * 16);
+    }
+    if (e == hipSuccess) e = hipMalloc(&p->packed, pk * sizeof(unsigned short));
+    if (e == hipSuccess) e = hipMalloc(&p->layers, (p->dims.size() - 1) * sizeof(FusedLayer));
+    if (e == hipSuccess) {
+        std::vector<FusedLayer> ly(p->dims.size() - 1);
+        for (size_t l = 0; l + 1 < p->dims.size(); l++) {
+            ly[l].kp = (p->dims[l] + 15) / 16 * 16;
+            ly[l].np = (p->dims[l + 1] + 15) / 16 * 16;
+            ly[l].nout = p->dims[l + 1];
+            ly[l].w = p->packed + p->pk_off[l];
+            ly[l].b = p->params + p->b_off[l];
+        }
+        e = hipMemcpy(p->layers, ly.data(), ly.size() * sizeof(FusedLayer), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(p->params, h.data(), bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->grads, 0, bytes);
     if (e == hipSuccess) e = hipMemset(p->m, 0, bytes);
@@ -507,7 +663,8 @@ void rh15d_mlp_free(rh15d_mlp *p) {
     if (!p) return;
     free_acts(p);
     (void)hipFree(p->params); (void)hipFree(p->grads); (void)hipFree(p->m); (void)hipFree(p->v);
-    (void)hipFree(p->mean); (void)hipFree(p->istd); (void)hipFree(p->partial);
+    (void)hipFree(p->mean); (void)hipFree(p->istd); (void)hipFree(p->partial); (void)hipFree(p->packed);
+    (void)hipFree(p->layers);
     delete p;
 }
 
@@ -597,6 +754,20 @@ int rh15d_mlp_fit_normalization(rh15d_mlp *p, const float *feat, int64_t n, void
 int rh15d_mlp_forward(rh15d_mlp *p, const float *feat, int64_t n, float *out, void *stream) {
     if (!p || !feat || !out || n < 0) { set_error("null argument"); return RH15D_EINVAL; }
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const int L = (int)p->dims.size() - 1;
+    if (p->n_hidden % 16 == 0 && p->n_hidden <= kFuseMaxW && p->n_out <= 16 && L <= kMaxDense) {
+        if (n == 0) return RH15D_OK;
+        // the weights change with every Adam step or set_params: pack them for this call
+        for (int l = 0; l < L; l++) {
+            const int K = p->dims[l], N = p->dims[l + 1], KB = (K + 15) / 16, NB = (N + 15) / 16;
+            hipLaunchKernelGGL(k_pack_b, dim3(blocks_for((int64_t)KB * NB * 256)), dim3(256), 0, st,
+                               p->params + p->w_off[l], K, N, KB, NB, p->packed + p->pk_off[l]);
+        }
+        hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)((n + kFuseRows - 1) / kFuseRows)), dim3(256), 0, st,
+                           p->layers, L, feat, p->mean, p->istd, n, out);
+        HIP_TRY(hipGetLastError());
+        return RH15D_OK;
+    }
     int rc = ensure_cap(p, std::min<int64_t>(std::max<int64_t>(n, 1), kChunk));
     if (rc != RH15D_OK) return rc;
     const int nout = p->dims.back();

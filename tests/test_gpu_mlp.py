@@ -59,8 +59,12 @@ def _forward_bound(p, dims, mean, std, x):
 
 
 @pytest.mark.parametrize("dims,n", [(OM.dims_of(256, 3, 6), 1000), (OM.dims_of(40, 2, 6), 77),
-                                    (OM.dims_of(256, 3, 6), 1), (OM.dims_of(100, 1, 3), 4099)])
+                                    (OM.dims_of(256, 3, 6), 1), (OM.dims_of(100, 1, 3), 4099),
+                                    (OM.dims_of(64, 2, 6), 130)])
 def test_forward_within_bf16_bound(dims, n):
+    """Widths that are multiples of 16 (up to 256) run the fused kernel
+    (all layers of 64 samples in one workgroup), the others the
+    layer-by-layer kernels; both are held to the same bound."""
     net, p = _net(dims, seed=n)
     x = synth.mlp_features(n + 1, n)
     mean, std = OM.normalization(x.astype(np.float64))
