@@ -549,7 +549,7 @@ __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out,
 // direction, through one column.  Down rays start at the top with no
 // incoming radiation; up rays start at the bottom with the diffusion
 // approximation I = B + mu dB/dtau.
-template <typename R, int MODE, int NS, int MC>
+template <typename R, int MODE, int NS, int NC, int MC>
 __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane, const R *__restrict__ rec,
                                             const R *__restrict__ phi, const R *__restrict__ popsb,
                                             R *__restrict__ part) {
@@ -565,7 +565,8 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
 #pragma unroll
     for (int q = 0; q < NS; q++) {
         const DevTransition &tr = A.tr[rfl(G.t[q])];
-        sl.kind[q] = rfl(tr.kind);
+        // a group lists its lines first and its NC continua last
+        sl.kind[q] = q >= NS - NC ? 1 : 0;
         sl.l[q] = rfl(tr.l);
         sl.u[q] = rfl(tr.u);
         sl.c[q] = rfl(tr.kind == 1 ? G.t[q] - A.n_lines : 0);
@@ -642,19 +643,9 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     // the spacing to the previous point along the sweep is stored with the
     // lower of the two points
     const int dz_shift = step > 0 ? 0 : 1;
-    PointIn<R, NS, MC> nxt;
-    if (N > 1) {
-        const int k1 = k + step;
-        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k1, gc0 + k1, gc0 + k1 + dz_shift, nxt);
-    }
-    for (int i = 1; i < N; i++) {
+    // one depth step from the inputs `cur` of the new point k
+    auto advance = [&](const PointIn<R, NS, MC> &cur) {
         k += step;
-        const PointIn<R, NS, MC> cur = nxt;
-        if (i + 1 < N) {
-            const int k2 = k + step;
-            load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k2, gc0 + k2, gc0 + k2 + dz_shift,
-                                  nxt);
-        }
         Shared<R, NS> sh;
         shared_terms<R, NS, MC>(cur, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
         const R dz = cur.dz;
@@ -676,12 +667,29 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             S_p[r] = p.S;
         }
         store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
+    };
+    auto load = [&](int kk, PointIn<R, NS, MC> &dst) {
+        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + kk, gc0 + kk, gc0 + kk + dz_shift, dst);
+    };
+    // two input buffers used alternately (the loop is unrolled by two), so
+    // the inputs of the next point load into the buffer not in use and no
+    // registers are copied between steps
+    PointIn<R, NS, MC> ba, bb;
+    if (N > 1) load(k + step, ba);
+    for (int i = 1; i < N; i += 2) {
+        if (i + 1 < N) load(k + 2 * step, bb);
+        advance(ba);
+        if (i + 1 >= N) break;
+        if (i + 2 < N) load(k + 2 * step, ba);
+        advance(bb);
     }
 }
 
-// Groups are ordered by their number of slots; one launch per slot count
-// covers the range [g_begin, g_end) so each variant gets its own registers.
-template <typename R, int MODE, int NS, int MC>
+// Groups are ordered by their number of slots and, within that, by their
+// number of continuum slots; one launch per (slots, continua) covers the
+// range [g_begin, g_end), so each variant gets its own registers and the
+// line / continuum choice of every slot is fixed at compile time.
+template <typename R, int MODE, int NS, int NC, int MC>
 __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end, const R *__restrict__ rec,
                                                const R *__restrict__ phi, const R *__restrict__ popsb,
                                                R *__restrict__ part) {
@@ -696,7 +704,7 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
         if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
         slot = rfl(a.retire_list[blockIdx.y]);
     }
-    sweep_group<R, MODE, NS, MC>(a, grp, slot, lane, rec, phi, popsb, part);
+    sweep_group<R, MODE, NS, NC, MC>(a, grp, slot, lane, rec, phi, popsb, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1330,8 +1338,8 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     const int NG = static_cast<int>(H.groups.size());
     std::vector<int> order(NG);
     for (int i = 0; i < NG; i++) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return H.groups[x].n_slots < H.groups[y].n_slots; });
+    auto cls = [&](int x) { return group_class(H.groups[x].n_slots, H.groups[x].n_slots - H.groups[x].n_line_slots); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls(x) < cls(y); });
     auto permute = [&](auto &v, int per_group) {
         auto w = v;
         for (int i = 0; i < NG; i++)
@@ -1349,10 +1357,10 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     D.T = static_cast<int>(atom->tr.size()); D.NL = static_cast<int>(atom->lam.size()); D.n_mu = n_mu;
     D.n_groups = NG; D.n_keys = H.n_keys; D.ray_cols = H.ray_cols;
     D.mc = shape.mc; D.pack = shape.pack;
-    for (int n = 0; n <= kMaxSlots + 1; n++) {
+    for (int id = 0; id <= kGroupClasses; id++) {
         int c = 0;
-        while (c < NG && H.groups[c].n_slots < n) c++;
-        D.g_begin[n] = c;
+        while (c < NG && group_class(H.groups[c].n_slots, H.groups[c].n_slots - H.groups[c].n_line_slots) < id) c++;
+        D.g_begin[id] = c;
     }
     D.mass = atom->mass; D.abund = atom->abund; D.c_bg = atom->c_bg; D.bg_kind = atom->bg_kind;
     std::vector<DevTransition> tr(D.T);
@@ -1601,14 +1609,25 @@ void launch_se(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
     }
 }
 
-template <typename R, int MODE, int NS, int MC>
+template <typename R, int MODE, int NS, int NC, int MC>
 void launch_sweep_range(const RunArgs &a, hipStream_t st) {
-    const int gb = a.A.g_begin[NS], ge = a.A.g_begin[NS + 1];
+    const int id = group_class(NS, NC);
+    const int gb = a.A.g_begin[id], ge = a.A.g_begin[id + 1];
     if (ge <= gb) return;
     const R *popsb = sizeof(R) == 8 ? reinterpret_cast<const R *>(a.pops) : reinterpret_cast<const R *>(a.popsf);
-    hipLaunchKernelGGL((k_sweep<R, MODE, NS, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge,
+    hipLaunchKernelGGL((k_sweep<R, MODE, NS, NC, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge,
                        reinterpret_cast<const R *>(a.rec), reinterpret_cast<const R *>(a.phi), popsb,
                        reinterpret_cast<R *>(a.part));
+}
+
+// every (slots, continua) class of NS slots, in class order
+template <typename R, int MODE, int NS, int MC>
+void launch_sweep_ns(const RunArgs &a, hipStream_t st) {
+    launch_sweep_range<R, MODE, NS, 0, MC>(a, st);
+    launch_sweep_range<R, MODE, NS, 1, MC>(a, st);
+    if constexpr (NS >= 2) launch_sweep_range<R, MODE, NS, 2, MC>(a, st);
+    if constexpr (NS >= 3) launch_sweep_range<R, MODE, NS, 3, MC>(a, st);
+    if constexpr (NS >= 4) launch_sweep_range<R, MODE, NS, 4, MC>(a, st);
 }
 
 // The launches for the different slot counts touch disjoint rate sums, so
@@ -1641,20 +1660,21 @@ struct SideStreams {
 template <typename R, int MODE, int MC>
 void launch_sweep_mc(const RunArgs &a, hipStream_t st, SideStreams *side) {
     int used = 0;
-    for (int ns = 1; ns <= kMaxSlots; ns++) used += a.A.g_begin[ns + 1] > a.A.g_begin[ns];
+    for (int ns = 1; ns <= kMaxSlots; ns++)
+        used += a.A.g_begin[group_class(ns + 1, 0)] > a.A.g_begin[group_class(ns, 0)];
     if (!side || !side->on || used < 2) {
-        launch_sweep_range<R, MODE, 1, MC>(a, st);
-        launch_sweep_range<R, MODE, 2, MC>(a, st);
-        launch_sweep_range<R, MODE, 3, MC>(a, st);
-        launch_sweep_range<R, MODE, 4, MC>(a, st);
+        launch_sweep_ns<R, MODE, 1, MC>(a, st);
+        launch_sweep_ns<R, MODE, 2, MC>(a, st);
+        launch_sweep_ns<R, MODE, 3, MC>(a, st);
+        launch_sweep_ns<R, MODE, 4, MC>(a, st);
         return;
     }
     (void)hipEventRecord(side->fork, st);
     for (int i = 0; i < kMaxSlots; i++) (void)hipStreamWaitEvent(side->s[i], side->fork, 0);
-    launch_sweep_range<R, MODE, 1, MC>(a, side->s[0]);
-    launch_sweep_range<R, MODE, 2, MC>(a, side->s[1]);
-    launch_sweep_range<R, MODE, 3, MC>(a, side->s[2]);
-    launch_sweep_range<R, MODE, 4, MC>(a, side->s[3]);
+    launch_sweep_ns<R, MODE, 1, MC>(a, side->s[0]);
+    launch_sweep_ns<R, MODE, 2, MC>(a, side->s[1]);
+    launch_sweep_ns<R, MODE, 3, MC>(a, side->s[2]);
+    launch_sweep_ns<R, MODE, 4, MC>(a, side->s[3]);
     for (int i = 0; i < kMaxSlots; i++) {
         (void)hipEventRecord(side->join[i], side->s[i]);
         (void)hipStreamWaitEvent(st, side->join[i], 0);

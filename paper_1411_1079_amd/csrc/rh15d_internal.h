@@ -31,6 +31,11 @@ constexpr double kBgTheta = 8750.0;
 constexpr int kMaxSlots = 4;
 constexpr int kMaxPairs = kMaxSlots * (kMaxSlots - 1);
 constexpr int kMaxKeys = 2 * kMaxSlots + kMaxPairs;
+// Groups are classed by (slots n, continuum slots c), c <= n <= kMaxSlots,
+// in the order of n, then c; class ids run over 0 .. kGroupClasses - 1
+// (n = 0 is not a real group but keeps the formula simple).
+constexpr int kGroupClasses = (kMaxSlots + 1) * (kMaxSlots + 2) / 2 + (kMaxSlots + 2);
+__host__ __device__ constexpr int group_class(int n, int c) { return n * (n + 1) / 2 + c; }
 constexpr int kWave = 64;
 
 struct HostTransition {
@@ -88,7 +93,7 @@ struct DevAtom {
     int L, n_lines, n_cont, T, NL, n_mu;
     int n_groups, n_keys;       // ray groups and rate keys per depth
     int mc, pack;               // angles per lane, packing of wavelengths into groups
-    int g_begin[kMaxSlots + 2]; // groups with n slots are [g_begin[n], g_begin[n+1])
+    int g_begin[kGroupClasses + 1]; // groups of class c (group_class) are [g_begin[c], g_begin[c+1])
     int ray_cols;               // line rays per depth row: sum over lines of 2 n_act n_mu
     int pad0;
     double mass, abund, c_bg;
