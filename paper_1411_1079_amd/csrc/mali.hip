@@ -1001,64 +1001,72 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
 // ---------------------------------------------------------------------------
 // Opacity and source function of the vertical (mu = 1, upward) ray at
 // wavelength j, depth point k; line profiles come from the prepared table.
-// The prepared tables (per-depth records, line profiles) are read in the
-// sweep's precision TB; the arithmetic runs in FP64 for both forms: the
-// emergent intensity spans far more decades than FP32 can hold (the Planck
-// function's Wien tail in the far ultraviolet), and this one ray per
-// wavelength costs a few percent of one iteration.  One thread per
-// (column, wavelength); the active transitions of the wavelength are
-// unpacked once, and each depth point's inputs are loaded one step ahead of
-// their use.
+// One thread per (column, wavelength); the active transitions of the
+// wavelength are unpacked once, and each depth point's inputs are loaded one
+// step ahead of their use.  The prepared tables (per-depth records, line
+// profiles) are read in the sweep's precision TB and the arithmetic runs in
+// AR: FP64 for the plain path; FP32 for the precision form, where the
+// emergent intensity spans more decades than FP32 holds (the Planck
+// function's Wien tail in the far ultraviolet), so every emissivity, source
+// function and intensity of the wavelength carries the factor
+// exp(h nu / k T_max) of the column's hottest point, removed in FP64 at the
+// end.  Opacities are not scaled.
+template <typename AR>
 struct EmTrans {
     int na;
     int kind[kMaxSlots], l[kMaxSlots], u[kMaxSlots], col[kMaxSlots];  // col: profile column or continuum index
-    double cblu[kMaxSlots], cbul[kMaxSlots], ca[kMaxSlots], alpha[kMaxSlots];
+    AR cblu[kMaxSlots], cbul[kMaxSlots], ca[kMaxSlots], alpha[kMaxSlots];
 };
 
+template <typename AR>
 struct EmIn {
-    double invT, kbg, dz;
-    double f[kMaxSlots];               // profile value (lines) or continuum G factor of the record
-    double nl[kMaxSlots], nu[kMaxSlots];
+    AR invT, kbg, dz;
+    AR f[kMaxSlots];               // profile value (lines) or continuum G factor of the record
+    AR nl[kMaxSlots], nu[kMaxSlots];
 };
 
-template <typename TB>
+template <typename TB, typename AR>
 __device__ __forceinline__ void em_load(const TB *__restrict__ rec, const TB *__restrict__ phi,
                                         const double *__restrict__ pops, int rec_w, int ray_cols, int L,
-                                        const EmTrans &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn &p) {
+                                        const EmTrans<AR> &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn<AR> &p) {
     const TB *r = rec + gc * rec_w;
-    p.invT = static_cast<double>(r[1]);
-    p.kbg = static_cast<double>(r[2]);
-    p.dz = static_cast<double>(rec[gc_dz * rec_w]);
+    p.invT = static_cast<AR>(r[1]);
+    p.kbg = static_cast<AR>(r[2]);
+    p.dz = static_cast<AR>(rec[gc_dz * rec_w]);
     const double *n = pops + g * L;
     const TB *pr = phi + gc * ray_cols;
 #pragma unroll
     for (int q = 0; q < kMaxSlots; q++) {
         if (q < et.na) {
-            p.nl[q] = n[et.l[q]];
-            p.nu[q] = n[et.u[q]];
-            p.f[q] = static_cast<double>(et.kind[q] == 0 ? pr[et.col[q]] : r[kRecHead + et.col[q]]);
+            p.nl[q] = static_cast<AR>(n[et.l[q]]);
+            p.nu[q] = static_cast<AR>(n[et.u[q]]);
+            p.f[q] = static_cast<AR>(et.kind[q] == 0 ? pr[et.col[q]] : r[kRecHead + et.col[q]]);
         }
     }
 }
 
-__device__ __forceinline__ void em_point(const EmIn &in, const EmTrans &et, double hnu_k, double two_hnu3, double lamfac,
-                                         double &chi, double &S, double &B) {
-    const double x = hnu_k * in.invT;
-    const double ex = d_exp(-x), omx = x > 0.5 ? 1.0 - ex : -d_expm1(-x);
-    B = two_hnu3 * ex / omx;
-    double c = in.kbg * lamfac;
-    double e = c * B;
+// chi, and the source function and Planck function times exp(x0)
+template <typename AR>
+__device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &et, AR hnu_k, AR two_hnu3, AR lamfac,
+                                         AR x0, AR scale, AR &chi, AR &S, AR &B) {
+    const AR x = hnu_k * in.invT;
+    const AR ex = d_exp(-x), omx = x > AR(0.5) ? AR(1) - ex : -d_expm1(-x);
+    const AR exs = sizeof(AR) == 8 ? ex : d_exp(x0 - x);
+    B = two_hnu3 * exs / omx;
+    AR c = in.kbg * lamfac;
+    AR e = c * B;
 #pragma unroll
     for (int q = 0; q < kMaxSlots; q++) {
         if (q < et.na) {
-            double vlu, vul, U;
+            AR vlu, vul, U;
             if (et.kind[q] == 0) {
                 vlu = et.cblu[q] * in.f[q];
                 vul = et.cbul[q] * in.f[q];
-                U = et.ca[q] * in.f[q];
+                U = et.ca[q] * in.f[q] * scale;
             } else {
-                const double G = in.f[q] * ex;
-                vlu = et.alpha[q]; vul = G * et.alpha[q]; U = two_hnu3 * G * et.alpha[q];
+                vlu = et.alpha[q];
+                vul = in.f[q] * ex * et.alpha[q];
+                U = two_hnu3 * (in.f[q] * exs) * et.alpha[q];
             }
             c += in.nl[q] * vlu - in.nu[q] * vul;
             e += in.nu[q] * U;
@@ -1068,10 +1076,9 @@ __device__ __forceinline__ void em_point(const EmIn &in, const EmTrans &et, doub
     S = e / c;
 }
 
-template <typename TB>
+template <typename TB, typename AR>
 __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restrict__ rec, const TB *__restrict__ phi,
                                                   const double *__restrict__ pops) {
-    using R = double;
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
     const int rec_w = a.rec_w, ray_cols = A.ray_cols, L = A.L;
@@ -1079,10 +1086,10 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
         const int slot = a.retire_list[w / A.NL];
         const int j = (int)(w % A.NL);
         const double nu = A.nu[j];
-        const double hnu_k = kH * nu / kKB;
-        const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
-        const double lamfac = A.lam[j] / kBgLambdaRef;
-        EmTrans et;
+        const AR hnu_k = static_cast<AR>(kH * nu / kKB);
+        const AR two_hnu3 = static_cast<AR>(2.0 * kH * nu * nu * nu / (kC * kC));
+        const AR lamfac = static_cast<AR>(A.lam[j] / kBgLambdaRef);
+        EmTrans<AR> et;
         et.na = A.jact_off[j + 1] - A.jact_off[j];
 #pragma unroll
         for (int q = 0; q < kMaxSlots; q++) {
@@ -1096,43 +1103,51 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
                 if (tr.kind == 0) {
                     et.col[q] = tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i];
                     const double c0 = tr.hnu4pi;
-                    et.cblu[q] = c0 * tr.Blu;
-                    et.cbul[q] = c0 * tr.Bul;
-                    et.ca[q] = c0 * tr.A;
+                    et.cblu[q] = static_cast<AR>(c0 * tr.Blu);
+                    et.cbul[q] = static_cast<AR>(c0 * tr.Bul);
+                    et.ca[q] = static_cast<AR>(c0 * tr.A);
                 } else {
                     et.col[q] = t - A.n_lines;
                     const double r = tr.nu0 / nu;
-                    et.alpha[q] = tr.alpha0 * r * r * r;
+                    et.alpha[q] = static_cast<AR>(tr.alpha0 * r * r * r);
                 }
             }
         }
         const ColGeom cg = geom(a, slot);
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
-        EmIn in;
-        R chi2, S2, B2, chi, S, B;
-        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 2, in);
-        em_point(in, et, hnu_k, two_hnu3, lamfac, chi2, S2, B2);
-        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 1, gc0 + N - 1, gc0 + N - 1, in);
-        em_point(in, et, hnu_k, two_hnu3, lamfac, chi, S, B);
-        const R dtv = R(0.5) * (chi + chi2) * in.dz;
-        R I = dtv > R(0) ? B + (B - B2) / dtv : B;
-        R chi_p = chi, S_p = S;
+        // scaling exponent: h nu / k T at the column's hottest point (FP32 only)
+        AR x0 = AR(0);
+        if (sizeof(AR) == 4) {
+            AR itmin = static_cast<AR>(rec[gc0 * rec_w + 1]);
+            for (int k = 1; k < N; k++) itmin = fmin(itmin, static_cast<AR>(rec[(gc0 + k) * rec_w + 1]));
+            x0 = fmin(hnu_k * itmin, AR(60));
+        }
+        const AR scale = sizeof(AR) == 8 ? AR(1) : d_exp(x0);
+        EmIn<AR> in;
+        AR chi2, S2, B2, chi, S, B;
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 2, in);
+        em_point<AR>(in, et, hnu_k, two_hnu3, lamfac, x0, scale, chi2, S2, B2);
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 1, gc0 + N - 1, gc0 + N - 1, in);
+        em_point<AR>(in, et, hnu_k, two_hnu3, lamfac, x0, scale, chi, S, B);
+        const AR dtv = AR(0.5) * (chi + chi2) * in.dz;
+        AR I = dtv > AR(0) ? B + (B - B2) / dtv : B;
+        AR chi_p = chi, S_p = S;
         // upward from k = N - 2 to the top; the step from k + 1 uses the
         // spacing stored with point k + 1
-        EmIn nxt;
-        em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt);
+        EmIn<AR> nxt;
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt);
         for (int k = N - 2; k >= 0; k--) {
-            const EmIn cur = nxt;
-            if (k > 0) em_load<TB>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + k - 1, gc0 + k - 1, gc0 + k, nxt);
-            em_point(cur, et, hnu_k, two_hnu3, lamfac, chi, S, B);
-            const R x = R(0.5) * (chi_p + chi) * cur.dz;
-            R e, wa, wb;
-            sc_weights<R>(x, e, wa, wb);
+            const EmIn<AR> cur = nxt;
+            if (k > 0) em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + k - 1, gc0 + k - 1, gc0 + k, nxt);
+            em_point<AR>(cur, et, hnu_k, two_hnu3, lamfac, x0, scale, chi, S, B);
+            const AR x = AR(0.5) * (chi_p + chi) * cur.dz;
+            AR e, wa, wb;
+            sc_weights<AR>(x, e, wa, wb);
             I = I * e + wa * S_p + wb * S;
             chi_p = chi; S_p = S;
         }
-        a.spectrum[(size_t)cg.col * A.NL + j] = static_cast<double>(I);
+        a.spectrum[(size_t)cg.col * A.NL + j] = static_cast<double>(I) * exp(-static_cast<double>(x0));
     }
 }
 
@@ -1723,10 +1738,10 @@ struct Launcher {
         if (want_spec) {
             const unsigned eb = grid_for((int64_t)a.S * a.A.NL, 256, 8192);
             if (fp32)
-                hipLaunchKernelGGL(k_emergent<float>, dim3(eb), dim3(256), 0, st, a,
+                hipLaunchKernelGGL((k_emergent<float, float>), dim3(eb), dim3(256), 0, st, a,
                                    reinterpret_cast<const float *>(a.rec), reinterpret_cast<const float *>(a.phi), a.pops);
             else
-                hipLaunchKernelGGL(k_emergent<double>, dim3(eb), dim3(256), 0, st, a,
+                hipLaunchKernelGGL((k_emergent<double, double>), dim3(eb), dim3(256), 0, st, a,
                                    reinterpret_cast<const double *>(a.rec), reinterpret_cast<const double *>(a.phi),
                                    a.pops);
         }
