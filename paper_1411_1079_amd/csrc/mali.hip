@@ -338,34 +338,23 @@ enum { MODE_RATES = 0, MODE_PSI = 1 };
 
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// One DPP stage: the value of another lane of the row (or the broadcast
-// lane), 0 where the pattern has no source or the row is masked off.
-template <int CTRL, int ROWS>
+// One DPP stage of a sum that only lane 63 reads: the value of another lane
+// (row shift) or of the last lane of an earlier row (row broadcast), 0 where
+// the shift has no source.  Every row is written (full row mask) with
+// out-of-range sources zero-filled, so the compiler folds the move into the
+// following add; lanes whose broadcast source is undefined end with values
+// nobody reads, lane 63 with the total of the fixed summation order.
+template <int CTRL>
 __device__ __forceinline__ float dpp_src(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
-template <int CTRL, int ROWS>
+template <int CTRL>
 __device__ __forceinline__ double dpp_src(double v) {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
-
-// Sum over the 64 lanes: an inclusive scan with row shifts 1, 2, 4, 8 and
-// the row broadcasts of lanes 15 and 31; lane 63 ends with the total.  The
-// order of the additions is fixed, so results are reproducible.
-template <typename R>
-__device__ __forceinline__ R wave_total(R v) {
-    v += dpp_src<0x111, 0xf>(v);
-    v += dpp_src<0x112, 0xf>(v);
-    v += dpp_src<0x114, 0xf>(v);
-    v += dpp_src<0x118, 0xf>(v);
-    v += dpp_src<0x142, 0xa>(v);
-    v += dpp_src<0x143, 0xc>(v);
-    return v;
-}
-
 
 // Uniform (per wavefront) description of the transitions a group touches.
 template <typename R, int NS>
@@ -517,6 +506,9 @@ __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi,
 // kernel reads with consecutive depth points in consecutive lanes.
 template <typename R, int NS, int MODE>
 __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int N, int k, int lane) {
+    // the weight products stay separate roundings from the first DPP add
+    // (no contraction into an FMA), so each stage is one DPP add
+#pragma clang fp contract(off)
     constexpr int NK = n_acc<NS, MODE>();
     R v[NK];
 #pragma unroll
@@ -528,17 +520,17 @@ __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out,
         }
     }
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x111, 0xf>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x111>(v[i]);
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x112, 0xf>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x112>(v[i]);
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x114, 0xf>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x114>(v[i]);
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x118, 0xf>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x118>(v[i]);
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x142, 0xa>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x142>(v[i]);
 #pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x143, 0xc>(v[i]);
+    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x143>(v[i]);
     if (lane == kWave - 1) {
 #pragma unroll
         for (int i = 0; i < NK; i++) out[(size_t)i * N + k] = v[i];
