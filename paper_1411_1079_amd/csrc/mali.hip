@@ -57,6 +57,16 @@ __device__ __forceinline__ float d_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
 __device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
 
+// 1 - exp(-x) for x >= 0, given ex = exp(-x): the difference itself where it
+// keeps its relative precision (x > 0.5); below, expm1 in FP64 and in FP32
+// the Taylor series through x^7 (truncation below 2e-7 relative at x = 0.5).
+__device__ __forceinline__ double one_m_exp(double x, double ex) { return x > 0.5 ? 1.0 - ex : -expm1(-x); }
+__device__ __forceinline__ float one_m_exp(float x, float ex) {
+    const float s = x * (1.0f + x * (-1.0f / 2.0f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f +
+                    x * (-1.0f / 720.0f + x * (1.0f / 5040.0f)))))));
+    return x > 0.5f ? 1.0f - ex : s;
+}
+
 // Reciprocals: hardware estimate, refined by Newton steps in FP64.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) {
@@ -69,16 +79,23 @@ __device__ __forceinline__ double rcp(double x) {
 
 // Linear short-characteristic weights (Olson & Kunasz 1987) of an optical
 // step x: I_b = I_a e + wa S_a + wb S_b.  Below the threshold the weights
-// come from their Taylor series (through x^6), which avoids the
-// cancellation in 1 - (1 - e^-x)/x.
+// come from their Taylor series, which avoids the cancellation in
+// 1 - (1 - e^-x)/x: through x^6 in FP64 (below 1e-2), in FP32 (below 0.1)
+// through x^4 for wb and x^5 for wa, whose truncation (3e-7 and 3e-8
+// relative at 0.1) is below the FP32 rounding of the rest of the step.
 template <typename R>
 __device__ __forceinline__ void sc_weights(R x, R &e, R &wa, R &wb) {
     const R thr = sizeof(R) == 8 ? R(1.0e-2) : R(0.1);
     if (x < thr) {
-        wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * (R(-1.0 / 120.0) +
-             x * (R(1.0 / 720.0) + x * R(-1.0 / 5040.0))))));
-        wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
-             x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
+        if constexpr (sizeof(R) == 8) {
+            wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * (R(-1.0 / 120.0) +
+                 x * (R(1.0 / 720.0) + x * R(-1.0 / 5040.0))))));
+            wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
+                 x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
+        } else {
+            wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * R(-1.0 / 120.0))));
+            wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) + x * R(1.0 / 144.0)))));
+        }
         e = d_exp(-x);
     } else if constexpr (sizeof(R) == 8) {
         const R one_m_e = -d_expm1(-x);
@@ -413,8 +430,7 @@ __device__ __forceinline__ void shared_terms(const PointIn<R, NS, MC> &in, const
                                              R hnu_k, R two_hnu3, R lamfac, Shared<R, NS> &sh) {
     const R x = hnu_k * in.invT;
     const R ex = d_exp(-x);  // exp(-h nu / k T)
-    const R omx = x > R(0.5) ? R(1) - ex : -d_expm1(-x);
-    sh.B = two_hnu3 * ex * rcp(omx);
+    sh.B = two_hnu3 * ex * rcp(one_m_exp(x, ex));
     const R chibg = in.kbg * lamfac;
     sh.etabg = chibg * sh.B;
     R chi = chibg, eta = sh.etabg;
@@ -498,43 +514,76 @@ __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi,
     }
 }
 
-// Sums the lanes' contributions of one depth point over the wavefront and
-// stores them (lane 63 holds the totals).  Each DPP stage is applied to all
-// sums before the next, so the independent sums fill each other's DPP wait
-// states, and lane 63 writes all totals under one branch.  `out` is
-// key-major ([key][depth] per column, N depths), which the rate-equation
-// kernel reads with consecutive depth points in consecutive lanes.
+// Sums over the wavefront, through LDS.  Each depth point's per-lane terms
+// (one row of 64 values per sum key, weighted by the lane's slot factor)
+// go to the wavefront's own LDS area; after B points the block's S = K B
+// rows are summed, P lanes per row, each lane reading every P-th 16-byte
+// chunk of the row (row pitch padded by P chunks, so the lanes of one read
+// cover distinct banks), the P partial sums are combined by DPP, and the
+// first lane of each row stores the total.  The data movement of the sums
+// runs on the LDS pipe and the vector unit adds each value once, where a
+// DPP tree per key and point spends six vector instructions on it.
+// `out` is key-major ([key][depth] per column, N depths), which the
+// rate-equation kernel reads with consecutive depth points in consecutive
+// lanes.
 template <typename R, int NS, int MODE>
-__device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out, int N, int k, int lane) {
-    // the weight products stay separate roundings from the first DPP add
-    // (no contraction into an FMA), so each stage is one DPP add
-#pragma clang fp contract(off)
-    constexpr int NK = n_acc<NS, MODE>();
-    R v[NK];
+struct Red {
+    static constexpr int K = n_acc<NS, MODE>();            // sums per depth point
+    static constexpr int T = sizeof(R) == 4 ? 16 : 8;       // rows per block aimed at
+    static constexpr int B = K >= T ? 1 : T / K;            // depth points per block
+    static constexpr int S = K * B;                         // rows per block
+    static constexpr int P = S <= 16 ? 4 : (S <= 32 ? 2 : 1);
+    static constexpr int CE = 16 / static_cast<int>(sizeof(R));
+    static constexpr int STRIDE = kWave + CE * P;           // row pitch, elements
+    static constexpr int SIZE = S * STRIDE;                 // elements per wavefront
+    static_assert(S * P <= kWave, "rows of a block exceed the wavefront");
+};
+
+template <typename R, int NS, int MODE>
+__device__ __forceinline__ void red_put(const R *acc, const R *kapj, R *lds, int b, int lane) {
+    using RS = Red<R, NS, MODE>;
 #pragma unroll
-    for (int i = 0; i < NK; i++) {
-        v[i] = acc[i];
+    for (int i = 0; i < RS::K; i++) {
+        R v = acc[i];
         if constexpr (MODE == MODE_RATES) {
             const int q = i < 2 * NS ? (i % NS) : (i - 2 * NS) / (NS > 1 ? NS - 1 : 1);
-            v[i] *= kapj[q];
+            v *= kapj[q];
+        }
+        lds[(i * RS::B + b) * RS::STRIDE + lane] = v;
+    }
+}
+
+// Totals of the block's first nb points, stored at depths k_first,
+// k_first + step, ...
+template <typename R, int NS, int MODE>
+__device__ __forceinline__ void red_flush(const R *lds, R *out, int N, int k_first, int step, int nb, int lane) {
+    using RS = Red<R, NS, MODE>;
+    using V = R __attribute__((ext_vector_type(RS::CE)));
+    // the rows were written by other lanes of this wavefront: keep the
+    // reads after the writes (LDS executes one wavefront's operations in
+    // order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int s = lane / RS::P, p = lane % RS::P;
+    R sum = R(0);
+    if (s < RS::S) {
+        const V *row = reinterpret_cast<const V *>(lds + s * RS::STRIDE);
+#pragma unroll
+        for (int j = 0; j < kWave / (RS::CE * RS::P); j++) {
+            const V c = row[p + j * RS::P];
+#pragma unroll
+            for (int e = 0; e < RS::CE; e++) sum += c[e];
         }
     }
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x111>(v[i]);
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x112>(v[i]);
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x114>(v[i]);
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x118>(v[i]);
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x142>(v[i]);
-#pragma unroll
-    for (int i = 0; i < NK; i++) v[i] += dpp_src<0x143>(v[i]);
-    if (lane == kWave - 1) {
-#pragma unroll
-        for (int i = 0; i < NK; i++) out[(size_t)i * N + k] = v[i];
-    }
+    if constexpr (RS::P >= 2) sum += dpp_src<0xb1>(sum);   // quad_perm [1,0,3,2]
+    if constexpr (RS::P >= 4) sum += dpp_src<0x4e>(sum);   // quad_perm [2,3,0,1]
+    const int key = s / RS::B, b = s % RS::B;
+    if (p == 0 && s < RS::S && b < nb) out[(size_t)key * N + k_first + b * step] = sum;
+    // the next block's writes stay after these reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One wavefront: 64 lanes, each one wavelength and MC angles of one
@@ -544,7 +593,7 @@ __device__ __forceinline__ void store_point(const R *acc, const R *kapj, R *out,
 template <typename R, int MODE, int NS, int NC, int MC>
 __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane, const R *__restrict__ rec,
                                             const R *__restrict__ phi, const R *__restrict__ popsb,
-                                            R *__restrict__ part) {
+                                            R *__restrict__ part, R *lds) {
     const DevAtom &A = a.A;
     const ColGeom cg = geom(a, slot);
     const int64_t g0 = cg.g0;
@@ -590,6 +639,16 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         invmu[r] = R(1) / mu[r];
         wmu[r] = static_cast<R>(A.wmu[m0 + r]);
     }
+    if constexpr (MC == 1) {
+        // one angle per lane: its weight joins the lane's per-slot factors
+        // applied once per depth point, and the rays add unweighted terms
+#pragma unroll
+        for (int q = 0; q < NS; q++) {
+            kapj[q] *= wmu[0];
+            wpsi[q] *= wmu[0];
+        }
+        wmu[0] = R(1);
+    }
     R *out = part + gc0 * A.n_keys + (size_t)key_off * N;
     const int rec_w = a.rec_w, L = A.L;
     constexpr int NK = n_acc<NS, MODE>();
@@ -600,6 +659,21 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     const int ray_cols = A.ray_cols;
 #pragma unroll
     for (int i = 0; i < NK; i++) acc[i] = R(0);
+    // reduction blocks: the current point's row within its block, the depth
+    // of the block's first point and the points still to come
+    using RS = Red<R, NS, MODE>;
+    int rb = 0, k_first = k, left = N;
+    auto emit = [&]() {
+        red_put<R, NS, MODE>(acc, kapj, lds, rb, lane);
+        left--;
+        if (rb == RS::B - 1 || left == 0) {
+            red_flush<R, NS, MODE>(lds, out, N, k_first, step, rb + 1, lane);
+            rb = 0;
+            k_first = k + step;
+        } else {
+            rb++;
+        }
+    };
     {
         PointIn<R, NS, MC> in0;
         load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k, gc0 + k, gc0 + k, in0);
@@ -630,7 +704,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
+        emit();
     }
     // the spacing to the previous point along the sweep is stored with the
     // lower of the two points
@@ -651,14 +725,14 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
             const R up = I[r] * e + wa * S_p[r];
-            const R Ieff = up + wb * sh.etabg * p.rchi;
             const R psi = wb * p.rchi;
+            const R Ieff = up + psi * sh.etabg;
             I[r] = up + wb * p.S;
             contribute<R, NS, MODE>(p, wpsi, wmu[r], Ieff, psi, acc);
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
-        store_point<R, NS, MODE>(acc, kapj, out, N, k, lane);
+        emit();
     };
     auto load = [&](int kk, PointIn<R, NS, MC> &dst) {
         load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + kk, gc0 + kk, gc0 + kk + dz_shift, dst);
@@ -685,6 +759,7 @@ template <typename R, int MODE, int NS, int NC, int MC>
 __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end, const R *__restrict__ rec,
                                                const R *__restrict__ phi, const R *__restrict__ popsb,
                                                R *__restrict__ part) {
+    __shared__ __align__(16) R red_lds[4 * Red<R, NS, MODE>::SIZE];
     const int grp = rfl(g_begin + blockIdx.x * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (grp >= g_end) return;
@@ -696,7 +771,8 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
         if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
         slot = rfl(a.retire_list[blockIdx.y]);
     }
-    sweep_group<R, MODE, NS, NC, MC>(a, grp, slot, lane, rec, phi, popsb, part);
+    sweep_group<R, MODE, NS, NC, MC>(a, grp, slot, lane, rec, phi, popsb, part,
+                                     red_lds + (threadIdx.x >> 6) * Red<R, NS, MODE>::SIZE);
 }
 
 // ---------------------------------------------------------------------------
@@ -1042,7 +1118,7 @@ template <typename AR>
 __device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &et, AR hnu_k, AR two_hnu3, AR lamfac,
                                          AR x0, AR scale, AR &chi, AR &S, AR &B) {
     const AR x = hnu_k * in.invT;
-    const AR ex = d_exp(-x), omx = x > AR(0.5) ? AR(1) - ex : -d_expm1(-x);
+    const AR ex = d_exp(-x), omx = one_m_exp(x, ex);
     const AR exs = sizeof(AR) == 8 ? ex : d_exp(x0 - x);
     B = two_hnu3 * exs / omx;
     AR c = in.kbg * lamfac;
