@@ -62,9 +62,14 @@ __device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
 // the Taylor series through x^7 (truncation below 2e-7 relative at x = 0.5).
 __device__ __forceinline__ double one_m_exp(double x, double ex) { return x > 0.5 ? 1.0 - ex : -expm1(-x); }
 __device__ __forceinline__ float one_m_exp(float x, float ex) {
-    const float s = x * (1.0f + x * (-1.0f / 2.0f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f +
-                    x * (-1.0f / 720.0f + x * (1.0f / 5040.0f)))))));
-    return x > 0.5f ? 1.0f - ex : s;
+    float r = 1.0f - ex;
+    // the series only when a lane of the wavefront needs it
+    if (__builtin_amdgcn_ballot_w64(!(x > 0.5f)) != 0) {
+        const float s = x * (1.0f + x * (-1.0f / 2.0f + x * (1.0f / 6.0f + x * (-1.0f / 24.0f + x * (1.0f / 120.0f +
+                        x * (-1.0f / 720.0f + x * (1.0f / 5040.0f)))))));
+        r = x > 0.5f ? r : s;
+    }
+    return r;
 }
 
 // Reciprocals: hardware estimate, refined by Newton steps in FP64.
@@ -491,16 +496,18 @@ template <int NS, int MODE>
 constexpr int n_acc() { return MODE == MODE_PSI ? NS : 2 * NS + NS * (NS - 1); }
 
 // Adds one ray's contributions (angle weight wmu) into the lane's sums.
-template <typename R, int NS, int MODE>
+// FIRST: the point's first ray, whose terms start the sums.
+template <typename R, int NS, int MODE, bool FIRST>
 __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi, R wmu, R Ieff, R psi, R *acc) {
+    auto add = [&](int i, R t) { acc[i] = FIRST ? t : acc[i] + t; };
     if constexpr (MODE == MODE_PSI) {
 #pragma unroll
-        for (int q = 0; q < NS; q++) acc[q] += wpsi[q] * wmu * p.ph[q] * psi;
+        for (int q = 0; q < NS; q++) add(q, wpsi[q] * wmu * p.ph[q] * psi);
     } else {
 #pragma unroll
         for (int q = 0; q < NS; q++) {
-            acc[q] += wmu * p.vlu[q] * Ieff;
-            acc[NS + q] += wmu * (p.U[q] * (R(1) - p.cht[q] * psi) + p.vul[q] * Ieff);
+            add(q, wmu * p.vlu[q] * Ieff);
+            add(NS + q, wmu * (p.U[q] * (R(1) - p.cht[q] * psi) + p.vul[q] * Ieff));
         }
 #pragma unroll
         for (int q = 0; q < NS; q++) {
@@ -508,7 +515,7 @@ __device__ __forceinline__ void contribute(const RayPt<R, NS> &p, const R *wpsi,
             for (int q2 = 0; q2 < NS; q2++) {
                 if (q2 == q) continue;
                 const int rank = q * (NS - 1) + (q2 < q ? q2 : q2 - 1);
-                acc[2 * NS + rank] += wmu * p.cht[q] * psi * p.U[q2];
+                add(2 * NS + rank, wmu * p.cht[q] * psi * p.U[q2]);
             }
         }
     }
@@ -573,7 +580,7 @@ __device__ __forceinline__ void red_flush(const R *lds, R *out, int N, int k_fir
         for (int j = 0; j < kWave / (RS::CE * RS::P); j++) {
             const V c = row[p + j * RS::P];
 #pragma unroll
-            for (int e = 0; e < RS::CE; e++) sum += c[e];
+            for (int e = 0; e < RS::CE; e++) sum = (j == 0 && e == 0) ? c[0] : sum + c[e];
         }
     }
     if constexpr (RS::P >= 2) sum += dpp_src<0xb1>(sum);   // quad_perm [1,0,3,2]
@@ -632,11 +639,11 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         // Psi* weights: W phi~ for lines, W / sum W for continua (W = w_nu w_mu / 2)
         wpsi[q] = sl.kind[q] == 1 ? R(0.5) * wj / sl.wsum[q] : R(0.5) * wj;
     }
-    R mu[MC], invmu[MC], wmu[MC];
+    R mu[MC], hinvmu[MC], wmu[MC];     // hinvmu = 1 / (2 mu)
 #pragma unroll
     for (int r = 0; r < MC; r++) {
         mu[r] = static_cast<R>(A.mu[m0 + r]);
-        invmu[r] = R(1) / mu[r];
+        hinvmu[r] = R(0.5) / mu[r];
         wmu[r] = static_cast<R>(A.wmu[m0 + r]);
     }
     if constexpr (MC == 1) {
@@ -658,7 +665,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     R acc[NK];
     const int ray_cols = A.ray_cols;
 #pragma unroll
-    for (int i = 0; i < NK; i++) acc[i] = R(0);
+    for (int i = 0; i < NK; i++) acc[i] = R(0);   // every point's first ray sets them
     // reduction blocks: the current point's row within its block, the depth
     // of the block's first point and the points still to come
     using RS = Red<R, NS, MODE>;
@@ -699,7 +706,8 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
                 const R dtv = R(0.5) * (p.chi + p2.chi) * dzb;
                 I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
             }
-            contribute<R, NS, MODE>(p, wpsi, wmu[r], I0, R(0), acc);
+            if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], I0, R(0), acc);
+            else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], I0, R(0), acc);
             I[r] = I0;
             chi_p[r] = p.chi;
             S_p[r] = p.S;
@@ -716,19 +724,18 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         shared_terms<R, NS, MC>(cur, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
         const R dz = cur.dz;
 #pragma unroll
-        for (int j = 0; j < NK; j++) acc[j] = R(0);
-#pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
             ray_terms<R, NS, MC>(sl, sh, cur, r, p);
-            const R x = R(0.5) * (chi_p[r] + p.chi) * dz * invmu[r];
+            const R x = (chi_p[r] + p.chi) * dz * hinvmu[r];
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
             const R up = I[r] * e + wa * S_p[r];
             const R psi = wb * p.rchi;
             const R Ieff = up + psi * sh.etabg;
             I[r] = up + wb * p.S;
-            contribute<R, NS, MODE>(p, wpsi, wmu[r], Ieff, psi, acc);
+            if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], Ieff, psi, acc);
+            else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], Ieff, psi, acc);
             chi_p[r] = p.chi;
             S_p[r] = p.S;
         }
