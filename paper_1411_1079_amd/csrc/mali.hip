@@ -123,10 +123,14 @@ template <typename F>
 __device__ __forceinline__ cplx_t<F> cmul(cplx_t<F> a, cplx_t<F> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 template <typename F>
 __device__ __forceinline__ cplx_t<F> cadd(cplx_t<F> a, F b) { return {a.r + b, a.i}; }
+// real part of a / b; in FP32 through the hardware reciprocal (about 1 ulp),
+// well inside the approximation's own error
 template <typename F>
-__device__ __forceinline__ cplx_t<F> cdiv(cplx_t<F> a, cplx_t<F> b) {
+__device__ __forceinline__ F cdiv_re(cplx_t<F> a, cplx_t<F> b) {
     const F d = b.r * b.r + b.i * b.i;
-    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+    const F n = a.r * b.r + a.i * b.i;
+    if constexpr (sizeof(F) == 4) return n * __builtin_amdgcn_rcpf(d);
+    else return n / d;
 }
 __device__ __forceinline__ double d_cos(double x) { return cos(x); }
 __device__ __forceinline__ float d_cos(float x) { return __cosf(x); }
@@ -141,13 +145,13 @@ __device__ __noinline__ F voigt_w4(F a, F v) {
     const F s = fabs(v) + a;
     if (s >= F(15.0)) {
         C den = cadd(cmul(t, t), F(0.5));
-        return cdiv(C{F(0.5641896) * t.r, F(0.5641896) * t.i}, den).r;
+        return cdiv_re(C{F(0.5641896) * t.r, F(0.5641896) * t.i}, den);
     }
     if (s >= F(5.5)) {
         const C u = cmul(t, t);
         const C num = cmul(t, cadd(C{F(0.5641896) * u.r, F(0.5641896) * u.i}, F(1.410474)));
         const C den = cadd(cmul(u, cadd(u, F(3.0))), F(0.75));
-        return cdiv(num, den).r;
+        return cdiv_re(num, den);
     }
     if (a >= F(0.195) * fabs(v) - F(0.176)) {
         C num = {F(0.5642236), F(0)};
@@ -161,7 +165,7 @@ __device__ __noinline__ F voigt_w4(F a, F v) {
         den = cadd(cmul(den, t), F(39.27121));
         den = cadd(cmul(den, t), F(38.82363));
         den = cadd(cmul(den, t), F(16.4955));
-        return cdiv(num, den).r;
+        return cdiv_re(num, den);
     }
     const C u = cmul(t, t);
     C p = {F(0.56419), F(0)};
@@ -179,8 +183,8 @@ __device__ __noinline__ F voigt_w4(F a, F v) {
     q = cadd(cmul(q, u), F(9022.228));
     q = cadd(cmul(q, u), F(-24322.84));
     q = cadd(cmul(q, u), F(32066.6));
-    const C frac = cdiv(cmul(t, p), q);
-    return d_exp(u.r) * d_cos(u.i) - frac.r;
+    const F frac = cdiv_re(cmul(t, p), q);
+    return d_exp(u.r) * d_cos(u.i) - frac;
 }
 
 template <typename R>
@@ -323,6 +327,7 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const R adamp = static_cast<R>(tr.gamma / (4.0 * kPI * dnd));
     const double rdnd = 1.0 / dnd;
     const double pre = rdnd / sqrt(kPI);
+    const double vzc = vz / kC;
     const int r0 = A.prof_off[t], nr = A.prof_off[t + 1] - r0;
     const double *pnu = A.prof_nu + r0, *pmus = A.prof_mus + r0, *pw = A.prof_w + r0;
     R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
@@ -331,7 +336,7 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     // written unnormalised, then scaled once the wavefront has the sum
     double acc = 0.0;
     for (int r = lane; r < nr; r += kWave) {
-        const double v = (pnu[r] - tr.nu0 * (1.0 + pmus[r] * vz / kC)) * rdnd;
+        const double v = (pnu[r] - tr.nu0 * (1.0 + pmus[r] * vzc)) * rdnd;
         const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
         const R ph = H * static_cast<R>(pre);
         acc += pw[r] * static_cast<double>(ph);
