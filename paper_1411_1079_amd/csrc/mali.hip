@@ -234,6 +234,7 @@ struct RunArgs {
     void *part;               // rate keys: slot block at slot*ND*n_keys, [key][N]
     void *rec;                // [gc][rec_w] per-depth data of the sweep (sweep precision)
     float *popsf;             // [gc][L] FP32 copy of the populations (FP32 form)
+    double *rad;              // [L*L][gc] radiative part of the rate-matrix entries (i, j)
     double *nse;              // [gc][L] rate-equation solution
     double *dk;               // [gc] max relative change per depth point
     int *flag;                // [gc] 0 ok, 1 non-finite/non-positive, 2 singular
@@ -804,11 +805,58 @@ __device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransitio
 
 // Sum of the rate sums `keys[b..e)` at depth k of a column whose key-major
 // block ([key][depth], N depths) starts at `part`.
+// The loads of four keys are issued before their sum, which adds them in
+// key order.
 template <typename R>
 __device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e, int N, int k) {
     double v = 0.0;
-    for (int i = b; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
+    int i = b;
+    for (; i + 4 <= e; i += 4) {
+        R x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = part[(size_t)keys[i + u] * N + k];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v += static_cast<double>(x[u]);
+    }
+    for (; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
     return v;
+}
+
+// Radiative part of the rate-matrix entry (i, j) = blockIdx.y / L, % L at
+// every depth point of the active slots: the sweep's rate sums of the
+// upward or downward transition from j to i, plus the cross terms of
+// overlapping transitions, added in key order.  One lane per depth point
+// and entry, with nothing else live, so many lanes' loads are in flight
+// together; the rate-equation kernel adds the collisional rates and solves.
+template <typename R>
+__global__ __launch_bounds__(256) void k_rad_rates(RunArgs a) {
+    const DevAtom &A = a.A;
+    const int L = A.L;
+    const int ij = blockIdx.y;
+    const int i = ij / L, j = ij % L;
+    if (i == j) return;
+    const size_t P = (size_t)a.S * a.ND;
+    const int64_t gc = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gc >= (int64_t)P) return;
+    const int slot = (int)(gc / a.ND);
+    if (a.slot_state[slot] != SLOT_ACTIVE) return;
+    const ColGeom cg = geom(a, slot);
+    const int k = (int)(gc - cg.gc0);
+    if (k >= cg.N) return;
+    const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
+    const int N = cg.N;
+    double v = 0.0;
+    const int tu = A.up_t[ij];
+    if (tu >= 0) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1], N, k);
+    const int td = A.dn_t[ij];
+    if (td >= 0) v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1], N, k);
+    for (int x = A.xe_off[ij]; x < A.xe_off[ij + 1]; x++) {
+        const int e = A.xe_val[x];
+        const int xp = (e > 0 ? e : -e) - 1;
+        const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1], N, k);
+        v += e > 0 ? X : -X;
+    }
+    a.rad[(size_t)ij * P + gc] = v;
 }
 
 // Rate matrix entry (i, j), i != j: radiative and collisional rates from j
@@ -818,10 +866,10 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                                              int64_t gc, double T, double ne) {
     const DevAtom &A = a.A;
     double v = 0.0;
+    if (!ZERO_RAD) v = a.rad[(size_t)(i * L + j) * ((size_t)a.S * a.ND) + gc];
     const int tu = A.up_t[i * L + j];
     if (tu >= 0) {  // j = l, i = u: excitation / ionisation
         const DevTransition &tr = A.tr[tu];
-        if (!ZERO_RAD) v += key_sum<R>(part, A.p_key, A.p_off[tu], A.p_off[tu + 1], N, k);
         v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]);
     }
     const int td = A.dn_t[i * L + j];
@@ -842,18 +890,8 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                 }
                 v += q;
             }
-        } else {
-            v += key_sum<R>(part, A.q_key, A.q_off[td], A.q_off[td + 1], N, k);
         }
         v += coll_down(a, tr, T, ne);
-    }
-    if (!ZERO_RAD) {
-        for (int x = A.xe_off[i * L + j]; x < A.xe_off[i * L + j + 1]; x++) {
-            const int e = A.xe_val[x];
-            const int xp = (e > 0 ? e : -e) - 1;
-            const double X = key_sum<R>(part, A.x_key, A.x_off[xp], A.x_off[xp + 1], N, k);
-            v += e > 0 ? X : -X;
-        }
     }
     return v;
 }
@@ -1599,7 +1637,7 @@ SweepShape pick_shape(rh15d_atom *atom, const rh15d_options *o) {
 }
 
 struct Layout {
-    size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_rec, off_popsf, off_nse, off_dk,
+    size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_rec, off_popsf, off_rad, off_nse, off_dk,
         off_flag, off_ring, off_slots, off_ctr, off_lists, total;
 };
 
@@ -1620,6 +1658,7 @@ Layout make_layout(const DevAtom &D, int64_t n_columns, int S, int ND, bool fp32
     l.off_part = take(P * D.n_keys * R);
     l.off_rec = take(P * rec_width(D.n_cont) * R);
     l.off_popsf = take(fp32 ? P * D.L * 4 : 8);
+    l.off_rad = take(P * D.L * D.L * 8);
     l.off_nse = take(P * D.L * 8);
     l.off_dk = take(P * 8);
     l.off_flag = take(P * 4);
@@ -1688,6 +1727,8 @@ void launch_se_l(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
         return;
     }
     const unsigned blocks = grid_for((int64_t)a.S * a.ND, 256, 1u << 30);
+    if (fp32) hipLaunchKernelGGL(k_rad_rates<float>, dim3(blocks, L * L), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_rad_rates<double>, dim3(blocks, L * L), dim3(256), 0, st, a);
     if (fp32) hipLaunchKernelGGL((k_se<float, L>), dim3(blocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((k_se<double, L>), dim3(blocks), dim3(256), 0, st, a);
 }
@@ -1979,6 +2020,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.part = ws + lay.off_part;
     a.rec = ws + lay.off_rec;
     a.popsf = fp32 ? reinterpret_cast<float *>(ws + lay.off_popsf) : nullptr;
+    a.rad = reinterpret_cast<double *>(ws + lay.off_rad);
     a.nse = reinterpret_cast<double *>(ws + lay.off_nse);
     a.dk = reinterpret_cast<double *>(ws + lay.off_dk);
     a.flag = reinterpret_cast<int *>(ws + lay.off_flag);
