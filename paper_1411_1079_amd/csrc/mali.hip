@@ -331,17 +331,20 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const double vzc = vz / kC;
     const int r0 = A.prof_off[t], nr = A.prof_off[t + 1] - r0;
     const double *pnu = A.prof_nu + r0, *pmus = A.prof_mus + r0, *pw = A.prof_w + r0;
+    const int *pdst = A.prof_dst + r0;
     R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
-    // quadrature rays (direction, wavelength, angle), then the vertical
-    // emergent ray of each wavelength (mu = 1, upward, weight 0); the row is
-    // written unnormalised, then scaled once the wavefront has the sum
+    // the line's rays in order of distance from the line centre, each stored
+    // at its place in the row (quadrature rays by direction, wavelength and
+    // angle, then the vertical emergent ray of each wavelength: mu = 1,
+    // upward, weight 0); the row is written unnormalised, then scaled once
+    // the wavefront has the sum
     double acc = 0.0;
     for (int r = lane; r < nr; r += kWave) {
         const double v = (pnu[r] - tr.nu0 * (1.0 + pmus[r] * vzc)) * rdnd;
         const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
         const R ph = H * static_cast<R>(pre);
         acc += pw[r] * static_cast<double>(ph);
-        phi[r] = ph;
+        phi[pdst[r]] = ph;
     }
     const double tot = wave_sum(acc);
     const R rtot = static_cast<R>(1.0 / tot);
@@ -1538,15 +1541,19 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
             jja[i] = static_cast<int>(std::lower_bound(act.begin(), act.end(), j) - act.begin());
         }
     UP(jo, &D.jact_off); UP(jt, &D.jact_t); UP(jja, &D.jact_ja);
-    // per line ray (the layout of the profile table): frequency, signed
-    // direction cosine (+ up) and quadrature weight W = w_nu w_mu / 2 (0 for
-    // the vertical emergent rays, which are not in the normalisation)
+    // per line ray: frequency, signed direction cosine (+ up), quadrature
+    // weight W = w_nu w_mu / 2 (0 for the vertical emergent rays, which are
+    // not in the normalisation) and the ray's place in the profile table.
+    // The preparation visits the rays in order of distance from the line
+    // centre, so the lanes of a wavefront mostly fall in the same region of
+    // the Voigt approximation.
     {
         std::vector<double> pnu, pmus, pw;
-        std::vector<int> poff(1, 0);
+        std::vector<int> poff(1, 0), pdst;
         for (int t = 0; t < D.n_lines; t++) {
             const auto &h = atom->tr[t];
             const int na = static_cast<int>(h.act.size()), nq = 2 * na * n_mu;
+            const size_t first = pnu.size();
             for (int r = 0; r < nq + na; r++) {
                 int ja, m = 0;
                 double mus, w = 0.0;
@@ -1563,11 +1570,23 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
                 pnu.push_back(atom->nu[h.act[ja]]);
                 pmus.push_back(mus);
                 pw.push_back(w);
+                pdst.push_back(r);
             }
+            std::vector<int> ord(nq + na);
+            for (int r = 0; r < nq + na; r++) ord[r] = r;
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+                return std::fabs(pnu[first + x] - h.nu0) < std::fabs(pnu[first + y] - h.nu0);
+            });
+            auto permute = [&](auto &v) {
+                std::vector<typename std::decay_t<decltype(v)>::value_type> w(v.begin() + first, v.end());
+                for (int r = 0; r < nq + na; r++) v[first + r] = w[ord[r]];
+            };
+            permute(pnu); permute(pmus); permute(pw); permute(pdst);
             poff.push_back(static_cast<int>(pnu.size()));
         }
-        if (pnu.empty()) { pnu.push_back(0.0); pmus.push_back(0.0); pw.push_back(0.0); }
+        if (pnu.empty()) { pnu.push_back(0.0); pmus.push_back(0.0); pw.push_back(0.0); pdst.push_back(0); }
         UP(pnu, &D.prof_nu); UP(pmus, &D.prof_mus); UP(pw, &D.prof_w); UP(poff, &D.prof_off);
+        UP(pdst, &D.prof_dst);
     }
     UP(H.groups, &D.groups);
     UP(H.lane_j, &D.lanes.j); UP(H.lane_m0, &D.lanes.m0);

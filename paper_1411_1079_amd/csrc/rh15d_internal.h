@@ -105,9 +105,10 @@ struct DevAtom {
     double *mu, *wmu;           // Gauss-Legendre on (0,1)
     int *jact_off, *jact_t;     // per wavelength: active transitions (CSR)
     int *jact_ja;               // ... and the wavelength's index in each one's active list
-    // per line ray, in the profile table's order (CSR over lines):
-    // frequency, signed direction cosine, quadrature weight
-    int *prof_off; double *prof_nu, *prof_mus, *prof_w;
+    // per line ray, in the order the preparation visits them (CSR over
+    // lines): place in the profile table's row, frequency, signed direction
+    // cosine, quadrature weight
+    int *prof_off, *prof_dst; double *prof_nu, *prof_mus, *prof_w;
     DevGroup *groups;
     DevLanes lanes;
     // rate keys per transition and per ordered transition pair (CSR)
