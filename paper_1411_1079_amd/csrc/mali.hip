@@ -338,17 +338,40 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     // angle, then the vertical emergent ray of each wavelength: mu = 1,
     // upward, weight 0); the row is written unnormalised, then scaled once
     // the wavefront has the sum
+    // four rays per lane and pass: their table entries load together
+    constexpr int U = 4;
     double acc = 0.0;
-    for (int r = lane; r < nr; r += kWave) {
-        const double v = (pnu[r] - tr.nu0 * (1.0 + pmus[r] * vzc)) * rdnd;
-        const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
-        const R ph = H * static_cast<R>(pre);
-        acc += pw[r] * static_cast<double>(ph);
-        phi[pdst[r]] = ph;
+    for (int r0 = lane; r0 < nr; r0 += U * kWave) {
+        double nu[U], mus[U], w[U];
+        int dst[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int r = r0 + u * kWave;
+            if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[u] = pdst[r]; }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (r0 + u * kWave < nr) {
+                const double v = (nu[u] - tr.nu0 * (1.0 + mus[u] * vzc)) * rdnd;
+                const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
+                const R ph = H * static_cast<R>(pre);
+                acc += w[u] * static_cast<double>(ph);
+                phi[dst[u]] = ph;
+            }
+        }
     }
     const double tot = wave_sum(acc);
     const R rtot = static_cast<R>(1.0 / tot);
-    for (int r = lane; r < nr; r += kWave) phi[r] = sizeof(R) == 8 ? static_cast<R>(phi[r] / tot) : phi[r] * rtot;
+    for (int r0 = lane; r0 < nr; r0 += U * kWave) {
+        R x[U];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (r0 + u * kWave < nr) x[u] = phi[r0 + u * kWave];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (r0 + u * kWave < nr)
+                phi[r0 + u * kWave] = sizeof(R) == 8 ? static_cast<R>(x[u] / tot) : x[u] * rtot;
+    }
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
 }
 
