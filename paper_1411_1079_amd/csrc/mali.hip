@@ -333,44 +333,77 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const double *pnu = A.prof_nu + r0, *pmus = A.prof_mus + r0, *pw = A.prof_w + r0;
     const int *pdst = A.prof_dst + r0;
     R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
-    // the line's rays in order of distance from the line centre, each stored
+    // The line's rays in order of distance from the line centre, each stored
     // at its place in the row (quadrature rays by direction, wavelength and
     // angle, then the vertical emergent ray of each wavelength: mu = 1,
-    // upward, weight 0); the row is written unnormalised, then scaled once
-    // the wavefront has the sum
-    // four rays per lane and pass: their table entries load together
-    constexpr int U = 4;
-    double acc = 0.0;
-    for (int r0 = lane; r0 < nr; r0 += U * kWave) {
-        double nu[U], mus[U], w[U];
-        int dst[U];
+    // upward, weight 0), scaled by the row's normalisation sum.  Four rays
+    // per lane at a time, their table entries loaded together; in FP32 a row
+    // of up to kHeld rays per lane stays in registers until the wavefront
+    // has the sum, otherwise it is written unnormalised and scaled in a
+    // second pass.
+    constexpr int U = 4, kHeld = sizeof(R) == 4 ? 8 : 0;
+    auto profile = [&](int r, double nu, double mus) -> R {
+        const double v = (nu - tr.nu0 * (1.0 + mus * vzc)) * rdnd;
+        const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
+        return H * static_cast<R>(pre);
+    };
+    double acc = 0.0, tot;
+    if (kHeld > 0 && nr <= kHeld * kWave) {
+        R val[kHeld > 0 ? kHeld : 1];
+        int dst[kHeld > 0 ? kHeld : 1];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int r = r0 + u * kWave;
-            if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[u] = pdst[r]; }
-        }
+        for (int h0 = 0; h0 < kHeld; h0 += U) {
+            double nu[U], mus[U], w[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (r0 + u * kWave < nr) {
-                const double v = (nu[u] - tr.nu0 * (1.0 + mus[u] * vzc)) * rdnd;
-                const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
-                const R ph = H * static_cast<R>(pre);
-                acc += w[u] * static_cast<double>(ph);
-                phi[dst[u]] = ph;
+            for (int u = 0; u < U; u++) {
+                const int r = lane + (h0 + u) * kWave;
+                if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[h0 + u] = pdst[r]; }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int r = lane + (h0 + u) * kWave;
+                if (r < nr) {
+                    val[h0 + u] = profile(r, nu[u], mus[u]);
+                    acc += w[u] * static_cast<double>(val[h0 + u]);
+                }
             }
         }
-    }
-    const double tot = wave_sum(acc);
-    const R rtot = static_cast<R>(1.0 / tot);
-    for (int r0 = lane; r0 < nr; r0 += U * kWave) {
-        R x[U];
+        tot = wave_sum(acc);
+        const R rtot = static_cast<R>(1.0 / tot);
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (r0 + u * kWave < nr) x[u] = phi[r0 + u * kWave];
+        for (int h = 0; h < kHeld; h++)
+            if (lane + h * kWave < nr) phi[dst[h]] = sizeof(R) == 8 ? static_cast<R>(val[h] / tot) : val[h] * rtot;
+    } else {
+        for (int r0 = lane; r0 < nr; r0 += U * kWave) {
+            double nu[U], mus[U], w[U];
+            int dst[U];
 #pragma unroll
-        for (int u = 0; u < U; u++)
-            if (r0 + u * kWave < nr)
-                phi[r0 + u * kWave] = sizeof(R) == 8 ? static_cast<R>(x[u] / tot) : x[u] * rtot;
+            for (int u = 0; u < U; u++) {
+                const int r = r0 + u * kWave;
+                if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[u] = pdst[r]; }
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int r = r0 + u * kWave;
+                if (r < nr) {
+                    const R ph = profile(r, nu[u], mus[u]);
+                    acc += w[u] * static_cast<double>(ph);
+                    phi[dst[u]] = ph;
+                }
+            }
+        }
+        tot = wave_sum(acc);
+        const R rtot = static_cast<R>(1.0 / tot);
+        for (int r0 = lane; r0 < nr; r0 += U * kWave) {
+            R x[U];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (r0 + u * kWave < nr) x[u] = phi[r0 + u * kWave];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (r0 + u * kWave < nr)
+                    phi[r0 + u * kWave] = sizeof(R) == 8 ? static_cast<R>(x[u] / tot) : x[u] * rtot;
+        }
     }
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
 }
