@@ -1202,15 +1202,17 @@ struct EmIn {
     AR nl[kMaxSlots], nu[kMaxSlots];
 };
 
+// Populations: FP64 by global depth index g (FP64 path), or the FP32 copy by
+// slot-local index gc (FP32 path; the same values rounded to FP32).
 template <typename TB, typename AR>
 __device__ __forceinline__ void em_load(const TB *__restrict__ rec, const TB *__restrict__ phi,
-                                        const double *__restrict__ pops, int rec_w, int ray_cols, int L,
+                                        const TB *__restrict__ pops, int rec_w, int ray_cols, int L,
                                         const EmTrans<AR> &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn<AR> &p) {
     const TB *r = rec + gc * rec_w;
     p.invT = static_cast<AR>(r[1]);
     p.kbg = static_cast<AR>(r[2]);
     p.dz = static_cast<AR>(rec[gc_dz * rec_w]);
-    const double *n = pops + g * L;
+    const TB *n = pops + (sizeof(TB) == 8 ? g : gc) * L;
     const TB *pr = phi + gc * ray_cols;
 #pragma unroll
     for (int q = 0; q < kMaxSlots; q++) {
@@ -1229,7 +1231,8 @@ __device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &
     const AR x = hnu_k * in.invT;
     const AR ex = d_exp(-x), omx = one_m_exp(x, ex);
     const AR exs = sizeof(AR) == 8 ? ex : d_exp(x0 - x);
-    B = two_hnu3 * exs / omx;
+    if constexpr (sizeof(AR) == 8) B = two_hnu3 * exs / omx;
+    else B = two_hnu3 * exs * rcp(omx);
     AR c = in.kbg * lamfac;
     AR e = c * B;
 #pragma unroll
@@ -1250,12 +1253,13 @@ __device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &
         }
     }
     chi = c;
-    S = e / c;
+    if constexpr (sizeof(AR) == 8) S = e / c;
+    else S = e * rcp(c);
 }
 
 template <typename TB, typename AR>
 __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restrict__ rec, const TB *__restrict__ phi,
-                                                  const double *__restrict__ pops) {
+                                                  const TB *__restrict__ pops) {
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
     const int rec_w = a.rec_w, ray_cols = A.ray_cols, L = A.L;
@@ -1316,7 +1320,10 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
         em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt);
         for (int k = N - 2; k >= 0; k--) {
             const EmIn<AR> cur = nxt;
-            if (k > 0) em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + k - 1, gc0 + k - 1, gc0 + k, nxt);
+            // issued on every step (the last one reloads the top point), so
+            // the wait for this point's values leaves it in flight
+            const int kn = k > 0 ? k - 1 : 0;
+            em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + kn, gc0 + kn, gc0 + kn + 1, nxt);
             em_point<AR>(cur, et, hnu_k, two_hnu3, lamfac, x0, scale, chi, S, B);
             const AR x = AR(0.5) * (chi_p + chi) * cur.dz;
             AR e, wa, wb;
@@ -1935,7 +1942,7 @@ struct Launcher {
             const unsigned eb = grid_for((int64_t)a.S * a.A.NL, 256, 8192);
             if (fp32)
                 hipLaunchKernelGGL((k_emergent<float, float>), dim3(eb), dim3(256), 0, st, a,
-                                   reinterpret_cast<const float *>(a.rec), reinterpret_cast<const float *>(a.phi), a.pops);
+                                   reinterpret_cast<const float *>(a.rec), reinterpret_cast<const float *>(a.phi), a.popsf);
             else
                 hipLaunchKernelGGL((k_emergent<double, double>), dim3(eb), dim3(256), 0, st, a,
                                    reinterpret_cast<const double *>(a.rec), reinterpret_cast<const double *>(a.phi),
