@@ -864,18 +864,18 @@ __device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransitio
 
 // Sum of the rate sums `keys[b..e)` at depth k of a column whose key-major
 // block ([key][depth], N depths) starts at `part`.
-// The loads of four keys are issued before their sum, which adds them in
+// The loads of eight keys are issued before their sum, which adds them in
 // key order.
 template <typename R>
 __device__ __forceinline__ double key_sum(const R *part, const int *keys, int b, int e, int N, int k) {
     double v = 0.0;
     int i = b;
-    for (; i + 4 <= e; i += 4) {
-        R x[4];
+    for (; i + 8 <= e; i += 8) {
+        R x[8];
 #pragma unroll
-        for (int u = 0; u < 4; u++) x[u] = part[(size_t)keys[i + u] * N + k];
+        for (int u = 0; u < 8; u++) x[u] = part[(size_t)keys[i + u] * N + k];
 #pragma unroll
-        for (int u = 0; u < 4; u++) v += static_cast<double>(x[u]);
+        for (int u = 0; u < 8; u++) v += static_cast<double>(x[u]);
     }
     for (; i < e; i++) v += static_cast<double>(part[(size_t)keys[i] * N + k]);
     return v;
