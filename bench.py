@@ -167,32 +167,34 @@ def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None):
     return out
 
 
-def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols):
+def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols, seed=1):
     """The FP64 oracle as it stands, one column per task on a thread pool of
-    the host cores, on the first columns of the first timed batch."""
+    the host cores, on a seeded random sample of the columns of the timed
+    batches (so the sample has the cube's mix of fast and slowly converging
+    columns), until the time budget or max_cols is reached."""
     import concurrent.futures
 
     from oracle import oracle as O
 
     threads = max(1, min(16, os.cpu_count() or 1))
     a = O.Atom(atom_path)
-    c0 = batches[gpu_first][0]
+    c0, c1 = batches[gpu_first][0], batches[-1][1]
+    order = [int(c) for c in c0 + np.random.default_rng(seed).permutation(c1 - c0)[:max_cols]]
     results = []
     t0 = time.perf_counter()
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        c = c0
-        while len(results) < max_cols:
-            chunk = list(range(c, c + threads))
-            futs = [ex.submit(O.solve_column, a, cols.column(i), n_mu=5, tol=1e-4, max_iter=200) for i in chunk]
-            results += [(i, f.result()) for i, f in zip(chunk, futs)]
-            c += threads
+        for i in range(0, len(order), threads):
+            chunk = order[i:i + threads]
+            futs = [ex.submit(O.solve_column, a, cols.column(c), n_mu=5, tol=1e-4, max_iter=200) for c in chunk]
+            results += [(c, f.result()) for c, f in zip(chunk, futs)]
             if time.perf_counter() - t0 > budget_s:
                 break
     dt = time.perf_counter() - t0
     conv = sum(1 for _, r in results if r["status"] == 0)
+    iters = np.array([r["n_iter"] for _, r in results])
     return dict(value=conv / dt, unit="columns/s", cores=threads, kind="oracle",
-                sample=f"{len(results)} columns of the cube (columns {c0}..{c0 + len(results) - 1}), "
-                       f"{dt:.1f} s wall on {threads} threads"), results
+                sample=f"{len(results)} columns drawn at random (seed {seed}) from columns {c0}..{c1 - 1} of the "
+                       f"cube, mean {iters.mean():.2f} iterations, {dt:.1f} s wall on {threads} threads"), results
 
 
 def converged_oracle(atom_path, cols, n, threads, seed=0):
@@ -287,13 +289,7 @@ def main():
     fields = {k: torch.as_tensor(getattr(cols, k)).to(dev) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
     batches = make_batches(rh, cols, fields, args.batch)
     atom = rh.Atom(atom_path)
-    ws_bytes = 0
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    for f in forms:
-        o = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, **FORMS[f])
-        ws_bytes = max(ws_bytes, max(rh.workspace_size(atom, dc, o) for _, _, dc in batches))
-    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
-    log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
 
     tune = {}
     if not args.no_autotune:
@@ -309,6 +305,14 @@ def main():
             tune[key]["sample_columns"] = sample.n_columns
             log(f"autotune {key}: {tune[key]}")
         del dcs
+    # sized after the autotuner: the tuned formal-solution shape sets the
+    # number of rate keys and so the workspace
+    ws_bytes = 0
+    for f in forms:
+        o = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, **FORMS[f])
+        ws_bytes = max(ws_bytes, max(rh.workspace_size(atom, dc, o) for _, _, dc in batches))
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
     net = train_info = None
     if "fp32w" in forms:
         log(f"train the start-solution network on cube seed {args.train_seed}")
