@@ -182,13 +182,26 @@ def cpu_baseline(atom_path, cols, batches, gpu_first, budget_s, max_cols, seed=1
     order = [int(c) for c in c0 + np.random.default_rng(seed).permutation(c1 - c0)[:max_cols]]
     results = []
     t0 = time.perf_counter()
+    # a pool: one column per task, a new task as soon as a thread is free,
+    # none started after the budget; the columns in flight then finish
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        for i in range(0, len(order), threads):
-            chunk = order[i:i + threads]
-            futs = [ex.submit(O.solve_column, a, cols.column(c), n_mu=5, tol=1e-4, max_iter=200) for c in chunk]
-            results += [(c, f.result()) for c, f in zip(chunk, futs)]
-            if time.perf_counter() - t0 > budget_s:
-                break
+        pending = {}
+        nxt = 0
+
+        def submit():
+            nonlocal nxt
+            c = order[nxt]
+            nxt += 1
+            pending[ex.submit(O.solve_column, a, cols.column(c), n_mu=5, tol=1e-4, max_iter=200)] = c
+
+        while nxt < len(order) and len(pending) < threads:
+            submit()
+        while pending:
+            done, _ = concurrent.futures.wait(list(pending), return_when=concurrent.futures.FIRST_COMPLETED)
+            for f in done:
+                results.append((pending.pop(f), f.result()))
+                if nxt < len(order) and time.perf_counter() - t0 < budget_s:
+                    submit()
     dt = time.perf_counter() - t0
     conv = sum(1 for _, r in results if r["status"] == 0)
     iters = np.array([r["n_iter"] for _, r in results])
