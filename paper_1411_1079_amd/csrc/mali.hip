@@ -12,12 +12,17 @@
 //    direction) of a column; the 64 rays of a wavefront share one set of
 //    active transitions, walk the depth recurrence in lock-step, read the
 //    per-depth column data as wave-uniform (scalar) loads and the
-//    normalised line profiles as coalesced rows, and reduce their rate
-//    contributions across the wavefront at every depth, in a fixed order,
-//    into per-depth rate keys (no atomics: results are bitwise
-//    reproducible);
-//  * rate-equation solve (k_se): one lane per depth point, an L x L FP64
-//    system in registers, Gaussian elimination with partial pivoting;
+//    normalised line profiles as coalesced rows, and sum their rate
+//    contributions over the wavefront through LDS in blocks of depth
+//    points, in a fixed order, into per-depth rate keys (no atomics:
+//    results are bitwise reproducible); one kernel per class of groups
+//    (transition slots, continua among them), the classes of a stage
+//    running concurrently on side streams;
+//  * rate-equation solve: the radiative part of every rate-matrix entry is
+//    gathered from the rate keys (k_rad_rates, one lane per depth point and
+//    entry), then one lane per depth point adds the collisional rates and
+//    solves the L x L FP64 system in registers by Gaussian elimination with
+//    partial pivoting (k_se);
 //  * convergence test and Ng (k_converge): one workgroup per column;
 //  * columns live in "slots" of a fixed depth stride; one iteration is a
 //    fixed sequence of kernels (sweep, rate solve, convergence + Ng, output
