@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # taken on: the JSON line reports null once that source has changed.
 SWEEP_TRAFFIC = {
     "source": "paper_1411_1079_amd/csrc/mali.hip",
-    "sha256": "a9cff7afceea26436a7d818e2e6698d88c56e509d829a3fd6962aab821cf969c",
+    "sha256": "fcbf52e20e1a509befec6c16f4db636ca1edd428fe0d2e648cd74ff839b2f39c",
     "read_bytes": 27.67e9,
     "written_bytes": 5.15e9,
     "summary": "profiles/k_sweep_fp32_cube256_counters.md",

@@ -923,11 +923,11 @@ __global__ __launch_bounds__(256) void k_rad_rates(RunArgs a) {
     a.rad[(size_t)ij * P + gc] = v;
 }
 
-// Rate matrix entry (i, j), i != j: radiative and collisional rates from j
-// into i, plus the cross terms of overlapping transitions.
-template <typename R, bool ZERO_RAD>
-__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, const R *part, int N, int k,
-                                             int64_t gc, double T, double ne) {
+// Rate matrix entry (i, j), i != j: the radiative rates from j into i with
+// the cross terms of overlapping transitions (gathered by k_rad_rates; with
+// zero radiation the spontaneous rates alone), plus the collisional rates.
+template <bool ZERO_RAD>
+__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, int64_t gc, double T, double ne) {
     const DevAtom &A = a.A;
     double v = 0.0;
     if (!ZERO_RAD) v = a.rad[(size_t)(i * L + j) * ((size_t)a.S * a.ND) + gc];
@@ -964,10 +964,8 @@ template <typename R, int L, bool ZERO_RAD>
 __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const ColGeom cg = geom(a, slot);
     if (k >= cg.N) return;
-    const int N = cg.N;
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
-    const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
     const double T = a.T[g], ne = a.ne[g];
     double M[L][L];
     double nold[L], b[L];
@@ -979,7 +977,7 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     for (int i = 0; i < L; i++)
 #pragma unroll
         for (int j = 0; j < L; j++)
-            M[i][j] = i == j ? 0.0 : rate_entry<R, ZERO_RAD>(a, i, j, L, part, N, k, gc, T, ne);
+            M[i][j] = i == j ? 0.0 : rate_entry<ZERO_RAD>(a, i, j, L, gc, T, ne);
 #pragma unroll
     for (int j = 0; j < L; j++) {
         double c = 0.0;
