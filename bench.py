@@ -113,11 +113,13 @@ def train_network(rh, torch, atom, args):
     return net, info
 
 
-def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None):
+def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None, shrink=None):
     from paper_1411_1079_amd import warmstart
     opts = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, profile=1, **FORMS[form])
     if form == "fp32w":
-        runs = [warmstart.WarmStartSolver(atom, dc, net, opts, workspace=ws) for _, _, dc in batches]
+        runs = [warmstart.WarmStartSolver(atom, dc, net, opts, workspace=ws,
+                                          shrink=warmstart.SHRINK if shrink is None else shrink)
+                for _, _, dc in batches]
         solvers = [r.solver for r in runs]
     else:
         runs = solvers = [rh.Solver(atom, dc, opts, want_spectrum=True, workspace=ws) for _, _, dc in batches]
@@ -262,7 +264,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--forms", default="fp64,fp32,fp32w")
     ap.add_argument("--train-seed", type=int, default=7)
-    ap.add_argument("--train-steps", type=int, default=12000)
+    ap.add_argument("--train-steps", type=int, default=48000)
+    ap.add_argument("--shrink", type=float, default=0.002,
+                    help="shrinkage of the predicted |ln b| toward LTE, about the held-out error of the network "
+                         "trained for --train-steps")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-max-columns", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -334,7 +339,7 @@ def main():
     res = {}
     for f in forms:
         log(f"form {f}: warmup {args.warmup}, steps {args.steps}")
-        r = run_form(rh, torch, atom, batches, f, args.steps, args.warmup, ws, net=net)
+        r = run_form(rh, torch, atom, batches, f, args.steps, args.warmup, ws, net=net, shrink=args.shrink)
         st = r["stats"]
         sweep_s = st["sweep_ms"] / 1e3
         res[f] = r
