@@ -161,7 +161,10 @@ typedef struct {
 int rh15d_default_options(rh15d_options *opt);
 
 /* Device workspace needed by rh15d_solve_columns for these columns and
- * options, in bytes (HOST *bytes). */
+ * options, in bytes (HOST *bytes).  The size depends on the sweep shape
+ * (its number of rate sums): with sweep_mc = sweep_pack = 0 it follows the
+ * shape rh15d_autotune has chosen for this device, so query it after
+ * tuning. */
 int rh15d_workspace_size(const rh15d_atom *atom, const rh15d_columns *cols,
                          const rh15d_options *opt, size_t *bytes);
 
