@@ -21,8 +21,11 @@
  *   5. maximum relative population change (Sec. 2.3, the convergence
  *      measure of Fig. 1) and Ng extrapolation (Sec. 2.3, Ng 1974 / Auer).
  * Start solutions: LTE and zero radiation (Sec. 2.3, "Different starting
- * solutions").  Collisional-radiative switching (Sec. 2.3) is available
- * as a constant collision multiplier.  Output: emergent vertical intensity
+ * solutions").  Collisional-radiative switching (Sec. 2.3; Hummer &
+ * Voels 1988): a constant collision multiplier, and a factor on the
+ * collision rates that starts at f0 and falls tenfold per iteration to 1
+ * (see orc_crs_factor; this schedule is a reading, the paper gives none).
+ * Output: emergent vertical intensity
  * (Sec. 2.2: only vertical emergent spectra) and per-transition Psi*.
  *
  * Everything is SI.  Depth index k = 0 is the top (largest z).
@@ -92,6 +95,7 @@ typedef struct {
     int ng_order, ng_delay, ng_period;
     int start;           /* 0 LTE, 1 zero radiation, 2 provided */
     double coll_scale;   /* collision multiplier (1 = physical) */
+    double crs_f0;       /* collisional-radiative switching: initial factor (<= 1: off) */
 } orc_opts;
 
 /* ------------------------------------------------------------------ */
@@ -677,7 +681,19 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
 }
 
 /* Statistical equilibrium at every depth; returns 0 or -1 on a singular system. */
-static int solve_se(const colstate *cs, const rates *R, const double *nold, double *nnew) {
+/* Collisional-radiative switching (Sec. 2.3; Hummer & Voels 1988): the
+ * collision rates of iteration it (1, 2, ...) are multiplied by
+ * f0 / 10^(it-1) while that exceeds 1, by 1 afterwards.  The factor is
+ * formed by repeated division by 10 (the same IEEE operations in any
+ * implementation). */
+double orc_crs_factor(double f0, int it) {
+    double f = f0;
+    for (int i = 1; i < it && f > 1.0; i++) f /= 10.0;
+    return f > 1.0 ? f : 1.0;
+}
+
+/* SE at every depth point with the collision rates times cf. */
+static int solve_se(const colstate *cs, const rates *R, const double *nold, double *nnew, double cf) {
     const orc_atom *a = cs->a;
     int N = cs->N, L = a->L, T = a->T;
     double *G = malloc(sizeof(double) * L * L), *b = malloc(sizeof(double) * L);
@@ -699,7 +715,7 @@ static int solve_se(const colstate *cs, const rates *R, const double *nold, doub
         }
         for (int i = 0; i < L; i++) for (int j = 0; j < L; j++) {
             if (i == j) continue;
-            double c = cs->C[(k * L + i) * L + j];
+            double c = cs->C[(k * L + i) * L + j] * cf;
             G[j * L + i] += c; G[i * L + i] -= c;
         }
         int istar = 0;
@@ -809,7 +825,7 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
     memcpy(n, cs.nstar, sizeof(double) * NV);
     if (o->start == 1) {
         sweep(&cs, n, 1, &R, NULL);
-        solve_se(&cs, &R, cs.nstar, n);
+        solve_se(&cs, &R, cs.nstar, n, 1.0);
     } else if (o->start == 2 && init_pops) {
         memcpy(n, init_pops, sizeof(double) * NV);
     }
@@ -817,7 +833,10 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
     int st = 1, it;
     for (it = 1; it <= o->max_iter; it++) {
         sweep(&cs, n, 0, &R, NULL);
-        int bad = solve_se(&cs, &R, n, nse);
+        /* while collisions are switched (cf > 1) the iterate solves another
+         * problem: it may not end the iteration or enter Ng's history */
+        const double cf = orc_crs_factor(o->crs_f0, it);
+        int bad = solve_se(&cs, &R, n, nse, cf);
         double dmax = 0.0;
         int finite = 1;
         for (int i = 0; i < NV; i++) {
@@ -829,8 +848,8 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
         if (bad) { st = 3; break; }
         if (!finite) { st = 2; break; }
         memcpy(n, nse, sizeof(double) * NV);
-        if (dmax < o->tol) { st = 0; break; }
-        if (M > 0 && it >= o->ng_delay) {
+        if (dmax < o->tol && cf == 1.0) { st = 0; break; }
+        if (M > 0 && it >= o->ng_delay && cf == 1.0) {
             /* push newest iterate */
             double *last = ring[ring_n - 1];
             for (int i = ring_n - 1; i > 0; i--) ring[i] = ring[i - 1];

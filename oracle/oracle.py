@@ -56,6 +56,8 @@ def lib():
         L.orc_formal_ray.argtypes = [C.c_int, dp, dp, C.c_double, dp, dp]
         L.orc_lte_populations.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp]
         L.orc_solve_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 7 + [C.c_void_p, dp, dp, ip, ip, dp, dp]
+        L.orc_crs_factor.argtypes = [C.c_double, C.c_int]
+        L.orc_crs_factor.restype = C.c_double
         L.orc_ng_step.argtypes = [C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_double)), dp]
         L.orc_column_profile_norm.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp]
         _lib = L
@@ -68,7 +70,8 @@ def _p(a):
 
 class _Opts(C.Structure):
     _fields_ = [("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("ng_order", C.c_int),
-                ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int), ("coll_scale", C.c_double)]
+                ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int), ("coll_scale", C.c_double),
+                ("crs_f0", C.c_double)]
 
 
 class Atom:
@@ -152,13 +155,18 @@ def profile_norm(atom: Atom, col: dict, n_mu: int):
     return nstar, norm[: atom.n_lines]
 
 
+def crs_factor(f0: float, it: int) -> float:
+    """Collision factor of iteration it under collisional-radiative switching."""
+    return lib().orc_crs_factor(f0, it)
+
+
 def solve_column(atom: Atom, col: dict, n_mu: int = 5, tol: float = 1e-4, max_iter: int = 200,
                  ng_order: int = 2, ng_delay: int = 5, ng_period: int = 4, start: int = START_LTE,
                  coll_scale: float = 1.0, init_pops=None, want_spectrum: bool = True,
-                 want_psi: bool = False) -> dict:
+                 want_psi: bool = False, crs_f0: float = 1.0) -> dict:
     N = len(col["z"])
     cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
-    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale)
+    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale, crs_f0)
     pops = np.empty((N, atom.n_levels))
     hist = np.empty(max(max_iter, 1))
     spec = np.empty(atom.n_lambda) if want_spectrum else None
