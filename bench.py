@@ -113,9 +113,9 @@ def train_network(rh, torch, atom, args):
     return net, info
 
 
-def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None, shrink=None):
+def run_form(rh, torch, atom, batches, form, steps, warmup, ws, net=None, shrink=None, crs_f0=1.0):
     from paper_1411_1079_amd import warmstart
-    opts = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, profile=1, **FORMS[form])
+    opts = rh.default_options(n_mu=5, tol=1e-4, max_iter=200, profile=1, crs_f0=crs_f0, **FORMS[form])
     if form == "fp32w":
         runs = [warmstart.WarmStartSolver(atom, dc, net, opts, workspace=ws,
                                           shrink=warmstart.SHRINK if shrink is None else shrink)
@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,fp32w")
     ap.add_argument("--train-seed", type=int, default=7)
     ap.add_argument("--train-steps", type=int, default=48000)
+    ap.add_argument("--crs", type=float, default=1.0,
+                    help="collisional-radiative switching: initial collision factor (1 = off)")
     ap.add_argument("--shrink", type=float, default=0.002,
                     help="shrinkage of the predicted |ln b| toward LTE, about the held-out error of the network "
                          "trained for --train-steps")
@@ -339,7 +341,8 @@ def main():
     res = {}
     for f in forms:
         log(f"form {f}: warmup {args.warmup}, steps {args.steps}")
-        r = run_form(rh, torch, atom, batches, f, args.steps, args.warmup, ws, net=net, shrink=args.shrink)
+        r = run_form(rh, torch, atom, batches, f, args.steps, args.warmup, ws, net=net, shrink=args.shrink,
+                     crs_f0=args.crs)
         st = r["stats"]
         sweep_s = st["sweep_ms"] / 1e3
         res[f] = r
@@ -371,7 +374,8 @@ def main():
             "workload": (f"synthetic 3D cube {args.nx}x{args.nx} columns (seed {args.seed}), 200-400 depth "
                          f"points, H-like 6-level atom (10 lines, 5 continua, 510 wavelengths), 5 angles, "
                          f"tol 1e-4 from LTE, batches of {args.batch} columns"),
-            "form": FORM_NAMES[headline],
+            "form": FORM_NAMES[headline] + (f", collisional-radiative switching from {args.crs:g}"
+                                             if args.crs > 1.0 else ""),
             "global_batch": args.batch,
             "parallelism": "1 GPU",
         },

@@ -121,6 +121,13 @@ typedef struct {
     int sweep_pack;     /* wavelengths per wavefront: 1 = one set of active
                            transitions per wavefront, 2 = mixed sets;
                            0 = automatic */
+    double crs_f0;      /* collisional-radiative switching (Sec. 2.3,
+                           Hummer & Voels 1988): the collision rates of
+                           iteration it (1, 2, ...) are multiplied by
+                           crs_f0 / 10^(it-1) while that exceeds 1, formed
+                           by repeated division by 10; no column converges
+                           and no iterate enters Ng's history while the
+                           factor exceeds 1.  <= 1 (default 1): off */
 } rh15d_options;
 
 /* Measurements of the calling thread's last rh15d_solve_columns made with
@@ -156,7 +163,7 @@ typedef struct {
 } rh15d_outputs;
 
 /* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, 200 iterations,
- * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, chunked,
+ * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, crs_f0 1, chunked,
  * no profiling, automatic sweep shape. */
 int rh15d_default_options(rh15d_options *opt);
 

@@ -245,7 +245,7 @@ struct RunArgs {
     int *flag;                // [gc] 0 ok, 1 non-finite/non-positive, 2 singular
     double *ring;             // [4][S*ND][L] Ng history
     int max_iter, ng_order, ng_delay, ng_period, start;
-    double tol, coll_scale;
+    double tol, coll_scale, crs_f0;
 };
 
 // Per-depth data of the sweep (slot-local depth gc), in the sweep's precision:
@@ -856,6 +856,16 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
 // statistical equilibrium per depth point
 // ---------------------------------------------------------------------------
 // Collisional rate coefficient u -> l of transition t at this point.
+// Collisional-radiative switching (Sec. 2.3; Hummer & Voels 1988): factor
+// of the collision rates in iteration it (1, 2, ...), f0 / 10^(it-1) while
+// that exceeds 1, formed by repeated division (the same IEEE operations
+// wherever it is evaluated); 1 for f0 <= 1.
+__device__ __forceinline__ double crs_factor(double f0, int it) {
+    double f = f0;
+    for (int i = 1; i < it && f > 1.0; i++) f /= 10.0;
+    return f > 1.0 ? f : 1.0;
+}
+
 __device__ __forceinline__ double coll_down(const RunArgs &a, const DevTransition &tr, double T, double ne) {
     double Cul;
     if (tr.coll_kind == 0) {
@@ -927,14 +937,15 @@ __global__ __launch_bounds__(256) void k_rad_rates(RunArgs a) {
 // the cross terms of overlapping transitions (gathered by k_rad_rates; with
 // zero radiation the spontaneous rates alone), plus the collisional rates.
 template <bool ZERO_RAD>
-__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, int64_t gc, double T, double ne) {
+__device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, int64_t gc, double T, double ne,
+                                             double cf) {
     const DevAtom &A = a.A;
     double v = 0.0;
     if (!ZERO_RAD) v = a.rad[(size_t)(i * L + j) * ((size_t)a.S * a.ND) + gc];
     const int tu = A.up_t[i * L + j];
     if (tu >= 0) {  // j = l, i = u: excitation / ionisation
         const DevTransition &tr = A.tr[tu];
-        v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]);
+        v += coll_down(a, tr, T, ne) * exp(a.lnr[gc * L + tr.u] - a.lnr[gc * L + tr.l]) * cf;
     }
     const int td = A.dn_t[i * L + j];
     if (td >= 0) {  // j = u, i = l: de-excitation / recombination
@@ -955,7 +966,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                 v += q;
             }
         }
-        v += coll_down(a, tr, T, ne);
+        v += coll_down(a, tr, T, ne) * cf;
     }
     return v;
 }
@@ -967,6 +978,8 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
     const DevAtom &A = a.A;
     const double T = a.T[g], ne = a.ne[g];
+    // collision factor of this iteration (the start solutions use 1)
+    const double cf = ZERO_RAD ? 1.0 : crs_factor(a.crs_f0, a.slot_it[slot] + 1);
     double M[L][L];
     double nold[L], b[L];
 #pragma unroll
@@ -977,7 +990,7 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     for (int i = 0; i < L; i++)
 #pragma unroll
         for (int j = 0; j < L; j++)
-            M[i][j] = i == j ? 0.0 : rate_entry<ZERO_RAD>(a, i, j, L, gc, T, ne);
+            M[i][j] = i == j ? 0.0 : rate_entry<ZERO_RAD>(a, i, j, L, gc, T, ne, cf);
 #pragma unroll
     for (int j = 0; j < L; j++) {
         double c = 0.0;
@@ -1119,9 +1132,12 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
     if (a.history && threadIdx.x == 0) a.history[(size_t)c * a.max_iter + it - 1] = fl > 0.0 ? NAN : dm;
     if (status < 0) {
         for (int i = threadIdx.x; i < NV; i += kConvThreads) pops[i] = nse[i];
-        if (dm < a.tol) {
+        // while the collisions are switched the iterate solves another
+        // problem: it may not end the iteration or enter Ng's history
+        const bool switched = crs_factor(a.crs_f0, it) > 1.0;
+        if (dm < a.tol && !switched) {
             status = RH15D_CONVERGED;
-        } else if (a.ng_order == 2 && it >= a.ng_delay) {
+        } else if (a.ng_order == 2 && it >= a.ng_delay && !switched) {
             const size_t stride = (size_t)a.S * a.ND * L;
             const int head = (a.ng_head[slot] + 1) & 3;
             double *newest = a.ring + head * stride + gc0 * L;
@@ -1773,6 +1789,7 @@ int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_opti
     if (o->sweep_pack < 0 || o->sweep_pack > 2) { set_error("sweep_pack must be 0, 1 or 2"); return RH15D_EINVAL; }
     if (o->start == RH15D_START_PROVIDED && !cols->init_pops) { set_error("start=PROVIDED needs init_pops"); return RH15D_EINVAL; }
     if (!(o->tol >= 0.0)) { set_error("tol must be >= 0"); return RH15D_EINVAL; }
+    if (!(o->crs_f0 >= 0.0) || !std::isfinite(o->crs_f0)) { set_error("crs_f0 must be finite and >= 0"); return RH15D_EINVAL; }
     if (cols->depth_offset && cols->depth_offset[0] != 0) { set_error("depth_offset[0] must be 0"); return RH15D_EINVAL; }
     for (int64_t c = 0; c < cols->n_columns; c++) {
         const int64_t n = cols->depth_offset[c + 1] - cols->depth_offset[c];
@@ -2023,6 +2040,7 @@ int rh15d_default_options(rh15d_options *o) {
     o->ng_period = 4;
     o->start = RH15D_START_LTE;
     o->coll_scale = 1.0;
+    o->crs_f0 = 1.0;
     o->scheduler = RH15D_SCHED_CHUNKED;
     o->batch_columns = 0;
     o->profile = 0;
@@ -2111,7 +2129,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.flag = reinterpret_cast<int *>(ws + lay.off_flag);
     a.ring = reinterpret_cast<double *>(ws + lay.off_ring);
     a.max_iter = o->max_iter; a.ng_order = o->ng_order; a.ng_delay = o->ng_delay; a.ng_period = o->ng_period;
-    a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale;
+    a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale; a.crs_f0 = o->crs_f0;
 
     Launcher run{a, fp32, o->start == RH15D_START_ZERO_RADIATION, out->spectrum != nullptr, out->psi_star != nullptr,
                  st};

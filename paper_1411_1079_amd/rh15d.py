@@ -45,7 +45,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("ng_order", C.c_int), ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int),
                 ("coll_scale", C.c_double), ("scheduler", C.c_int), ("batch_columns", C.c_int),
-                ("profile", C.c_int), ("sweep_mc", C.c_int), ("sweep_pack", C.c_int)]
+                ("profile", C.c_int), ("sweep_mc", C.c_int), ("sweep_pack", C.c_int), ("crs_f0", C.c_double)]
 
 
 class Stats(C.Structure):
