@@ -281,8 +281,8 @@ def main():
                          "hardware byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the columns are independent and this build runs on a single "
-              "MI355X; run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the columns are independent, so several GPUs would each solve "
+              "their own share of them with no exchange; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         import torch
