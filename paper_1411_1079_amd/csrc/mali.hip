@@ -428,6 +428,8 @@ __global__ __launch_bounds__(256) void k_prep_profile(RunArgs a) {
 
 enum { MODE_RATES = 0, MODE_PSI = 1 };
 
+constexpr unsigned kXcds = 8;   // accelerator complex dies of the MI355X, one L2 each
+
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // One DPP stage of a sum that only lane 63 reads: the value of another lane
@@ -837,16 +839,24 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
                                                const R *__restrict__ phi, const R *__restrict__ popsb,
                                                R *__restrict__ part) {
     __shared__ __align__(16) R red_lds[4 * Red<R, NS, MODE>::SIZE];
-    const int grp = rfl(g_begin + blockIdx.x * 4 + (threadIdx.x >> 6));
+    // The hardware deals consecutive workgroups to the eight XCDs in turn.
+    // Renumber them so that each XCD gets a contiguous run of (slot, group
+    // block) pairs: the groups of one column then share one L2 for the
+    // column's records, populations and profile rows.
+    const unsigned nb = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const unsigned per = nb / kXcds, rem = nb % kXcds, x = lin % kXcds, r = lin / kXcds;
+    const unsigned logical = x < rem ? x * (per + 1) + r : rem * (per + 1) + (x - rem) * per + r;
+    const int bx = (int)(logical % gridDim.x), by = (int)(logical / gridDim.x);
+    const int grp = rfl(g_begin + bx * 4 + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (grp >= g_end) return;
     int slot;
     if (MODE == MODE_RATES) {
-        slot = blockIdx.y;
+        slot = by;
         if (a.slot_state[slot] != SLOT_ACTIVE) return;
     } else {
-        if ((int)blockIdx.y >= a.ctr[CTR_RETIRE]) return;
-        slot = rfl(a.retire_list[blockIdx.y]);
+        if (by >= a.ctr[CTR_RETIRE]) return;
+        slot = rfl(a.retire_list[by]);
     }
     sweep_group<R, MODE, NS, NC, MC>(a, grp, slot, lane, rec, phi, popsb, part,
                                      red_lds + (threadIdx.x >> 6) * Red<R, NS, MODE>::SIZE);
