@@ -41,9 +41,9 @@ HBM_PEAK_GBS = 8000.0
 # taken on: the JSON line reports null once that source has changed.
 SWEEP_TRAFFIC = {
     "source": "paper_1411_1079_amd/csrc/mali.hip",
-    "sha256": "e49a09ff5700dfb3aa61cc65039b63bdd4e53a3c9cf9f3f0af4098e05484a600",
-    "read_bytes": 27.67e9,
-    "written_bytes": 5.17e9,
+    "sha256": "faa7bd61e2052098e6276862805a998627bf5da4d46d569ee81efc2b3cafaeb6",
+    "read_bytes": 25.75e9,
+    "written_bytes": 5.14e9,
     "summary": "profiles/k_sweep_fp32_cube256_counters.md",
 }
 
