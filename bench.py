@@ -101,7 +101,10 @@ def train_network(rh, torch, atom, args):
     dc = rh.DeviceColumns.from_host(cols)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    res = rh.solve(atom, dc, precision=0, scheduler=1, n_mu=5, tol=1e-6, max_iter=300, profile=0)
+    # a fixed formal-solution shape (not the autotuner's choice), so that the
+    # targets, and the trained network, are the same on every run
+    res = rh.solve(atom, dc, precision=0, scheduler=1, n_mu=5, tol=1e-6, max_iter=300, profile=0,
+                   sweep_mc=1, sweep_pack=1)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     net, rep = warmstart.train(atom, dc, res["pops"], steps=args.train_steps, batch=8192, lr=2e-3, seed=1)
