@@ -256,6 +256,52 @@ class Solver:
         return out
 
 
+def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stream=None) -> int:
+    """Solve again, with the option set `opts`, every column of `dc` whose
+    status in the result `out` (the dict of CUDA tensors that solve() or
+    Solver.result() returns) is not converged, and write the new results
+    into `out`; n_iter then counts the iterations of both attempts.  The
+    paper's code re-runs failed columns with other options (Sec. 2.3,
+    convergence aids); here any option set can serve, e.g. the LTE start,
+    collisional-radiative switching or a larger iteration limit.  The
+    history rows of those columns become the second attempt's.  Returns
+    the number of columns solved again (a host synchronisation)."""
+    import torch
+    bad = torch.nonzero(out["status"] != CONVERGED).flatten().cpu().numpy()
+    if bad.size == 0:
+        return 0
+    off = dc.offset
+    lens = np.diff(off)[bad]
+    idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in bad])
+    dev = dc.z.device
+    it = torch.as_tensor(idx, dtype=torch.int64, device=dev)
+    fields = {k: torch.index_select(getattr(dc, k), 0, it) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    init = None
+    if opts.start == START_PROVIDED:
+        if dc.init_pops is None:
+            raise ValueError("a provided start needs the columns' init_pops")
+        init = torch.index_select(dc.init_pops, 0, it)
+    sub = DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), init_pops=init, **fields)
+    r = Solver(atom, sub, opts, want_spectrum=out.get("spectrum") is not None,
+               want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None).run(stream)
+    cb = torch.as_tensor(bad, dtype=torch.int64, device=dev)
+    out["pops"].index_copy_(0, it, r.pops)
+    if out.get("psi_star") is not None:
+        out["psi_star"].index_copy_(0, it, r.psi_star)
+    if out.get("spectrum") is not None:
+        out["spectrum"].index_copy_(0, cb, r.spectrum)
+    if out.get("history") is not None:
+        # the second attempt's history, cut or padded (NaN) to the width of out
+        h = out["history"]
+        rows = torch.full((bad.size, h.shape[1]), float("nan"), dtype=h.dtype, device=dev)
+        w = min(h.shape[1], r.history.shape[1])
+        rows[:, :w] = r.history[:, :w]
+        h.index_copy_(0, cb, rows)
+    out["n_iter"].index_copy_(0, cb, out["n_iter"].index_select(0, cb) + r.n_iter)
+    out["status"].index_copy_(0, cb, r.status)
+    return int(bad.size)
+
+
 def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, **opts) -> dict:
     """Solve every column; returns CUDA tensors (pops, history, n_iter,
     status, spectrum, psi_star)."""

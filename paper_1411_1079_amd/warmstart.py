@@ -124,34 +124,9 @@ class WarmStartSolver:
         """Re-solve every column whose status is not converged from LTE and
         write its results into this solver's outputs; n_iter then counts the
         iterations of both attempts.  Returns the number of columns redone."""
-        import torch
-        s = self.solver
-        bad = torch.nonzero(s.status != rh.CONVERGED).flatten().cpu().numpy()
-        self.refined = int(bad.size)
-        if bad.size == 0:
-            return 0
-        dc = self.dc
-        off = dc.offset
-        lens = np.diff(off)[bad]
-        idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in bad])
-        it = torch.as_tensor(idx, dtype=torch.int64, device=dc.z.device)
-        sub = rh.DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64),
-                               **{k: torch.index_select(getattr(dc, k), 0, it)
-                                  for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")})
         o = rh.Options.from_buffer_copy(self.opts)
         o.start = rh.START_LTE
-        r = rh.Solver(self.atom, sub, o, want_spectrum=s.spectrum is not None, want_psi=s.psi_star is not None,
-                      want_history=s.history is not None).run(stream)
-        cb = torch.as_tensor(bad, dtype=torch.int64, device=dc.z.device)
-        s.pops.index_copy_(0, it, r.pops)
-        if s.psi_star is not None:
-            s.psi_star.index_copy_(0, it, r.psi_star)
-        if s.spectrum is not None:
-            s.spectrum.index_copy_(0, cb, r.spectrum)
-        if s.history is not None:
-            s.history.index_copy_(0, cb, r.history)
-        s.n_iter.index_copy_(0, cb, s.n_iter.index_select(0, cb) + r.n_iter)
-        s.status.index_copy_(0, cb, r.status)
+        self.refined = rh.resolve_failed(self.atom, self.dc, self.solver.result(), o, stream=stream)
         return self.refined
 
     def result(self) -> dict:

@@ -1,8 +1,9 @@
-"""Collisional-radiative switching (Sec. 2.3) through the C ABI: the GPU
-path against the oracle with the switched collisions, in lock-step for
-FP64 (same iteration counts, same Ng decisions) and within 1e-3 for the
-FP32 form; switching off reproduces the default bit for bit; invalid
-factors are rejected."""
+"""Convergence aids (Sec. 2.3) through the C ABI.  Collisional-radiative
+switching: the GPU path against the oracle with the switched collisions, in
+lock-step for FP64 (same iteration counts, same Ng decisions) and within
+1e-3 for the FP32 form; switching off reproduces the default bit for bit;
+invalid factors are rejected.  Failed columns solved again with another
+option set."""
 import numpy as np
 import pytest
 
@@ -84,3 +85,44 @@ def test_invalid_factor_rejected(atom_dir, bad):
     dc = rh.DeviceColumns.from_host(_columns().select([0]))
     with pytest.raises(rh.RH15DError, match="crs_f0"):
         rh.solve(atom, dc, crs_f0=bad)
+
+
+def test_failed_columns_solved_again_with_other_options(atom_dir):
+    """Columns stopped by a small iteration limit are solved again with
+    another option set (switched collisions, a larger limit): every column
+    then converges, the re-solved ones match the oracle run with the second
+    option set (their iteration counts adding both attempts), and the
+    columns that had converged keep their results bit for bit."""
+    rh = _rh()
+    cols = _columns()
+    atom = rh.Atom(atom_dir["h6"])
+    dc = rh.DeviceColumns.from_host(cols)
+    first = dict(n_mu=3, tol=1e-6, max_iter=6, coll_scale=0.3)
+    print(f"[gpu] first attempt {first}", flush=True)
+    out = rh.solve(atom, dc, want_psi=True, **first)
+    torch.cuda.synchronize()
+    g0 = {k: v.cpu().numpy().copy() for k, v in out.items()}
+    failed = g0["status"] != 0
+    assert failed.any() and (~failed).any()
+    again = dict(n_mu=3, tol=1e-6, max_iter=120, coll_scale=0.3, crs_f0=1e3)
+    print(f"[gpu] second attempt {again}", flush=True)
+    n = rh.resolve_failed(atom, dc, out, rh.default_options(**again))
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert n == int(failed.sum()) and np.all(g["status"] == 0)
+    a = O.Atom(atom_dir["h6"])
+    for c in range(cols.n_columns):
+        lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
+        if not failed[c]:
+            for k in ("n_iter", "status"):
+                assert g[k][c] == g0[k][c]
+            np.testing.assert_array_equal(g["pops"][lo:hi], g0["pops"][lo:hi])
+            np.testing.assert_array_equal(g["spectrum"][c], g0["spectrum"][c])
+            continue
+        r, rtol = conftest.oracle_lockstep_rtol(a, cols.column(c), **again)
+        assert g["n_iter"][c] == first["max_iter"] + r["n_iter"]
+        np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=rtol)
+        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=rtol)
+        np.testing.assert_allclose(g["psi_star"][lo:hi].T, r["psi_star"], rtol=rtol, atol=1e-300)
+        m = min(first["max_iter"], r["n_iter"])
+        np.testing.assert_allclose(g["history"][c, :m], r["history"][:m], rtol=1e-6, atol=4 * rtol)
