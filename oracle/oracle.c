@@ -20,8 +20,8 @@
  *      with particle conservation replacing one equation;
  *   5. maximum relative population change (Sec. 2.3, the convergence
  *      measure of Fig. 1) and Ng extrapolation (Sec. 2.3, Ng 1974 / Auer).
- * Start solutions: LTE and zero radiation (Sec. 2.3, "Different starting
- * solutions").  Collisional-radiative switching (Sec. 2.3; Hummer &
+ * Start solutions: LTE, zero radiation and escape-probability iterations
+ * (Sec. 2.3, "Different starting solutions").  Collisional-radiative switching (Sec. 2.3; Hummer &
  * Voels 1988): a constant collision multiplier, and a factor on the
  * collision rates that starts at f0 and falls tenfold per iteration to 1
  * (see orc_crs_factor; this schedule is a reading, the paper gives none).
@@ -96,6 +96,9 @@ typedef struct {
     int start;           /* 0 LTE, 1 zero radiation, 2 provided */
     double coll_scale;   /* collision multiplier (1 = physical) */
     double crs_f0;       /* collisional-radiative switching: initial factor (<= 1: off) */
+    double tol_fp;       /* > 0: also require the estimated distance to the fixed point
+                            below tol_fp (see converged_at); 0: off */
+    int esc_iter;        /* escape-probability start: number of iterations */
 } orc_opts;
 
 /* ------------------------------------------------------------------ */
@@ -794,19 +797,118 @@ int orc_ng_step(int M, int n, double *const *x, double *out) {
     return 1;
 }
 
+/* Stopping rule.  Sec. 2.3 measures convergence by the maximum relative
+ * population change Delta_k of iteration k; the column has converged when
+ * Delta_k < tol.  With tol_fp > 0 the distance to the fixed point that the
+ * last two changes imply is bounded as well: for a linear iteration with
+ * contraction factor r = Delta_k / Delta_{k-1} the remaining distance is
+ * Delta_k r / (1 - r), which must fall below tol_fp; it needs
+ * Delta_k < Delta_{k-1} and is tested as Delta_k^2 < tol_fp (Delta_{k-1} -
+ * Delta_k), with no division.  The ratio is that of two plain iterations:
+ * when the previous iteration ended with an Ng extrapolation, or at the
+ * first iteration, there is no ratio and only Delta_k = 0 passes.  (This
+ * bound is a reading: the paper states the threshold on Delta only.) */
+static int converged_at(double d, double dprev, double tol, double tol_fp) {
+    if (!(d < tol)) return 0;
+    if (!(tol_fp > 0.0)) return 1;
+    if (dprev < 0.0) return d == 0.0;
+    return d < dprev && d * d < tol_fp * (dprev - d);
+}
+
+/* Column data the method can use: finite positive T, n_e, n_H, finite
+ * velocities, non-negative microturbulence and strictly decreasing z. */
+static int column_valid(int N, const double *z, const double *T, const double *ne, const double *nH,
+                        const double *vz, const double *vt) {
+    for (int k = 0; k < N; k++) {
+        if (!(isfinite(T[k]) && T[k] > 0.0 && isfinite(ne[k]) && ne[k] > 0.0 && isfinite(nH[k]) && nH[k] > 0.0))
+            return 0;
+        if (!(isfinite(vz[k]) && isfinite(vt[k]) && vt[k] >= 0.0 && isfinite(z[k]))) return 0;
+        if (k > 0 && !(z[k] < z[k - 1])) return 0;
+    }
+    return 1;
+}
+
+/* Escape probability of the escape-probability start: (1 - e^-tau)/tau,
+ * the fraction of photons created at vertical optical depth tau that
+ * leave a uniform layer of that thickness (1 at tau = 0). */
+static double escape_probability(double tau) { return tau > 0.0 ? -expm1(-tau) / tau : 1.0; }
+
+/* Escape-probability start (Sec. 2.3, "Different starting solutions":
+ * populations from a few statistical-equilibrium iterations with an
+ * assumed probability of photon escape).  Starting from LTE, each of the
+ * esc_iter iterations
+ *   1. takes, for every transition, the vertical optical depth from the top
+ *      at its reference frequency with the current populations: for a line
+ *      chi = (h nu0 / 4 pi)(n_l B_lu - n_u B_ul) phi(nu0), phi(nu0) the
+ *      rest-frame line-centre profile H(a, 0) / (sqrt(pi) Delta nu_D), for a
+ *      continuum chi = (n_l - n_u G(nu_edge)) alpha(nu_edge); negative
+ *      opacities count as 0; tau by the trapezoid rule in z from tau = 0
+ *      at the top point;
+ *   2. solves the rate equations with the spontaneous rate of every
+ *      transition times its escape probability beta(tau) and no other
+ *      radiative rate (net radiative bracket), plus collisions.
+ * beta = 1 everywhere is the zero-radiation start.  zr holds the
+ * zero-radiation rates (P = 0, Q' the spontaneous rates); n is updated in
+ * place. */
+static int escape_start(const colstate *cs, const rates *zr, int n_it, double *n) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L, T = a->T;
+    rates R;
+    R.P = calloc((size_t)T * N, sizeof(double));
+    R.Q = malloc(sizeof(double) * T * N);
+    R.X = calloc((size_t)T * T * N, sizeof(double));
+    double *chi = malloc(sizeof(double) * N), *nn = malloc(sizeof(double) * N * L);
+    int rc = 0;
+    for (int s = 0; s < n_it && rc == 0; s++) {
+        for (int t = 0; t < T; t++) {
+            const orc_trans *tr = &a->tr[t];
+            for (int k = 0; k < N; k++) {
+                double nl = n[k * L + tr->l], nu = n[k * L + tr->u], c;
+                if (tr->kind == 0) {
+                    double dnd = cs->dnuD[t * N + k];
+                    double H0 = tr->voigt ? orc_voigt_H(cs->adamp[t * N + k], 0.0) : 1.0;
+                    c = PH * tr->nu0 / (4.0 * PPI) * (nl * tr->Blu - nu * tr->Bul) * H0 / (sqrt(PPI) * dnd);
+                } else {
+                    double G = exp(cs->lnr[k * L + tr->l] - cs->lnr[k * L + tr->u]) * exp(-PH * tr->nu0 / (PKB * cs->T[k]));
+                    c = (nl - nu * G) * tr->alpha0;
+                }
+                chi[k] = c > 0.0 ? c : 0.0;
+            }
+            double tau = 0.0;
+            for (int k = 0; k < N; k++) {
+                if (k > 0) tau += 0.5 * (chi[k - 1] + chi[k]) * (cs->z[k - 1] - cs->z[k]);
+                R.Q[t * N + k] = zr->Q[t * N + k] * escape_probability(tau);
+            }
+        }
+        if (solve_se(cs, &R, n, nn, 1.0)) rc = -1;
+        memcpy(n, nn, sizeof(double) * N * L);
+    }
+    free(R.P); free(R.Q); free(R.X); free(chi); free(nn);
+    return rc;
+}
+
 /* Solve one column.  Arrays of the column: N points, top first.
  * Outputs (any may be NULL except pops): pops[N][L], history[max_iter],
  * spectrum[NL], psi_star[T][N]; n_iter and status scalars.
  * status: 0 converged, 1 iteration limit, 2 non-finite or non-positive
- * populations, 3 singular rate matrix. */
+ * populations, 3 singular rate matrix, 4 invalid column data (outputs
+ * NaN, no iteration). */
 int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
                      const double *nH, const double *vz, const double *vt, const double *init_pops,
                      const orc_opts *o, double *pops, double *history, int *n_iter, int *status,
                      double *spectrum, double *psi_star) {
     if (N < 2) FAIL(-3, "need at least 2 depth points");
-    for (int k = 1; k < N; k++) if (!(z[k] < z[k - 1])) FAIL(-3, "z must decrease with depth index");
     if (o->n_mu < 1 || o->n_mu > 16) FAIL(-3, "n_mu out of range");
     if (o->ng_order != 0 && o->ng_order != 2) FAIL(-3, "only Ng order 2 (or 0 = off) is implemented");
+    if (!column_valid(N, z, T, ne, nH, vz, vt)) {
+        for (int i = 0; i < N * a->L; i++) pops[i] = NAN;
+        if (history) for (int i = 0; i < o->max_iter; i++) history[i] = NAN;
+        if (spectrum) for (int j = 0; j < a->NL; j++) spectrum[j] = NAN;
+        if (psi_star) for (int i = 0; i < a->T * N; i++) psi_star[i] = NAN;
+        *n_iter = 0;
+        *status = 4;
+        return 0;
+    }
     colstate cs = {0};
     cs.a = a; cs.N = N; cs.nmu = o->n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
     cs.mu = malloc(sizeof(double) * o->n_mu); cs.wmu = malloc(sizeof(double) * o->n_mu);
@@ -828,9 +930,13 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
         solve_se(&cs, &R, cs.nstar, n, 1.0);
     } else if (o->start == 2 && init_pops) {
         memcpy(n, init_pops, sizeof(double) * NV);
+    } else if (o->start == 3) {
+        sweep(&cs, n, 1, &R, NULL);
+        escape_start(&cs, &R, o->esc_iter, n);
     }
     if (history) for (int i = 0; i < o->max_iter; i++) history[i] = NAN;
     int st = 1, it;
+    double dprev = -1.0;   /* change of the previous iteration (none yet) */
     for (it = 1; it <= o->max_iter; it++) {
         sweep(&cs, n, 0, &R, NULL);
         /* while collisions are switched (cf > 1) the iterate solves another
@@ -848,7 +954,8 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
         if (bad) { st = 3; break; }
         if (!finite) { st = 2; break; }
         memcpy(n, nse, sizeof(double) * NV);
-        if (dmax < o->tol && cf == 1.0) { st = 0; break; }
+        if (cf == 1.0 && converged_at(dmax, dprev, o->tol, o->tol_fp)) { st = 0; break; }
+        dprev = dmax;
         if (M > 0 && it >= o->ng_delay && cf == 1.0) {
             /* push newest iterate */
             double *last = ring[ring_n - 1];
@@ -860,7 +967,9 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
              * history restarts after each attempt, applied or skipped */
             int need = o->ng_period > ring_n ? o->ng_period : ring_n;
             if (ng_count >= need) {
-                orc_ng_step(M, NV, ring, n);
+                /* an applied extrapolation leaves no contraction ratio for
+                 * the next iteration's stopping test */
+                if (orc_ng_step(M, NV, ring, n)) dprev = -1.0;
                 ng_count = 0;
             }
         }
@@ -889,6 +998,23 @@ int orc_column_profile_norm(const orc_atom *a, int N, const double *z, const dou
     column_prepare(&cs, 1.0);
     if (nstar) memcpy(nstar, cs.nstar, sizeof(double) * N * a->L);
     if (norm) memcpy(norm, cs.norm, sizeof(double) * N * a->n_lines);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return 0;
+}
+
+/* Doppler widths (Hz) and Voigt damping parameters of every line at every
+ * depth point of a column, [n_lines][N] each, as the column preparation
+ * computes them (tests only). */
+int orc_column_damping(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                       const double *nH, const double *vz, const double *vt, double *dnuD, double *adamp) {
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = 1; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double)); cs.wmu = malloc(sizeof(double));
+    orc_gauss_legendre(1, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    if (dnuD) memcpy(dnuD, cs.dnuD, sizeof(double) * N * a->n_lines);
+    if (adamp) memcpy(adamp, cs.adamp, sizeof(double) * N * a->n_lines);
     column_release(&cs);
     free(cs.mu); free(cs.wmu);
     return 0;

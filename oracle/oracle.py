@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-START_LTE, START_ZERO_RADIATION, START_PROVIDED = 0, 1, 2
+START_LTE, START_ZERO_RADIATION, START_PROVIDED, START_ESCAPE = 0, 1, 2, 3
+BAD_INPUT = 4
 
 
 def build() -> str:
@@ -60,6 +61,7 @@ def lib():
         L.orc_crs_factor.restype = C.c_double
         L.orc_ng_step.argtypes = [C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_double)), dp]
         L.orc_column_profile_norm.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp]
+        L.orc_column_damping.argtypes = [C.c_void_p, C.c_int] + [dp] * 8
         _lib = L
     return _lib
 
@@ -71,7 +73,7 @@ def _p(a):
 class _Opts(C.Structure):
     _fields_ = [("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("ng_order", C.c_int),
                 ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int), ("coll_scale", C.c_double),
-                ("crs_f0", C.c_double)]
+                ("crs_f0", C.c_double), ("tol_fp", C.c_double), ("esc_iter", C.c_int)]
 
 
 class Atom:
@@ -155,6 +157,18 @@ def profile_norm(atom: Atom, col: dict, n_mu: int):
     return nstar, norm[: atom.n_lines]
 
 
+def column_damping(atom: Atom, col: dict):
+    """Doppler widths (Hz) and Voigt damping parameters [n_lines][N] of the
+    column preparation."""
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    dnd = np.empty((max(atom.n_lines, 1), N))
+    ad = np.empty((max(atom.n_lines, 1), N))
+    lib().orc_column_damping(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                             _p(dnd), _p(ad))
+    return dnd[: atom.n_lines], ad[: atom.n_lines]
+
+
 def crs_factor(f0: float, it: int) -> float:
     """Collision factor of iteration it under collisional-radiative switching."""
     return lib().orc_crs_factor(f0, it)
@@ -163,10 +177,10 @@ def crs_factor(f0: float, it: int) -> float:
 def solve_column(atom: Atom, col: dict, n_mu: int = 5, tol: float = 1e-4, max_iter: int = 200,
                  ng_order: int = 2, ng_delay: int = 5, ng_period: int = 4, start: int = START_LTE,
                  coll_scale: float = 1.0, init_pops=None, want_spectrum: bool = True,
-                 want_psi: bool = False, crs_f0: float = 1.0) -> dict:
+                 want_psi: bool = False, crs_f0: float = 1.0, tol_fp: float = 0.0, esc_iter: int = 3) -> dict:
     N = len(col["z"])
     cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
-    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale, crs_f0)
+    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale, crs_f0, tol_fp, esc_iter)
     pops = np.empty((N, atom.n_levels))
     hist = np.empty(max(max_iter, 1))
     spec = np.empty(atom.n_lambda) if want_spectrum else None

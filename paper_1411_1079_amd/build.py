@@ -21,15 +21,19 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every source (concurrently), then link."""
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [cmd for cmd, p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB] + objs
     subprocess.run(cmd, check=True)
     for o in objs:

@@ -4,9 +4,9 @@ Independent of the oracle's code: it parses the atom file itself, builds
 the wavelength grid and quadratures itself, and obtains the radiation
 field from explicit Lambda matrices (the exact formal solution for a
 source function that is piecewise linear in optical depth, integrated in
-40-digit arithmetic) instead of a depth recurrence.  It supports Gaussian
-line profiles only (Voigt-profile atoms are pinned against
-scipy.special.wofz separately).
+40-digit arithmetic) instead of a depth recurrence.  Line profiles are
+Gaussian, or Voigt from the Faddeeva function (scipy.special.wofz) with
+the radiative damping width computed here from the Einstein A values.
 
 Used to pin the oracle against what the mathematics fixes:
 * the statistical-equilibrium fixed point (classical Lambda iteration,
@@ -89,6 +89,20 @@ class BAtom:
             w[1:] += 0.5 * (nu[:-1] - nu[1:])
             d["act"], d["w"] = act, w
 
+    def damping(self, ti):
+        """Radiative damping width (s^-1) of line ti: the sum of the Einstein
+        A values of all lines out of its upper and out of its lower level."""
+        d = self.tr[ti]
+        return sum(e["A"] for e in self.tr if e["kind"] == 0 and e["u"] in (d["u"], d["l"]))
+
+
+def _profile_H(kind, a, v):
+    """Gaussian exp(-v^2), or the Voigt function H(a, v) = Re w(v + i a)."""
+    if kind == "GAUSS":
+        return math.exp(-v * v)
+    from scipy.special import wofz
+    return float(wofz(complex(v, a)).real)
+
 
 def lte_pops(atom: BAtom, T, ne, ntot):
     """Boltzmann within a stage, Saha between stages (relative to level 0)."""
@@ -130,8 +144,9 @@ class Problem:
     """A column, an atom and n_mu Gauss-Legendre angles: every ray's
     opacity terms as explicit functions of the populations."""
 
-    def __init__(self, atom: BAtom, col: dict, n_mu: int, coll_scale: float = 1.0):
+    def __init__(self, atom: BAtom, col: dict, n_mu: int, coll_scale: float = 1.0, damping_scale: float = 1.0):
         self.a, self.col = atom, col
+        self.damping_scale = damping_scale
         self.N = len(col["z"])
         x, w = np.polynomial.legendre.leggauss(n_mu)
         self.mu, self.wmu = 0.5 * (x + 1), 0.5 * w
@@ -145,17 +160,17 @@ class Problem:
         for ti, d in enumerate(atom.tr):
             if d["kind"] != 0:
                 continue
-            assert d["profile"] == "GAUSS"
             ph = np.zeros((self.N, len(self.rays)))
             for k in range(self.N):
                 dnd = d["nu0"] / C * math.sqrt(2 * KB * T[k] / atom.mass + col["v_turb"][k] ** 2)
+                adamp = damping_scale * atom.damping(ti) / (4 * math.pi * dnd)
                 tot = 0.0
                 for r, (j, m, s) in enumerate(self.rays):
                     if j not in d["act"]:
                         continue
                     mus = self.mu[m] if s else -self.mu[m]
                     v = (atom.nu[j] - d["nu0"] * (1 + mus * col["v_z"][k] / C)) / dnd
-                    ph[k, r] = math.exp(-v * v) / (math.sqrt(math.pi) * dnd)
+                    ph[k, r] = _profile_H(d["profile"], adamp, v) / (math.sqrt(math.pi) * dnd)
                     tot += self.weight(ti, r) * ph[k, r]
                 ph[k] /= tot
                 self.norm[ti][k] = tot
@@ -360,7 +375,8 @@ class Problem:
                     if d["kind"] == 0:
                         dnd = d["nu0"] / C * math.sqrt(2 * KB * T[k] / a.mass + self.col["v_turb"][k] ** 2)
                         v = (nu - d["nu0"] * (1 + self.col["v_z"][k] / C)) / dnd
-                        p = math.exp(-v * v) / (math.sqrt(math.pi) * dnd) / self.norm[ti][k]
+                        adamp = self.damping_scale * a.damping(ti) / (4 * math.pi * dnd)
+                        p = _profile_H(d["profile"], adamp, v) / (math.sqrt(math.pi) * dnd) / self.norm[ti][k]
                         c = H * d["nu0"] / (4 * math.pi)
                         Vlu, Vul, U = c * d["Blu"] * p, c * d["Bul"] * p, c * d["A"] * p
                     else:

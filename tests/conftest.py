@@ -22,16 +22,20 @@ def atom_dir(tmp_path_factory):
     paths = synth.write_atoms(str(d))
     paths["tiny"] = write_tiny_atom(os.path.join(str(d), "tiny.atom"))
     paths["tiny_nobg"] = write_tiny_atom(os.path.join(str(d), "tiny_nobg.atom"), c_bg=None)
+    paths["tiny_voigt"] = write_tiny_atom(os.path.join(str(d), "tiny_voigt.atom"), profile="VOIGT", f_scale=1e6,
+                                          n_line=11, x_max=30.0)
     return paths
 
 
 TINY_MASS = 1.00794
 
 
-def write_tiny_atom(path, c_bg=1.0e-38):
+def write_tiny_atom(path, c_bg=1.0e-38, profile="GAUSS", f_scale=1.0, n_line=9, x_max=4.0):
     """Four-level test atom with Gaussian profiles and every kind of
     overlap: two lines with the same rest wavelength (a full blend), a
-    line inside a continuum, and two overlapping continua."""
+    line inside a continuum, and two overlapping continua.  With
+    profile="VOIGT", strong lines (f_scale) and wide line grids (x_max
+    Doppler units of 10 km/s) the radiative damping shapes the wings."""
     levels = [(0.0, 2.0, 0), (1.5, 2.0, 0), (3.0, 4.0, 0), (5.9, 1.0, 1)]
     ev = synth._EV
     hc = synth._H * synth._C
@@ -40,12 +44,12 @@ def write_tiny_atom(path, c_bg=1.0e-38):
         return hc / ((levels[hi][0] - levels[lo][0]) * ev) * 1e9
 
     lines = [
-        dict(l=0, u=1, f=3e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
-             lam=synth.line_grid_nm(lam0(0, 1), n=9, x_max=4.0)),
-        dict(l=1, u=2, f=2e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
-             lam=synth.line_grid_nm(lam0(1, 2), n=9, x_max=4.0)),
-        dict(l=0, u=2, f=1e-7, profile="GAUSS", coll="OMEGA", cval=1.0,
-             lam=synth.line_grid_nm(lam0(0, 2), n=9, x_max=4.0)),
+        dict(l=0, u=1, f=3e-7 * f_scale, profile=profile, coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(0, 1), n=n_line, x_max=x_max)),
+        dict(l=1, u=2, f=2e-7 * f_scale, profile=profile, coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(1, 2), n=n_line, x_max=x_max)),
+        dict(l=0, u=2, f=1e-7 * f_scale, profile=profile, coll="OMEGA", cval=1.0,
+             lam=synth.line_grid_nm(lam0(0, 2), n=n_line, x_max=x_max)),
     ]
     conts = [dict(l=i, u=3, alpha=a, coll="OMEGA", cval=0.1,
                   lam=np.sort(synth.continuum_grid_nm(lam0(i, 3), n=5)))
