@@ -25,6 +25,11 @@
  * Voels 1988): a constant collision multiplier, and a factor on the
  * collision rates that starts at f0 and falls tenfold per iteration to 1
  * (see orc_crs_factor; this schedule is a reading, the paper gives none).
+ * Partial frequency redistribution (Sec. 2.1: MALI extended to PRD after
+ * Uitenbroek 2001, angle-averaged option; Sec. 2.3: PRD switching, Eq. 1):
+ * lines flagged PRD emit with psi = rho phi, rho updated after every
+ * iteration from the angle-averaged redistribution function R_II (see
+ * orc_rII and prd_update).
  * Output: emergent vertical intensity
  * (Sec. 2.2: only vertical emergent spectra) and per-transition Psi*.
  *
@@ -65,6 +70,9 @@ typedef struct {
     int coll_kind;      /* 0: Omega model, 1: fixed destruction probability eps */
     double coll_val;
     double alpha0;      /* continuum cross-section at the edge, m^2 */
+    double c_el;        /* line: elastic-collision rate per hydrogen atom, m^3 s^-1
+                           (Q_E = c_el n_H; broadens the line and sets its coherence) */
+    int prd;            /* line: partial frequency redistribution (angle-averaged R_II) */
     int n_own;
     double *lam_own;    /* the transition's own wavelengths, m */
     /* derived */
@@ -99,6 +107,9 @@ typedef struct {
     double tol_fp;       /* > 0: also require the estimated distance to the fixed point
                             below tol_fp (see converged_at); 0: off */
     int esc_iter;        /* escape-probability start: number of iterations */
+    int prd;             /* 1: lines flagged PRD in the atom use PRD; 0: every line CRD */
+    double prd_eps0;     /* PRD switching (Eq. 1): eps of the update after iteration n is
+                            min(1, prd_eps0 n^2); <= 0: off (eps = 1) */
 } orc_opts;
 
 /* ------------------------------------------------------------------ */
@@ -204,7 +215,23 @@ int orc_atom_load(const char *path, orc_atom **out) {
     memcpy(a->tr, lines, sizeof(orc_trans) * a->n_lines);
     free(lines);
     for (int i = 0; i < a->n_cont; i++) if (parse_transition(&ts, &a->tr[a->n_lines + i], 1, a->L)) goto bad;
-    if (tok_expect(&ts, "BACKGROUND") || !(tk = next_tok(&ts))) goto bad;
+    /* optional: elastic collisions and the redistribution of lines */
+    if (!(tk = next_tok(&ts))) goto bad;
+    if (!strcmp(tk, "ELASTIC")) {
+        int ne;
+        if (tok_int(&ts, &ne) || ne < 0) goto bad;
+        for (int i = 0; i < ne; i++) {
+            int li;
+            double c;
+            const char *kind;
+            if (tok_int(&ts, &li) || li < 0 || li >= a->n_lines || tok_double(&ts, &c) || !(c >= 0.0)) goto bad;
+            if (!(kind = next_tok(&ts))) goto bad;
+            a->tr[li].c_el = c;
+            if (!strcmp(kind, "PRD")) a->tr[li].prd = 1; else if (!strcmp(kind, "CRD")) a->tr[li].prd = 0; else goto bad;
+        }
+        if (!(tk = next_tok(&ts))) goto bad;
+    }
+    if (strcmp(tk, "BACKGROUND") || !(tk = next_tok(&ts))) goto bad;
     if (!strcmp(tk, "NONE")) a->bg_kind = 0;
     else if (!strcmp(tk, "HMINUS")) { a->bg_kind = 1; if (tok_double(&ts, &a->c_bg)) goto bad; }
     else goto bad;
@@ -370,6 +397,74 @@ double orc_voigt_H(double a, double v) {
     return wr;
 }
 
+/* Angle-averaged redistribution function R_II (Hummer 1962) in Doppler
+ * units, for damping parameter a > 0 and frequencies x, x2 (normalised so
+ * that its integral over x2 is H(a, x) / sqrt(pi)).  Written as the
+ * Lorentzian average, over the frequency xi of the scattering in the atom's
+ * frame, of the angle-averaged Doppler kernel of coherent scattering,
+ * (1/2) erfc(max(|x - xi|, |x2 - xi|)) = (1/2) erfc(|xi - m| + d) with
+ * m = (x + x2)/2 and d = |x - x2|/2:
+ *   R_II(x, x2) = 1/2 integral (a/pi) / (a^2 + xi^2) erfc(|xi - m| + d) dxi,
+ * which equals Hummer's integral over u of exp(-u^2) times a difference of
+ * arctangents.  Quadrature (a reading; the paper prints no formula):
+ * 0 where d >= 6 (erfc(6) = 2.2e-17); otherwise xi runs over
+ * [m - w, m + w], w = 6 - d, cut at xi = m (the kink) and at xi = +-0.5
+ * where inside; pieces within |xi| <= 0.5 (the Lorentzian core) are mapped
+ * to t = asinh(xi / a), where the Lorentzian measure is dt / (pi cosh t),
+ * and integrated by 4-point Gauss-Legendre on 8 panels uniform in t; the
+ * other pieces by 4-point Gauss-Legendre on ceil(length) panels uniform in
+ * xi.  Accuracy: within 1e-4 of the larger of R_II(x, x) and
+ * R_II(x2, x2) for 1e-4 <= a <= 0.5. */
+#define RII_CORE 0.5
+#define RII_CORE_PANELS 8
+double orc_rII(double a, double x, double x2) {
+    static const double gx[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563, 0.8611363115940526};
+    static const double gw[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461, 0.3478548451374538};
+    double m = 0.5 * (x + x2), d = 0.5 * fabs(x - x2);
+    if (d >= 6.0) return 0.0;
+    double w = 6.0 - d;
+    /* cut points in increasing order */
+    double e[5];
+    int ne = 0;
+    e[ne++] = m - w;
+    if (-RII_CORE > m - w && -RII_CORE < m) e[ne++] = -RII_CORE;
+    if (RII_CORE > m - w && RII_CORE < m) e[ne++] = RII_CORE;
+    e[ne++] = m;
+    double e2[2];
+    int ne2 = 0;
+    if (-RII_CORE > m && -RII_CORE < m + w) e2[ne2++] = -RII_CORE;
+    if (RII_CORE > m && RII_CORE < m + w) e2[ne2++] = RII_CORE;
+    for (int i = 0; i < ne2; i++) e[ne++] = e2[i];
+    e[ne++] = m + w;
+    double sum = 0.0;
+    for (int i = 0; i + 1 < ne; i++) {
+        double lo = e[i], hi = e[i + 1];
+        if (!(hi > lo)) continue;
+        if (lo >= -RII_CORE && hi <= RII_CORE) {
+            double t0 = asinh(lo / a), h = (asinh(hi / a) - t0) / RII_CORE_PANELS;
+            for (int p = 0; p < RII_CORE_PANELS; p++) {
+                double c = t0 + (p + 0.5) * h;
+                for (int q = 0; q < 4; q++) {
+                    double sh = sinh(c + 0.5 * h * gx[q]);
+                    sum += 0.5 * h * gw[q] * erfc(fabs(a * sh - m) + d) / (PPI * sqrt(1.0 + sh * sh));
+                }
+            }
+        } else {
+            int np = (int)ceil(hi - lo);
+            if (np < 1) np = 1;
+            double h = (hi - lo) / np;
+            for (int p = 0; p < np; p++) {
+                double c = lo + (p + 0.5) * h;
+                for (int q = 0; q < 4; q++) {
+                    double xi = c + 0.5 * h * gx[q];
+                    sum += 0.5 * h * gw[q] * (a / PPI) / (a * a + xi * xi) * erfc(fabs(xi - m) + d);
+                }
+            }
+        }
+    }
+    return 0.5 * sum;
+}
+
 /* Linear short-characteristic weights for an optical step x along a ray:
  * I_b = I_a e + wa S_a + wb S_b. */
 void orc_sc_coefficients(double x, double *e, double *wa, double *wb) {
@@ -471,6 +566,10 @@ typedef struct {
     double *adamp;       /* [n_lines][N] */
     double *norm;        /* [n_lines][N] profile normalisation sum */
     double **phi;        /* per line: [N][n_act][nmu][2] normalised profile */
+    /* PRD (lines with prd set, when the solve enables PRD; NULL otherwise) */
+    double **gII;        /* per line: [N][n_act][n_act] redistribution weights g(j', j) */
+    double **rho;        /* per line: [N][n_act] emission / absorption profile ratio */
+    double *Iall;        /* [NL][nmu][2][N] intensity of every ray of the last sweep */
 } colstate;
 
 static double line_profile(const orc_atom *a, int t, const colstate *cs, int k, double nu, double mus) {
@@ -523,7 +622,7 @@ static void column_prepare(colstate *cs, double coll_scale) {
             double vth2 = 2.0 * PKB * cs->T[k] / a->mass + cs->vt[k] * cs->vt[k];
             double dnd = tr->nu0 / PC * sqrt(vth2);
             cs->dnuD[t * N + k] = dnd;
-            cs->adamp[t * N + k] = tr->gamma_rad / (4.0 * PPI * dnd);
+            cs->adamp[t * N + k] = (tr->gamma_rad + tr->c_el * cs->nH[k]) / (4.0 * PPI * dnd);
         }
         int na = tr->n_act;
         double *ph = malloc(sizeof(double) * (size_t)N * na * nmu * 2);
@@ -545,10 +644,38 @@ static void column_prepare(colstate *cs, double coll_scale) {
     }
 }
 
+static void prd_tables(colstate *cs, int t);
+
 static void column_release(colstate *cs) {
     free(cs->ntot); free(cs->lnr); free(cs->nstar); free(cs->C); free(cs->kbg);
     for (int t = 0; t < cs->a->n_lines; t++) free(cs->phi[t]);
     free(cs->phi); free(cs->dnuD); free(cs->adamp); free(cs->norm);
+    if (cs->rho) {
+        for (int t = 0; t < cs->a->n_lines; t++) { free(cs->rho[t]); free(cs->gII[t]); }
+        free(cs->rho); free(cs->gII);
+    }
+    free(cs->Iall);
+}
+
+/* PRD state of a prepared column: rho = 1 (CRD) and the redistribution
+ * weights of every PRD line; returns 1 if any line uses PRD. */
+static int prd_prepare(colstate *cs) {
+    const orc_atom *a = cs->a;
+    int any = 0;
+    for (int t = 0; t < a->n_lines; t++) any |= a->tr[t].prd;
+    if (!any) return 0;
+    int nl = a->n_lines;
+    cs->rho = calloc(nl, sizeof(double *));
+    cs->gII = calloc(nl, sizeof(double *));
+    for (int t = 0; t < nl; t++) {
+        if (!a->tr[t].prd) continue;
+        size_t n = (size_t)cs->N * a->tr[t].n_act;
+        cs->rho[t] = malloc(sizeof(double) * n);
+        for (size_t i = 0; i < n; i++) cs->rho[t][i] = 1.0;
+        prd_tables(cs, t);
+    }
+    cs->Iall = malloc(sizeof(double) * (size_t)a->NL * cs->nmu * 2 * cs->N);
+    return 1;
 }
 
 /* Accumulators of the preconditioned rates. */
@@ -565,8 +692,10 @@ static void transition_terms(const colstate *cs, const double *n, int t, int ja,
     (void)n;
     if (tr->kind == 0) {
         double p = cs->phi[t][(((size_t)k * tr->n_act + ja) * cs->nmu + m) * 2 + s];
+        /* emission (spontaneous and stimulated) with psi = rho phi for PRD lines */
+        double ps = cs->rho && cs->rho[t] ? p * cs->rho[t][(size_t)k * tr->n_act + ja] : p;
         double c = PH * tr->nu0 / (4.0 * PPI);
-        *Vlu = c * tr->Blu * p; *Vul = c * tr->Bul * p; *U = c * tr->Aul * p;
+        *Vlu = c * tr->Blu * p; *Vul = c * tr->Bul * ps; *U = c * tr->Aul * ps;
         *kap = 4.0 * PPI * W / (PH * tr->nu0);
     } else {
         double nu = a->nu[j];
@@ -631,7 +760,9 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
                     for (int k = 0; k < N; k++) { Ieff[k] = 0.0; psi[k] = 0.0; }
                 } else if (s == 0) {               /* downward: top to bottom */
                     double I = 0.0;
+                    double *Is = (mode == 0 && cs->Iall) ? cs->Iall + (((size_t)j * cs->nmu + m) * 2 + s) * N : NULL;
                     Ieff[0] = 0.0; psi[0] = 0.0;
+                    if (Is) Is[0] = I;
                     for (int k = 1; k < N; k++) {
                         double x = 0.5 * (chi[k - 1] + chi[k]) * (cs->z[k - 1] - cs->z[k]) / mu;
                         double e, wa, wb;
@@ -639,11 +770,14 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
                         Ieff[k] = I * e + wa * S[k - 1] + wb * etabg[k] / chi[k];
                         psi[k] = wb / chi[k];
                         I = I * e + wa * S[k - 1] + wb * S[k];
+                        if (Is) Is[k] = I;
                     }
                 } else {                           /* upward: bottom to top */
                     double dtv = 0.5 * (chi[N - 1] + chi[N - 2]) * (cs->z[N - 2] - cs->z[N - 1]);
                     double I = (dtv > 0.0) ? B[N - 1] + mu * (B[N - 1] - B[N - 2]) / dtv : B[N - 1];
+                    double *Is = (mode == 0 && cs->Iall) ? cs->Iall + (((size_t)j * cs->nmu + m) * 2 + s) * N : NULL;
                     Ieff[N - 1] = I; psi[N - 1] = 0.0;
+                    if (Is) Is[N - 1] = I;
                     for (int k = N - 2; k >= 0; k--) {
                         double x = 0.5 * (chi[k + 1] + chi[k]) * (cs->z[k] - cs->z[k + 1]) / mu;
                         double e, wa, wb;
@@ -651,6 +785,7 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
                         Ieff[k] = I * e + wa * S[k + 1] + wb * etabg[k] / chi[k];
                         psi[k] = wb / chi[k];
                         I = I * e + wa * S[k + 1] + wb * S[k];
+                        if (Is) Is[k] = I;
                     }
                 }
                 /* accumulation */
@@ -681,6 +816,129 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
     }
     free(chi); free(eta); free(S); free(etabg); free(B); free(Ieff); free(psi);
     free(Vlu); free(Vul); free(U); free(kap); free(chit); free(act); free(jact);
+}
+
+/* ------------------------------------------------------------------ */
+/* partial frequency redistribution                                     */
+/* ------------------------------------------------------------------ */
+static int prd_on(const colstate *cs, int t) { return cs->rho && cs->rho[t]; }
+
+/* Redistribution weights of PRD line t at every depth point:
+ * g(j', j) = w_j' R_II(x_j', x_j) / sum_j'' w_j'' R_II(x_j'', x_j), x the
+ * rest-frame frequency offset in Doppler widths of the point, w the
+ * line's trapezoid frequency weights.  With these weights a constant
+ * mean intensity is redistributed into itself exactly. */
+static void prd_tables(colstate *cs, int t) {
+    const orc_atom *a = cs->a;
+    const orc_trans *tr = &a->tr[t];
+    int N = cs->N, na = tr->n_act;
+    double *g = malloc(sizeof(double) * (size_t)N * na * na);
+    double *x = malloc(sizeof(double) * na), *R = malloc(sizeof(double) * na * na);
+    for (int k = 0; k < N; k++) {
+        double dnd = cs->dnuD[t * N + k], ad = cs->adamp[t * N + k];
+        for (int j = 0; j < na; j++) x[j] = (a->nu[tr->act[j]] - tr->nu0) / dnd;
+        for (int j = 0; j < na; j++)
+            for (int j2 = 0; j2 <= j; j2++) R[j * na + j2] = R[j2 * na + j] = orc_rII(ad, x[j], x[j2]);
+        for (int j = 0; j < na; j++) {
+            double sum = 0.0;
+            for (int j2 = 0; j2 < na; j2++) sum += tr->wnu[j2] * R[j2 * na + j];
+            for (int j2 = 0; j2 < na; j2++) g[((size_t)k * na + j) * na + j2] = tr->wnu[j2] * R[j2 * na + j] / sum;
+        }
+    }
+    free(x); free(R);
+    cs->gII[t] = g;
+}
+
+/* Actual radiative rate coefficients of transition t at depth k with the
+ * intensities of the last sweep: upward (per particle in l) and downward
+ * (per particle in u), emission with the current rho. */
+static void actual_rates(const colstate *cs, int t, int k, double *up, double *down) {
+    const orc_atom *a = cs->a;
+    const orc_trans *tr = &a->tr[t];
+    int N = cs->N;
+    double ru = 0.0, rd = 0.0;
+    for (int ja = 0; ja < tr->n_act; ja++) {
+        int j = tr->act[ja];
+        for (int m = 0; m < cs->nmu; m++) for (int s = 0; s < 2; s++) {
+            double Vlu, Vul, U, kap;
+            transition_terms(cs, NULL, t, ja, j, m, s, k, &Vlu, &Vul, &U, &kap);
+            double I = cs->Iall[(((size_t)j * cs->nmu + m) * 2 + s) * N + k];
+            ru += kap * Vlu * I;
+            rd += kap * (U + Vul * I);
+        }
+    }
+    *up = ru; *down = rd;
+}
+
+/* rho update of every PRD line after iteration `it` (Uitenbroek 2001,
+ * angle-averaged PRD; the emission profile of a line whose upper level u
+ * is populated partly by coherent scattering), from the intensities of the
+ * iteration's formal solution and the new populations n:
+ *   rho(j) = 1 + gamma n_l B_lu / (n_u P_u) [sum_j' g(j', j) J(j') - Jbar],
+ * J(j') = sum over angles and directions of (w_mu / 2) I, Jbar the
+ * profile-weighted mean intensity sum_rays W phi I, P_u the total rate out
+ * of u (radiative with the sweep's intensities and the current rho, plus
+ * collisional with factor cf), gamma = P_u / (P_u + Q_E) the coherent
+ * fraction, Q_E = c_el n_H.  Then PRD switching (Sec. 2.3, Eq. 1):
+ * rho' = rho eps + (1 - eps), eps = min(1, eps0 it^2) (eps0 <= 0: 1);
+ * negative rho' count as 0; and rho' is normalised so that
+ * sum_rays W phi rho' = 1 (the emission profile integrates to 1, as the
+ * absorption profile does). */
+static void prd_update(colstate *cs, const double *n, int it, double eps0, double cf) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L, T = a->T;
+    double eps = 1.0;
+    if (eps0 > 0.0) { eps = eps0 * (double)it * (double)it; if (eps > 1.0) eps = 1.0; }
+    double **newrho = calloc(a->n_lines ? a->n_lines : 1, sizeof(double *));
+    for (int t = 0; t < a->n_lines; t++) {
+        if (!prd_on(cs, t)) continue;
+        const orc_trans *tr = &a->tr[t];
+        int na = tr->n_act, u = tr->u, l = tr->l;
+        double *nr = malloc(sizeof(double) * (size_t)N * na), *J = malloc(sizeof(double) * na);
+        for (int k = 0; k < N; k++) {
+            /* total rate out of the upper level */
+            double Pu = 0.0;
+            for (int t2 = 0; t2 < T; t2++) {
+                if (a->tr[t2].u != u && a->tr[t2].l != u) continue;
+                double up, down;
+                actual_rates(cs, t2, k, &up, &down);
+                Pu += (a->tr[t2].u == u) ? down : up;
+            }
+            for (int i = 0; i < L; i++) if (i != u) Pu += cs->C[(k * L + u) * L + i] * cf;
+            double gam = Pu / (Pu + tr->c_el * cs->nH[k]);
+            double nl = n[k * L + l], nu = n[k * L + u];
+            double fac = gam * nl * tr->Blu / (nu * Pu);
+            /* angle-averaged and profile-weighted mean intensities */
+            double Jbar = 0.0;
+            for (int ja = 0; ja < na; ja++) {
+                int j = tr->act[ja];
+                J[ja] = 0.0;
+                for (int m = 0; m < cs->nmu; m++) for (int s = 0; s < 2; s++) {
+                    double I = cs->Iall[(((size_t)j * cs->nmu + m) * 2 + s) * N + k];
+                    J[ja] += 0.5 * cs->wmu[m] * I;
+                    Jbar += tr->wnu[ja] * 0.5 * cs->wmu[m] * cs->phi[t][(((size_t)k * na + ja) * cs->nmu + m) * 2 + s] * I;
+                }
+            }
+            double norm = 0.0;
+            for (int ja = 0; ja < na; ja++) {
+                double sJ = 0.0;
+                for (int j2 = 0; j2 < na; j2++) sJ += cs->gII[t][((size_t)k * na + ja) * na + j2] * J[j2];
+                double r = isfinite(fac) ? 1.0 + fac * (sJ - Jbar) : 1.0;
+                r = r * eps + (1.0 - eps);
+                if (!(r > 0.0)) r = 0.0;
+                nr[(size_t)k * na + ja] = r;
+                for (int m = 0; m < cs->nmu; m++) for (int s = 0; s < 2; s++)
+                    norm += tr->wnu[ja] * 0.5 * cs->wmu[m] * cs->phi[t][(((size_t)k * na + ja) * cs->nmu + m) * 2 + s] * r;
+            }
+            for (int ja = 0; ja < na; ja++) nr[(size_t)k * na + ja] /= norm;
+        }
+        free(J);
+        newrho[t] = nr;
+    }
+    /* every line's rates above used the previous rho: replace them only now */
+    for (int t = 0; t < a->n_lines; t++)
+        if (newrho[t]) { free(cs->rho[t]); cs->rho[t] = newrho[t]; }
+    free(newrho);
 }
 
 /* Statistical equilibrium at every depth; returns 0 or -1 on a singular system. */
@@ -749,8 +1007,14 @@ static void emergent(const colstate *cs, const double *n, double *spec) {
                 double Vlu, Vul, U;
                 if (tr->kind == 0) {
                     double p = line_profile(a, t, cs, k, nu, 1.0) / cs->norm[t * N + k];
+                    double ps = p;
+                    if (cs->rho && cs->rho[t]) {
+                        int ja = 0;
+                        while (tr->act[ja] != j) ja++;
+                        ps = p * cs->rho[t][(size_t)k * tr->n_act + ja];
+                    }
                     double cc = PH * tr->nu0 / (4.0 * PPI);
-                    Vlu = cc * tr->Blu * p; Vul = cc * tr->Bul * p; U = cc * tr->Aul * p;
+                    Vlu = cc * tr->Blu * p; Vul = cc * tr->Bul * ps; U = cc * tr->Aul * ps;
                 } else {
                     double alpha = tr->alpha0 * pow(tr->nu0 / nu, 3.0);
                     double G = exp(cs->lnr[k * L + tr->l] - cs->lnr[k * L + tr->u]) * exp(-PH * nu / (PKB * cs->T[k]));
@@ -889,14 +1153,15 @@ static int escape_start(const colstate *cs, const rates *zr, int n_it, double *n
 
 /* Solve one column.  Arrays of the column: N points, top first.
  * Outputs (any may be NULL except pops): pops[N][L], history[max_iter],
- * spectrum[NL], psi_star[T][N]; n_iter and status scalars.
+ * spectrum[NL], psi_star[T][N], prd_rho (the final rho of every PRD line,
+ * in line order, [N][n_act] each); n_iter and status scalars.
  * status: 0 converged, 1 iteration limit, 2 non-finite or non-positive
  * populations, 3 singular rate matrix, 4 invalid column data (outputs
  * NaN, no iteration). */
 int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
                      const double *nH, const double *vz, const double *vt, const double *init_pops,
                      const orc_opts *o, double *pops, double *history, int *n_iter, int *status,
-                     double *spectrum, double *psi_star) {
+                     double *spectrum, double *psi_star, double *prd_rho) {
     if (N < 2) FAIL(-3, "need at least 2 depth points");
     if (o->n_mu < 1 || o->n_mu > 16) FAIL(-3, "n_mu out of range");
     if (o->ng_order != 0 && o->ng_order != 2) FAIL(-3, "only Ng order 2 (or 0 = off) is implemented");
@@ -914,6 +1179,7 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
     cs.mu = malloc(sizeof(double) * o->n_mu); cs.wmu = malloc(sizeof(double) * o->n_mu);
     orc_gauss_legendre(o->n_mu, cs.mu, cs.wmu);
     column_prepare(&cs, o->coll_scale > 0 ? o->coll_scale : 1.0);
+    const int prd = o->prd ? prd_prepare(&cs) : 0;
     int L = a->L, Tn = a->T, NV = N * L;
     rates R;
     R.P = malloc(sizeof(double) * (Tn ? Tn : 1) * N); R.Q = malloc(sizeof(double) * (Tn ? Tn : 1) * N);
@@ -973,6 +1239,8 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
                 ng_count = 0;
             }
         }
+        /* PRD: rho from this iteration's radiation field and the new populations */
+        if (prd) prd_update(&cs, n, it, o->prd_eps0, cf);
     }
     if (it > o->max_iter) it = o->max_iter;
     *n_iter = it;
@@ -980,6 +1248,13 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
     memcpy(pops, n, sizeof(double) * NV);
     if (spectrum) emergent(&cs, n, spectrum);
     if (psi_star) sweep(&cs, n, 2, NULL, psi_star);
+    if (prd_rho && prd)
+        for (int t = 0; t < a->n_lines; t++)
+            if (cs.rho[t]) {
+                size_t m = (size_t)N * a->tr[t].n_act;
+                memcpy(prd_rho, cs.rho[t], sizeof(double) * m);
+                prd_rho += m;
+            }
     for (int i = 0; i < 8; i++) free(ring[i]);
     free(n); free(nse); free(R.P); free(R.Q); free(R.X);
     column_release(&cs);
@@ -1015,6 +1290,32 @@ int orc_column_damping(const orc_atom *a, int N, const double *z, const double *
     column_prepare(&cs, 1.0);
     if (dnuD) memcpy(dnuD, cs.dnuD, sizeof(double) * N * a->n_lines);
     if (adamp) memcpy(adamp, cs.adamp, sizeof(double) * N * a->n_lines);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return 0;
+}
+
+/* One rho update of a prepared column with every ray's intensity set to
+ * I_const, populations pops and switching (eps0, it); rho of the PRD lines
+ * out as in orc_solve_column (tests only). */
+int orc_column_prd_rho(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                       const double *nH, const double *vz, const double *vt, int n_mu, const double *pops,
+                       double I_const, double eps0, int it, double *rho_out) {
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * n_mu); cs.wmu = malloc(sizeof(double) * n_mu);
+    orc_gauss_legendre(n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    if (!prd_prepare(&cs)) { column_release(&cs); free(cs.mu); free(cs.wmu); FAIL(-3, "no PRD line"); }
+    size_t nI = (size_t)a->NL * n_mu * 2 * N;
+    for (size_t i = 0; i < nI; i++) cs.Iall[i] = I_const;
+    prd_update(&cs, pops, it, eps0, 1.0);
+    for (int t = 0; t < a->n_lines; t++)
+        if (cs.rho[t]) {
+            size_t m = (size_t)N * a->tr[t].n_act;
+            memcpy(rho_out, cs.rho[t], sizeof(double) * m);
+            rho_out += m;
+        }
     column_release(&cs);
     free(cs.mu); free(cs.wmu);
     return 0;

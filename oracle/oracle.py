@@ -56,7 +56,11 @@ def lib():
         L.orc_sc_coefficients.argtypes = [C.c_double, dp, dp, dp]
         L.orc_formal_ray.argtypes = [C.c_int, dp, dp, C.c_double, dp, dp]
         L.orc_lte_populations.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, dp]
-        L.orc_solve_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 7 + [C.c_void_p, dp, dp, ip, ip, dp, dp]
+        L.orc_solve_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 7 + [C.c_void_p, dp, dp, ip, ip, dp, dp, dp]
+        L.orc_rII.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_rII.restype = C.c_double
+        L.orc_column_prd_rho.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, C.c_double, C.c_double,
+                                                                            C.c_int, dp]
         L.orc_crs_factor.argtypes = [C.c_double, C.c_int]
         L.orc_crs_factor.restype = C.c_double
         L.orc_ng_step.argtypes = [C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_double)), dp]
@@ -73,7 +77,8 @@ def _p(a):
 class _Opts(C.Structure):
     _fields_ = [("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int), ("ng_order", C.c_int),
                 ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int), ("coll_scale", C.c_double),
-                ("crs_f0", C.c_double), ("tol_fp", C.c_double), ("esc_iter", C.c_int)]
+                ("crs_f0", C.c_double), ("tol_fp", C.c_double), ("esc_iter", C.c_int), ("prd", C.c_int),
+                ("prd_eps0", C.c_double)]
 
 
 class Atom:
@@ -169,6 +174,35 @@ def column_damping(atom: Atom, col: dict):
     return dnd[: atom.n_lines], ad[: atom.n_lines]
 
 
+def rII(a: float, x: float, x2: float) -> float:
+    """Angle-averaged R_II(x, x2) in Doppler units (the oracle's quadrature)."""
+    return lib().orc_rII(float(a), float(x), float(x2))
+
+
+def prd_line_sizes(atom: Atom, prd_lines) -> list:
+    """(line index, number of active wavelengths) of the given PRD lines."""
+    return [(t, len(atom.transition(t)["act"])) for t in prd_lines]
+
+
+def prd_rho_constant_field(atom: Atom, col: dict, n_mu: int, pops, I_const: float, prd_lines, eps0=0.0, it=1):
+    """One rho update with every ray's intensity I_const: rho per PRD line,
+    a list of [N][n_act] arrays."""
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    sizes = prd_line_sizes(atom, prd_lines)
+    out = np.empty(sum(N * n for _, n in sizes))
+    pops = np.ascontiguousarray(pops, dtype=np.float64)
+    rc = lib().orc_column_prd_rho(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                  n_mu, _p(pops), float(I_const), float(eps0), int(it), _p(out))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    res, o = [], 0
+    for _, n in sizes:
+        res.append(out[o:o + N * n].reshape(N, n))
+        o += N * n
+    return res
+
+
 def crs_factor(f0: float, it: int) -> float:
     """Collision factor of iteration it under collisional-radiative switching."""
     return lib().orc_crs_factor(f0, it)
@@ -177,10 +211,14 @@ def crs_factor(f0: float, it: int) -> float:
 def solve_column(atom: Atom, col: dict, n_mu: int = 5, tol: float = 1e-4, max_iter: int = 200,
                  ng_order: int = 2, ng_delay: int = 5, ng_period: int = 4, start: int = START_LTE,
                  coll_scale: float = 1.0, init_pops=None, want_spectrum: bool = True,
-                 want_psi: bool = False, crs_f0: float = 1.0, tol_fp: float = 0.0, esc_iter: int = 3) -> dict:
+                 want_psi: bool = False, crs_f0: float = 1.0, tol_fp: float = 0.0, esc_iter: int = 3,
+                 prd: int = 0, prd_eps0: float = 0.0, prd_lines=()) -> dict:
     N = len(col["z"])
     cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
-    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale, crs_f0, tol_fp, esc_iter)
+    o = _Opts(n_mu, tol, max_iter, ng_order, ng_delay, ng_period, start, coll_scale, crs_f0, tol_fp, esc_iter, prd,
+              prd_eps0)
+    sizes = prd_line_sizes(atom, prd_lines) if prd else []
+    rho = np.empty(max(1, sum(N * n for _, n in sizes)))
     pops = np.empty((N, atom.n_levels))
     hist = np.empty(max(max_iter, 1))
     spec = np.empty(atom.n_lambda) if want_spectrum else None
@@ -191,11 +229,17 @@ def solve_column(atom: Atom, col: dict, n_mu: int = 5, tol: float = 1e-4, max_it
     n_iter, status = C.c_int(), C.c_int()
     rc = lib().orc_solve_column(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
                                 _p(ip), C.byref(o), _p(pops), _p(hist), C.byref(n_iter), C.byref(status),
-                                _p(spec), _p(psi))
+                                _p(spec), _p(psi), _p(rho) if sizes else None)
     if rc != 0:
         raise ValueError(lib().orc_last_error().decode())
-    return dict(pops=pops, history=hist[:max_iter], n_iter=n_iter.value, status=status.value, spectrum=spec,
-                psi_star=psi)
+    out = dict(pops=pops, history=hist[:max_iter], n_iter=n_iter.value, status=status.value, spectrum=spec,
+               psi_star=psi)
+    if sizes:
+        o2, out["rho"] = 0, []
+        for _, n in sizes:
+            out["rho"].append(rho[o2:o2 + N * n].reshape(N, n))
+            o2 += N * n
+    return out
 
 
 def solve_columns(atom: Atom, columns, threads: int | None = None, **kw) -> list:

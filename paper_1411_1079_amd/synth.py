@@ -32,8 +32,14 @@ Atom text format (whitespace separated, '#' starts a comment)::
     CONTINUA <n>
       <l> <u> <alpha_edge [m^2]> <OMEGA|EPS> <value> <n_lambda>
       <n_lambda wavelengths [nm]>
+    ELASTIC <n>                       # optional section
+      <line index> <c_el [m^3 s^-1]> <PRD|CRD>
     BACKGROUND NONE | HMINUS <C_bg>
     END
+
+ELASTIC lists lines with elastic collisions (rate c_el n_H, which adds to
+the line's damping width) and whether their emission follows partial
+frequency redistribution; lines not listed have neither.
 """
 from __future__ import annotations
 
@@ -121,11 +127,12 @@ def continuum_grid_nm(edge_nm: float, n: int = 20) -> np.ndarray:
     return _C / nu * 1e9
 
 
-def write_atom(path, name, mass_amu, abundance, levels, lines, continua, background):
+def write_atom(path, name, mass_amu, abundance, levels, lines, continua, background, elastic=None):
     """Write an atom file. levels: [(E_eV, g, stage)]; lines: dicts with
     l, u, f, profile (GAUSS|VOIGT), coll (OMEGA|EPS), cval, lam [nm];
     continua: dicts with l, u, alpha [m^2], coll, cval, lam [nm];
-    background: None or the C_bg of the H-minus-like law."""
+    background: None or the C_bg of the H-minus-like law; elastic: None or
+    [(line index, c_el [m^3 s^-1], "PRD" | "CRD")]."""
     out = ["RH15D-ATOM 1", f"NAME {name}", f"MASS_AMU {_fmt(mass_amu)}", f"ABUNDANCE {_fmt(abundance)}",
            f"LEVELS {len(levels)}", "#  E[eV]  g  stage"]
     for E, g, st in levels:
@@ -140,6 +147,10 @@ def write_atom(path, name, mass_amu, abundance, levels, lines, continua, backgro
     for ct in continua:
         out.append(f"  {ct['l']} {ct['u']} {_fmt(ct['alpha'])} {ct['coll']} {_fmt(ct['cval'])} {len(ct['lam'])}")
         out.append("    " + " ".join(_fmt(v) for v in ct["lam"]))
+    if elastic:
+        out.append(f"ELASTIC {len(elastic)}")
+        for li, c, kind in elastic:
+            out.append(f"  {int(li)} {_fmt(c)} {kind}")
     if background is None:
         out.append("BACKGROUND NONE")
     else:
@@ -205,6 +216,46 @@ def write_h6_atom(path: str, c_bg: float | None) -> str:
         conts.append(dict(l=n - 1, u=5, alpha=7.91e-22 * n, coll="OMEGA", cval=0.1,
                           lam=np.sort(continuum_grid_nm(edge))))
     return write_atom(path, "H6", 1.00794, 1.0, lev, lines, conts, c_bg)
+
+
+# Ca II-like atom: 4s 2S, 3d 2D (one level), 4p 2P1/2, 4p 2P3/2 and the
+# Ca III ground state; rounded synthetic data with the right structure, not
+# a laboratory atom.
+CA_LEVELS = [(0.0, 2.0, 0), (1.697, 10.0, 0), (3.123, 2.0, 0), (3.151, 4.0, 0), (11.871, 1.0, 1)]
+CA_LINES = [  # (l, u, f, PRD)
+    (0, 3, 0.68, True),     # K-like resonance line
+    (0, 2, 0.33, True),     # H-like resonance line
+    (1, 3, 0.06, False),    # infrared lines from the metastable level
+    (1, 2, 0.03, False),
+    (0, 1, 1.0e-8, False),  # weak forbidden-like line
+]
+CA_MASS_AMU = 40.078
+CA_ABUNDANCE = 2.2e-6
+CA_C_ELASTIC = 1.0e-14      # m^3 s^-1: Q_E = 1e9 s^-1 at n_H = 1e23 m^-3
+
+
+def write_ca_atom(path: str, c_bg: float | None, n_prd: int = 61, n_crd: int = 41, n_forbidden: int = 21,
+                  n_cont: int = 190, prd: bool = True) -> str:
+    """Five-level Ca II-like atom: two resonance lines with partial
+    frequency redistribution (n_prd wavelengths each, sinh grid over +-300
+    km/s), two infrared lines and a weak forbidden line with complete
+    redistribution, Voigt profiles, elastic collisions on the four strong
+    lines, and four bound-free continua (n_cont wavelengths each): about
+    1000 wavelengths with the defaults.  prd=False writes the same atom
+    with every line in complete redistribution."""
+    lines, conts, el = [], [], []
+    for i, (l, u, f, is_prd) in enumerate(CA_LINES):
+        dE = (CA_LEVELS[u][0] - CA_LEVELS[l][0]) * _EV
+        lam0 = _H * _C / dE * 1e9
+        n = n_prd if is_prd else (n_forbidden if f < 1e-6 else n_crd)
+        lines.append(dict(l=l, u=u, f=f, profile="VOIGT", coll="OMEGA", cval=1.0, lam=line_grid_nm(lam0, n=n)))
+        if f > 1e-6:
+            el.append((i, CA_C_ELASTIC, "PRD" if (is_prd and prd) else "CRD"))
+    for lo, alpha in ((0, 2.0e-22), (1, 6.0e-22), (2, 2.0e-22), (3, 2.0e-22)):
+        dE = (CA_LEVELS[4][0] - CA_LEVELS[lo][0]) * _EV
+        edge = _H * _C / dE * 1e9
+        conts.append(dict(l=lo, u=4, alpha=alpha, coll="OMEGA", cval=0.1, lam=np.sort(continuum_grid_nm(edge, n=n_cont))))
+    return write_atom(path, "CA2", CA_MASS_AMU, CA_ABUNDANCE, CA_LEVELS, lines, conts, c_bg, elastic=el)
 
 
 # ----------------------------------------------------------------------------
@@ -391,11 +442,15 @@ def cube_columns(seed: int, nx: int = 256, ny: int = 256, nz: int = CUBE_NZ, cor
 
 
 def write_atoms(directory: str) -> dict:
-    """Write the two model atoms and return their paths."""
+    """Write the model atoms and return their paths (ca2_crd: the Ca II-like
+    atom with every line in complete redistribution)."""
     os.makedirs(directory, exist_ok=True)
+    c_bg = hminus_calibration()
     return {
         "two_level": write_two_level_atom(os.path.join(directory, "two_level.atom")),
-        "h6": write_h6_atom(os.path.join(directory, "h6.atom"), hminus_calibration()),
+        "h6": write_h6_atom(os.path.join(directory, "h6.atom"), c_bg),
+        "ca2": write_ca_atom(os.path.join(directory, "ca2.atom"), c_bg),
+        "ca2_crd": write_ca_atom(os.path.join(directory, "ca2_crd.atom"), c_bg, prd=False),
     }
 
 

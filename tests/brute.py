@@ -67,7 +67,15 @@ class BAtom:
             d = dict(kind=1, l=int(nxt()), u=int(nxt()), alpha=float(nxt()), coll=nxt(), cval=float(nxt()))
             n = int(nxt()); d["lam"] = np.array([float(nxt()) for _ in range(n)]) * 1e-9
             self.tr.append(d)
-        assert nxt() == "BACKGROUND"
+        for d in self.tr:
+            d["c_el"], d["prd"] = 0.0, False
+        w = nxt()
+        if w == "ELASTIC":
+            for _ in range(int(nxt())):
+                li, c, kind = int(nxt()), float(nxt()), nxt()
+                self.tr[li]["c_el"], self.tr[li]["prd"] = c, kind == "PRD"
+            w = nxt()
+        assert w == "BACKGROUND"
         b = nxt()
         self.c_bg = float(nxt()) if b == "HMINUS" else 0.0
         for d in self.tr:
@@ -163,7 +171,7 @@ class Problem:
             ph = np.zeros((self.N, len(self.rays)))
             for k in range(self.N):
                 dnd = d["nu0"] / C * math.sqrt(2 * KB * T[k] / atom.mass + col["v_turb"][k] ** 2)
-                adamp = damping_scale * atom.damping(ti) / (4 * math.pi * dnd)
+                adamp = damping_scale * (atom.damping(ti) + d["c_el"] * col["n_H"][k]) / (4 * math.pi * dnd)
                 tot = 0.0
                 for r, (j, m, s) in enumerate(self.rays):
                     if j not in d["act"]:
@@ -188,6 +196,85 @@ class Problem:
                 self.C[k, l, u] += Cul * self.nstar[k, u] / self.nstar[k, l]
                 self.C[k, u, l] += Cul
 
+    # ---------------------------------------------------------------- PRD
+    rho = None      # {line index: [N][n_act]} emission / absorption profile ratio, None: CRD
+
+    def rho_at(self, ti, k, j):
+        if not self.rho or ti not in self.rho:
+            return 1.0
+        ja = int(np.nonzero(self.a.tr[ti]["act"] == j)[0][0])
+        return self.rho[ti][k, ja]
+
+    @staticmethod
+    def hummer_rII(a, x, x2):
+        """R_II-A of Hummer (1962) from its defining integral,
+        pi^-3/2 int_{(xb - xs)/2}^inf exp(-u^2) [atan((xs + u)/a) - atan((xb - u)/a)] du
+        (xb, xs the larger and smaller of x, x2), by adaptive quadrature."""
+        from scipy.integrate import quad
+        xb, xs = max(x, x2), min(x, x2)
+        u0 = 0.5 * (xb - xs)
+        f = lambda u: math.exp(-u * u) * (math.atan((xs + u) / a) - math.atan((xb - u) / a))
+        pts = [p for p in (xb,) if p > u0]
+        hi = max(u0, xb) + 9.0
+        v1, _ = quad(f, u0, hi, points=pts or None, limit=400, epsabs=0, epsrel=1e-12)
+        return v1 / math.pi ** 1.5
+
+    def prd_rho(self, n, eps=1.0):
+        """rho of every PRD line for populations n and the exact radiation
+        field of the current rho (emission profile of a line whose upper level
+        is partly populated by coherent scattering, angle-averaged R_II),
+        switched by eps and normalised so that sum W phi rho = 1."""
+        a, N, L = self.a, self.N, self.a.L
+        T = self.col["T"]
+        Ir = {}
+        for r in range(len(self.rays)):
+            if self.active(r):
+                Ir[r] = self.intensity(r, n)
+        out = {}
+        for ti, d in enumerate(a.tr):
+            if d["kind"] != 0 or not d["prd"]:
+                continue
+            l, u, act = d["l"], d["u"], d["act"]
+            na = len(act)
+            rho = np.zeros((N, na))
+            for k in range(N):
+                Pu = sum(self.C[k, u, i] for i in range(L) if i != u)
+                for t2, d2 in enumerate(a.tr):
+                    if d2["u"] != u and d2["l"] != u:
+                        continue
+                    for r, I in Ir.items():
+                        if self.weight(t2, r) == 0.0:
+                            continue
+                        Vlu, Vul, U, kap = self.terms(t2, r, k)
+                        Pu += kap * (U + Vul * I[k]) if d2["u"] == u else kap * Vlu * I[k]
+                dnd = d["nu0"] / C * math.sqrt(2 * KB * T[k] / a.mass + self.col["v_turb"][k] ** 2)
+                ad = (a.damping(ti) + d["c_el"] * self.col["n_H"][k]) / (4 * math.pi * dnd)
+                x = (a.nu[act] - d["nu0"]) / dnd
+                J = np.zeros(na)
+                Jbar = 0.0
+                for r, I in Ir.items():
+                    j, m, s_ = self.rays[r]
+                    if j not in act:
+                        continue
+                    ja = int(np.nonzero(act == j)[0][0])
+                    J[ja] += 0.5 * self.wmu[m] * I[k]
+                    Jbar += self.weight(ti, r) * self.phi[ti][k, r] * I[k]
+                R = np.array([[self.hummer_rII(ad, x[i], x[i2]) for i2 in range(na)] for i in range(na)])
+                gam = Pu / (Pu + d["c_el"] * self.col["n_H"][k])
+                fac = gam * n[k, l] * d["Blu"] / (n[k, u] * Pu)
+                for ja in range(na):
+                    g = d["w"] * R[:, ja]
+                    rr = 1.0 + fac * (g @ J / g.sum() - Jbar)
+                    rho[k, ja] = max(rr * eps + (1.0 - eps), 0.0)
+                norm = 0.0
+                for r in Ir:
+                    j, m, s_ = self.rays[r]
+                    if j in act:
+                        norm += self.weight(ti, r) * self.phi[ti][k, r] * rho[k, int(np.nonzero(act == j)[0][0])]
+                rho[k] /= norm
+            out[ti] = rho
+        return out
+
     def weight(self, ti, r):
         j, m, s = self.rays[r]
         d = self.a.tr[ti]
@@ -202,8 +289,9 @@ class Problem:
         W = self.weight(ti, r)
         if d["kind"] == 0:
             p = self.phi[ti][k, r]
+            ps = p * self.rho_at(ti, k, j)
             c = H * d["nu0"] / (4 * math.pi)
-            return c * d["Blu"] * p, c * d["Bul"] * p, c * d["A"] * p, 4 * math.pi * W / (H * d["nu0"])
+            return c * d["Blu"] * p, c * d["Bul"] * ps, c * d["A"] * ps, 4 * math.pi * W / (H * d["nu0"])
         T = self.col["T"][k]
         alpha = d["alpha"] * (d["nu0"] / nu) ** 3
         G = self.nstar[k, d["l"]] / self.nstar[k, d["u"]] * math.exp(-H * nu / (KB * T))
@@ -375,10 +463,11 @@ class Problem:
                     if d["kind"] == 0:
                         dnd = d["nu0"] / C * math.sqrt(2 * KB * T[k] / a.mass + self.col["v_turb"][k] ** 2)
                         v = (nu - d["nu0"] * (1 + self.col["v_z"][k] / C)) / dnd
-                        adamp = self.damping_scale * a.damping(ti) / (4 * math.pi * dnd)
+                        adamp = self.damping_scale * (a.damping(ti) + d["c_el"] * self.col["n_H"][k]) / (4 * math.pi * dnd)
                         p = _profile_H(d["profile"], adamp, v) / (math.sqrt(math.pi) * dnd) / self.norm[ti][k]
+                        ps = p * self.rho_at(ti, k, j)
                         c = H * d["nu0"] / (4 * math.pi)
-                        Vlu, Vul, U = c * d["Blu"] * p, c * d["Bul"] * p, c * d["A"] * p
+                        Vlu, Vul, U = c * d["Blu"] * p, c * d["Bul"] * ps, c * d["A"] * ps
                     else:
                         alpha = d["alpha"] * (d["nu0"] / nu) ** 3
                         G = self.nstar[k, d["l"]] / self.nstar[k, d["u"]] * math.exp(-H * nu / (KB * T[k]))

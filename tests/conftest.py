@@ -24,7 +24,33 @@ def atom_dir(tmp_path_factory):
     paths["tiny_nobg"] = write_tiny_atom(os.path.join(str(d), "tiny_nobg.atom"), c_bg=None)
     paths["tiny_voigt"] = write_tiny_atom(os.path.join(str(d), "tiny_voigt.atom"), profile="VOIGT", f_scale=1e6,
                                           n_line=11, x_max=30.0)
+    paths["prd_tiny"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny.atom"))
+    paths["prd_tiny_crd"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny_crd.atom"), prd=False)
+    paths["prd_tiny_gamma0"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny_gamma0.atom"), c_el=1.0e3)
+    paths["prd_tiny_gamma0_crd"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny_gamma0_crd.atom"), c_el=1.0e3,
+                                                       prd=False)
     return paths
+
+
+def write_prd_tiny_atom(path, prd=True, c_el=1.0e-16, n_line=13, x_max=6.0):
+    """Four-level atom for partial frequency redistribution on tiny grids:
+    a strong Voigt resonance line 0-1 with PRD (elastic collisions c_el
+    n_H), a weaker Voigt line 0-2 with complete redistribution, and one
+    continuum from level 0."""
+    levels = [(0.0, 2.0, 0), (3.0, 6.0, 0), (3.4, 2.0, 0), (6.5, 1.0, 1)]
+    ev = synth._EV
+    hc = synth._H * synth._C
+
+    def lam0(lo, hi):
+        return hc / ((levels[hi][0] - levels[lo][0]) * ev) * 1e9
+
+    lines = [dict(l=0, u=1, f=0.5, profile="VOIGT", coll="OMEGA", cval=1.0,
+                  lam=synth.line_grid_nm(lam0(0, 1), n=n_line, x_max=x_max)),
+             dict(l=0, u=2, f=0.05, profile="VOIGT", coll="OMEGA", cval=1.0,
+                  lam=synth.line_grid_nm(lam0(0, 2), n=7, x_max=3.0))]
+    conts = [dict(l=0, u=3, alpha=1e-22, coll="OMEGA", cval=0.1, lam=np.sort(synth.continuum_grid_nm(lam0(0, 3), n=4)))]
+    el = [(0, c_el, "PRD" if prd else "CRD")]
+    return synth.write_atom(path, "PRDTINY", TINY_MASS, 1.0, levels, lines, conts, 1.0e-38, elastic=el)
 
 
 TINY_MASS = 1.00794
@@ -74,14 +100,19 @@ def oracle_lockstep_rtol(atom, col, floor=1e-10, **kw):
     input temperatures are perturbed by about one unit in the last place,
     whichever is larger.  Columns whose iteration amplifies rounding (Ng
     steps on nearly parallel iterates, weak collisions) cannot be reproduced
-    by any other summation order more closely than that."""
+    by any other summation order more closely than that.  The column must
+    be stable: the perturbation may not change the oracle's iteration count
+    (such a column is no parity case), and the tolerance may not exceed
+    1e-8; the value used is printed."""
     from oracle import oracle as O
     r = O.solve_column(atom, col, want_psi=True, **kw)
     c2 = dict(col)
     c2["T"] = col["T"] * (1.0 + 2e-16 * np.cos(np.arange(len(col["T"]))))
     r2 = O.solve_column(atom, c2, want_psi=True, **kw)
-    if r2["n_iter"] != r["n_iter"]:
-        return r, 1e-6
+    assert r2["n_iter"] == r["n_iter"], "the oracle's iteration count is not stable under a 1-ulp perturbation"
     s = max(float(np.max(np.abs(r2["pops"] / r["pops"] - 1.0))),
             float(np.max(np.abs(r2["spectrum"] / r["spectrum"] - 1.0))))
-    return r, max(floor, 10.0 * s)
+    rtol = max(floor, 10.0 * s)
+    print(f"[lockstep] n_iter={r['n_iter']} rtol={rtol:.2e}", flush=True)
+    assert rtol <= 1e-8, rtol
+    return r, rtol

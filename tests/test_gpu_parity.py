@@ -141,32 +141,50 @@ def test_chunking_and_determinism(atom_dir):
 
 
 def test_fp32_precision_form(atom_dir):
-    """Formal solution and rate accumulation in FP32, converged to 1e-4
-    maximum relative change: within 1e-3 of the FP64 oracle under the same
-    stopping rule, and within 1e-3 of the oracle converged to 1e-10 on every
-    column where the stopping rule itself is that accurate (the FP64 oracle
-    stopped at 1e-4 within 5e-4 of its 1e-10 answer; slowly converging
-    columns stop farther from the fixed point in any precision).  Two of the
-    columns have emergent intensities below the smallest normal FP32 number
-    (far-ultraviolet continuum), which the emergent ray must still give to
-    1e-3."""
+    """Formal solution and rate accumulation in FP32, stopped by the change
+    test of 1e-4 and the fixed-point bound of 2e-4: within 1e-3 of the FP64
+    oracle under the same stopping rule, and within 1e-3 of the oracle
+    converged to 1e-10, on every column (slowly converging ones included).
+    Two of the columns have emergent intensities below the smallest normal
+    FP32 number (far-ultraviolet continuum), which the emergent ray must
+    still give to 1e-3."""
     cube = synth.cube_columns(1, 64, 64)
     cube12 = synth.cube_columns(12, 64, 64)
     cols = synth.Columns.from_list([synth.cfg2_columns(seed=0, n_columns=3).column(c) for c in range(3)] +
-                                   [cube.column(c) for c in (90, 200)] + [cube12.column(c) for c in (0, 5)])
-    g = gpu_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-4, max_iter=100, precision=1)
-    same = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-4, max_iter=100)
-    conv = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-10, max_iter=300)
+                                   [cube.column(c) for c in (90, 200, 686, 818)] +
+                                   [cube12.column(c) for c in (0, 5)])
+    kw = dict(n_mu=5, tol=1e-4, tol_fp=2e-4, max_iter=200)
+    g = gpu_solve(atom_dir["h6"], cols, precision=1, **kw)
+    same = oracle_solve(atom_dir["h6"], cols, **kw)
+    conv = oracle_solve(atom_dir["h6"], cols, n_mu=5, tol=1e-10, max_iter=400)
     assert min(r["spectrum"].min() for r in conv) < np.finfo(np.float32).tiny
-    n_conv = 0
     for c, (r, rc) in enumerate(zip(same, conv)):
         a, b = int(cols.offset[c]), int(cols.offset[c + 1])
         assert g["status"][c] == 0
-        np.testing.assert_allclose(g["pops"][a:b], r["pops"], rtol=1e-3)
-        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-3)
-        stop_err = max(np.max(np.abs(r["pops"] / rc["pops"] - 1)), np.max(np.abs(r["spectrum"] / rc["spectrum"] - 1)))
-        if stop_err < 5e-4:
-            n_conv += 1
-            np.testing.assert_allclose(g["pops"][a:b], rc["pops"], rtol=1e-3)
-            np.testing.assert_allclose(g["spectrum"][c], rc["spectrum"], rtol=1e-3)
-    assert n_conv >= cols.n_columns - 2
+        for ref in (r, rc):
+            np.testing.assert_allclose(g["pops"][a:b], ref["pops"], rtol=1e-3, err_msg=f"column {c}")
+            np.testing.assert_allclose(g["spectrum"][c], ref["spectrum"], rtol=1e-3, err_msg=f"column {c}")
+
+
+def test_fp32_precision_error_at_fixed_iterations(atom_dir):
+    """The precision error alone: 256 random cube columns, the FP32 form and
+    the FP64 oracle each run exactly 24 iterations (no stopping test), so
+    both hold the same iterate; populations and emergent intensities agree
+    within 1e-3 element by element."""
+    import concurrent.futures
+    cube = synth.cube_columns(1, 64, 64)
+    picks = sorted(np.random.default_rng(3).choice(cube.n_columns, size=256, replace=False))
+    cols = cube.select([int(c) for c in picks])
+    kw = dict(n_mu=3, tol=0.0, max_iter=24)
+    g = gpu_solve(atom_dir["h6"], cols, precision=1, scheduler=1, **kw)
+    a = O.Atom(atom_dir["h6"])
+    with concurrent.futures.ThreadPoolExecutor(max_workers=16) as ex:
+        orc = list(ex.map(lambda c: O.solve_column(a, cols.column(c), **kw), range(cols.n_columns)))
+    worst = 0.0
+    for c, r in enumerate(orc):
+        lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
+        assert g["n_iter"][c] == r["n_iter"] == 24
+        e = max(np.max(np.abs(g["pops"][lo:hi] / r["pops"] - 1)), np.max(np.abs(g["spectrum"][c] / r["spectrum"] - 1)))
+        worst = max(worst, e)
+    print(f"FP32 vs FP64 after 24 iterations, 256 columns: max relative difference {worst:.3e}", flush=True)
+    assert worst < 1e-3

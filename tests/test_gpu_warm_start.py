@@ -4,7 +4,9 @@ its prediction, and check what it gains and that MALI still decides the
 answer.  The size of the gain is an empirical property of the synthetic
 atmospheres (not pinned by the paper); the test requires a reduction of
 the mean iteration count by at least 5 % and of the 99th percentile, and
-unchanged accuracy against the oracle."""
+answers within 1e-3 of the oracle converged to 1e-10 from either start
+(both stop by the change test of 1e-4 and the fixed-point bound of
+2e-4)."""
 import numpy as np
 import pytest
 
@@ -14,7 +16,7 @@ from paper_1411_1079_amd import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-KW = dict(n_mu=5, tol=1e-4, max_iter=200)
+KW = dict(n_mu=5, tol=1e-4, tol_fp=2e-4, max_iter=200)
 
 
 @pytest.fixture(scope="module")
@@ -59,13 +61,11 @@ def _errors(atom_path, cols, out, picks):
 
 
 def _accuracy_unchanged(atom_path, cols, out, cold, picks):
-    """The learned start leaves the answer as accurate as the LTE start:
-    within 1e-3 of the converged oracle, or, on slowly converging columns
-    where the stopping rule leaves the LTE-started answer farther away, no
-    farther than 1.5 times that distance."""
+    """Both the learned start and the LTE start end within 1e-3 of the
+    oracle converged to 1e-10."""
     ew, ec = _errors(atom_path, cols, out, picks), _errors(atom_path, cols, cold, picks)
     print(f"errors vs converged oracle: learned start {ew}, LTE start {ec}", flush=True)
-    assert np.all(ew <= np.maximum(1e-3, 1.5 * ec)), (ew, ec)
+    assert np.all(ew <= 1e-3) and np.all(ec <= 1e-3), (ew, ec)
 
 
 def test_warm_start_reduces_iterations(trained, cubes, atom_dir):
