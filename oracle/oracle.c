@@ -1239,8 +1239,10 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
                 ng_count = 0;
             }
         }
-        /* PRD: rho from this iteration's radiation field and the new populations */
-        if (prd) prd_update(&cs, n, it, o->prd_eps0, cf);
+        /* PRD: rho from this iteration's radiation field and the new
+         * populations, for the next formal solution (none after the last
+         * iteration: the emergent spectrum keeps the rho of the last one) */
+        if (prd && it < o->max_iter) prd_update(&cs, n, it, o->prd_eps0, cf);
     }
     if (it > o->max_iter) it = o->max_iter;
     *n_iter = it;
