@@ -883,7 +883,8 @@ static void actual_rates(const colstate *cs, int t, int k, double *up, double *d
  * rho' = rho eps + (1 - eps), eps = min(1, eps0 it^2) (eps0 <= 0: 1);
  * negative rho' count as 0; and rho' is normalised so that
  * sum_rays W phi rho' = 1 (the emission profile integrates to 1, as the
- * absorption profile does). */
+ * absorption profile does); where that sum is not positive (every rho'
+ * clamped), rho = 1 (CRD) at that point. */
 static void prd_update(colstate *cs, const double *n, int it, double eps0, double cf) {
     const orc_atom *a = cs->a;
     int N = cs->N, L = a->L, T = a->T;
@@ -930,7 +931,9 @@ static void prd_update(colstate *cs, const double *n, int it, double eps0, doubl
                 for (int m = 0; m < cs->nmu; m++) for (int s = 0; s < 2; s++)
                     norm += tr->wnu[ja] * 0.5 * cs->wmu[m] * cs->phi[t][(((size_t)k * na + ja) * cs->nmu + m) * 2 + s] * r;
             }
-            for (int ja = 0; ja < na; ja++) nr[(size_t)k * na + ja] /= norm;
+            /* no positive emission left (every rho' clamped to 0): CRD at this point */
+            for (int ja = 0; ja < na; ja++)
+                nr[(size_t)k * na + ja] = (norm > 0.0 && isfinite(norm)) ? nr[(size_t)k * na + ja] / norm : 1.0;
         }
         free(J);
         newrho[t] = nr;

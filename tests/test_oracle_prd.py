@@ -138,3 +138,13 @@ def test_prd_fixed_point_against_brute_force(atom_dir):
     # a rho off by a plausible mistake (no normalisation) is far outside that
     P.rho = {0: r["rho"][0] * 1.01}
     assert np.max(np.abs(P.se_solve(P.rate_matrix(r["pops"]), r["pops"]) / r["pops"] - 1)) > 1e-4
+
+
+def test_two_point_column_stays_finite(atom_dir):
+    """A two-point column, where every rho' at the top point can be clamped
+    to 0, keeps finite populations (CRD at such a point)."""
+    a = O.Atom(atom_dir["prd_tiny"])
+    r = O.solve_column(a, conftest.tiny_column(2), n_mu=3, tol=0.0, max_iter=20, coll_scale=1e-2, prd=1,
+                       prd_lines=(0,), want_psi=True)
+    assert r["status"] == 1 and np.all(np.isfinite(r["pops"])) and np.all(np.isfinite(r["rho"][0]))
+    assert np.all(np.isfinite(r["spectrum"])) and np.all(np.isfinite(r["psi_star"]))
