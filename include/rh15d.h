@@ -41,7 +41,7 @@ enum {
 };
 
 enum { RH15D_FP64 = 0, RH15D_FP32 = 1 };
-enum { RH15D_START_LTE = 0, RH15D_START_ZERO_RADIATION = 1, RH15D_START_PROVIDED = 2 };
+enum { RH15D_START_LTE = 0, RH15D_START_ZERO_RADIATION = 1, RH15D_START_PROVIDED = 2, RH15D_START_ESCAPE = 3 };
 enum { RH15D_SCHED_CHUNKED = 0, RH15D_SCHED_SLOTS = 1 };
 
 /* Per-column status codes written to rh15d_outputs.status. */
@@ -49,7 +49,14 @@ enum {
     RH15D_CONVERGED = 0,    /* max relative change fell below tol */
     RH15D_MAX_ITER = 1,     /* iteration limit reached */
     RH15D_NONFINITE = 2,    /* a population became non-finite or non-positive */
-    RH15D_SINGULAR = 3      /* a rate matrix had a zero pivot */
+    RH15D_SINGULAR = 3,     /* a rate matrix had a zero pivot */
+    RH15D_BAD_INPUT = 4     /* the column's data cannot be used (a non-finite or
+                               non-positive T, n_e or n_H, a non-finite velocity,
+                               a negative microturbulence, or z not strictly
+                               decreasing): no iteration, n_iter = 0, its
+                               populations, history, spectrum and Psi* are NaN;
+                               the other columns are unaffected (Sec. 2.2: a
+                               problematic column is dealt with on its own) */
 };
 
 #define RH15D_MAX_LEVELS 8
@@ -92,7 +99,10 @@ typedef struct {
     const double *n_H;            /* DEVICE [total_depth] hydrogen density, m^-3, > 0 */
     const double *v_z;            /* DEVICE [total_depth] vertical velocity, m/s,
                                      positive upward (towards an observer at mu = 1) */
-    const double *v_turb;         /* DEVICE [total_depth] microturbulence, m/s */
+    const double *v_turb;         /* DEVICE [total_depth] microturbulence, m/s, >= 0
+                                     (the device values are checked per column on
+                                     the device: a column that breaks one of these
+                                     conditions gets status RH15D_BAD_INPUT) */
     const double *init_pops;      /* DEVICE [total_depth][n_levels] start populations
                                      (read only when start = RH15D_START_PROVIDED) */
 } rh15d_columns;
@@ -128,11 +138,39 @@ typedef struct {
                            by repeated division by 10; no column converges
                            and no iterate enters Ng's history while the
                            factor exceeds 1.  <= 1 (default 1): off */
+    double tol_fp;      /* > 0: a column converges only when, besides the change
+                           test of tol, the distance to the fixed point that its
+                           last two changes imply is below tol_fp: with
+                           r = Delta_k / Delta_{k-1} < 1 the remainder of a
+                           linear iteration Delta_k r / (1 - r), tested as
+                           Delta_k^2 < tol_fp (Delta_{k-1} - Delta_k).  There is
+                           no ratio at the first iteration or after an applied
+                           Ng extrapolation (then only Delta_k = 0 passes).
+                           0 (default): the change test alone (Sec. 2.3) */
+    int esc_iter;       /* RH15D_START_ESCAPE: statistical-equilibrium iterations
+                           from LTE with the spontaneous rate of every transition
+                           times the escape probability (1 - e^-tau)/tau of its
+                           vertical optical depth tau from the top at the line
+                           centre (rest frame) or continuum edge, no other
+                           radiative rates (Sec. 2.3, starting solutions);
+                           0..100, default 3 */
+    int prd;            /* 1: lines the atom marks PRD emit with the angle-averaged
+                           partial-redistribution profile psi = rho phi
+                           (Sec. 2.1; rho from the angle-averaged R_II of
+                           Hummer 1962 after every iteration, see
+                           rh15d_solve_columns); 0 (default): every line in
+                           complete redistribution.  Forces one angle per lane
+                           (sweep_mc must be 0 or 1) */
+    double prd_eps0;    /* PRD switching (Sec. 2.3, Eq. 1): the rho update after
+                           iteration n is rho eps + (1 - eps), eps = min(1,
+                           prd_eps0 n^2); <= 0 (default): off */
 } rh15d_options;
 
-/* Measurements of the calling thread's last rh15d_solve_columns made with
- * options.profile = 1 (all zero otherwise).  Times come from HIP events
- * recorded on the caller's stream around the library's own launches. */
+/* Measurements of the calling thread's last rh15d_solve_columns.  The
+ * times and work counts are filled with options.profile = 1 (zero
+ * otherwise); they come from HIP events recorded on the caller's stream
+ * around the library's own launches.  graph_launches is filled on every
+ * call. */
 typedef struct {
     int64_t sweep_launches;     /* formal-solution launches (rate mode) */
     double sweep_ms;            /* their summed duration */
@@ -144,6 +182,10 @@ typedef struct {
     int64_t ray_steps;          /* formal-solution ray-steps of the rate launches */
     double sweep_flops;         /* algorithmic flops of the rate launches */
     double sweep_bytes;         /* algorithmic HBM bytes of the rate launches */
+    int64_t graph_launches;     /* iterations replayed as a captured HIP graph
+                                   (slot scheduler on a non-default stream with
+                                   profile = 0); 0 when every iteration was
+                                   launched kernel by kernel */
 } rh15d_stats;
 
 int rh15d_last_stats(rh15d_stats *stats);
@@ -162,9 +204,10 @@ typedef struct {
                            may be NULL */
 } rh15d_outputs;
 
-/* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, 200 iterations,
- * Ng order 2 / delay 5 / period 4, LTE start, coll_scale 1, crs_f0 1, chunked,
- * no profiling, automatic sweep shape. */
+/* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, tol_fp 0, 200
+ * iterations, Ng order 2 / delay 5 / period 4, LTE start (esc_iter 3),
+ * coll_scale 1, crs_f0 1, chunked, no profiling, automatic sweep shape,
+ * complete redistribution (prd 0, prd_eps0 0). */
 int rh15d_default_options(rh15d_options *opt);
 
 /* Device workspace needed by rh15d_solve_columns for these columns and
@@ -181,7 +224,18 @@ int rh15d_workspace_size(const rh15d_atom *atom, const rh15d_columns *cols,
  * solution of every (wavelength, angle, direction) ray with the diagonal
  * Psi* and the preconditioned rate accumulation, the statistical-
  * equilibrium solve per depth, the convergence test and Ng; finally the
- * vertical emergent spectrum and Psi*.  Work is enqueued on hip_stream
+ * vertical emergent spectrum and Psi*.  With options.prd, after the
+ * convergence test of every iteration each PRD line's
+ * rho(j) = 1 + gamma n_l B_lu / (n_u P_u) [sum_j' g(j, j') J(j') - Jbar]
+ * is recomputed from that iteration's intensities and the new populations
+ * (J the angle-averaged, Jbar the profile-weighted mean intensity, P_u the
+ * total rate out of the upper level, gamma = P_u / (P_u + c_el n_H) the
+ * coherent fraction, g the redistribution weights of the angle-averaged
+ * R_II normalised per output frequency), switched (prd_eps0) and
+ * normalised so that the emission profile integrates to 1; the next
+ * formal solution and the emergent spectrum use psi = rho phi for
+ * spontaneous and stimulated emission (Uitenbroek 2001, angle-averaged
+ * PRD; a reading of its discretisation).  Work is enqueued on hip_stream
  * (NULL = the default stream); the call returns after the iteration loop
  * has finished on the device (it reads a done-counter back each iteration),
  * and all outputs are valid once the stream is synchronised.  workspace is

@@ -122,7 +122,25 @@ int parse_atom_file(const char *path, rh15d_atom *a, std::string &err) {
     for (int i = 0; i < nc; i++)
         if (!read_transition(tk, a->tr[nl + i], 1, a->L)) { err = "malformed continuum"; return RH15D_EIO; }
     a->n_lines = nl; a->n_cont = nc;
-    if (!tk.expect("BACKGROUND") || !tk.word(w)) { err = "malformed BACKGROUND"; return RH15D_EIO; }
+    // optional: elastic collisions and the redistribution of lines
+    if (!tk.word(w)) { err = "malformed atom file"; return RH15D_EIO; }
+    if (w == "ELASTIC") {
+        int ne;
+        if (!tk.integer(ne) || ne < 0) { err = "malformed ELASTIC"; return RH15D_EIO; }
+        for (int i = 0; i < ne; i++) {
+            int li;
+            double c;
+            std::string kind;
+            if (!tk.integer(li) || li < 0 || li >= nl || !tk.num(c) || !(c >= 0.0) || !tk.word(kind) ||
+                (kind != "PRD" && kind != "CRD")) {
+                err = "malformed ELASTIC row"; return RH15D_EIO;
+            }
+            a->tr[li].c_el = c;
+            a->tr[li].prd = kind == "PRD";
+        }
+        if (!tk.word(w)) { err = "malformed atom file"; return RH15D_EIO; }
+    }
+    if (w != "BACKGROUND" || !tk.word(w)) { err = "malformed BACKGROUND"; return RH15D_EIO; }
     if (w == "NONE") a->bg_kind = 0;
     else if (w == "HMINUS") { a->bg_kind = 1; if (!tk.num(a->c_bg)) { err = "malformed HMINUS"; return RH15D_EIO; } }
     else { err = "unknown background"; return RH15D_EIO; }
@@ -235,6 +253,28 @@ void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGro
         cols += (2 * n_mu + 1) * static_cast<int>(a.tr[t].act.size());
     }
     out.ray_cols = cols;
+    // PRD lines: their rays' columns in the emission-profile row (same order
+    // as in the profile row); wavelengths whose intensities the rho update
+    // reads: those of the PRD lines and of every transition into or out of
+    // a PRD line's upper level (its total depopulation rate)
+    out.psi_off.assign(T, -1);
+    int pcols = 0;
+    std::vector<char> upper(a.L, 0), stored(T, 0);
+    for (int t = 0; t < a.n_lines; t++)
+        if (a.tr[t].prd) {
+            out.psi_off[t] = pcols;
+            pcols += (2 * n_mu + 1) * static_cast<int>(a.tr[t].act.size());
+            upper[a.tr[t].u] = 1;
+        }
+    out.psi_cols = pcols;
+    for (int t = 0; t < T; t++) stored[t] = a.tr[t].prd || upper[a.tr[t].u] || upper[a.tr[t].l];
+    out.st_idx.assign(NL, -1);
+    int nst = 0;
+    if (pcols > 0)
+        for (int j = 0; j < NL; j++)
+            for (int i = a.jact_off[j]; i < a.jact_off[j + 1]; i++)
+                if (stored[a.jact_t[i]]) { out.st_idx[j] = nst++; break; }
+    out.ist_cols = nst * n_mu * 2;
 
     std::vector<std::vector<int>> p_keys(T), q_keys(T);
     std::map<std::pair<int, int>, std::vector<int>> x_keys;
@@ -281,8 +321,9 @@ void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGro
                 out.lane_lamfac.push_back(a.lam[j] / kBgLambdaRef);
                 out.lane_hnu_k.push_back(kH * nu / kKB);
                 out.lane_2hnu3c2.push_back(2.0 * kH * nu * nu * nu / (kC * kC));
+                out.lane_ist.push_back(real && out.st_idx[j] >= 0 ? (out.st_idx[j] * n_mu + m0) * 2 + s : -1);
                 for (int q = 0; q < kMaxSlots; q++) {
-                    int pb = -1;
+                    int pb = -1, ps = -1;
                     double wj = 0, kapj = 0, alpha = 0;
                     // padding lanes repeat lane 0's ray with zero weights, so their
                     // opacity stays finite and their contributions vanish
@@ -295,6 +336,7 @@ void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGro
                             wj = real ? tr.w[ja] : 0.0;
                             if (tr.kind == 0) {
                                 pb = ray_off[cur[q]] + (s * na + ja) * n_mu + m0;
+                                if (out.psi_off[cur[q]] >= 0) ps = out.psi_off[cur[q]] + (s * na + ja) * n_mu + m0;
                                 kapj = 4.0 * kPI * wj * 0.5 / (kH * tr.nu0);
                             } else {
                                 kapj = 4.0 * kPI * wj * 0.5 / (kH * nu);
@@ -303,6 +345,7 @@ void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGro
                         }
                     }
                     out.pbase.push_back(pb);
+                    out.psb.push_back(ps);
                     out.wj.push_back(wj);
                     out.kapj.push_back(kapj);
                     out.alpha.push_back(alpha);

@@ -207,6 +207,8 @@ __device__ __forceinline__ int64_t rfl_wave(int64_t x) { return (int64_t)__built
 // rays (2 directions x angles x wavelengths) of one line at one depth that
 // the profile-preparation wavefront holds in registers
 constexpr int kMaxLineRays = 1536;
+// wavelengths of a line with partial frequency redistribution
+constexpr int kMaxPrdFreq = 256;
 
 // ---------------------------------------------------------------------------
 // per-launch arguments
@@ -228,6 +230,8 @@ struct RunArgs {
     int32_t *n_iter, *status;
     // per slot
     int *slot_col, *slot_state, *slot_it, *ng_count, *ng_head;
+    int *slot_bad;            // nonzero: the column's data failed the input checks
+    double *slot_dprev;       // change of the slot's previous plain iteration, -1 if none
     int *ctr;                 // [CTR_COUNT]
     int *retire_list, *refill_list;
     // workspace, slot-local depth index gc = slot * ND + k
@@ -244,8 +248,13 @@ struct RunArgs {
     double *dk;               // [gc] max relative change per depth point
     int *flag;                // [gc] 0 ok, 1 non-finite/non-positive, 2 singular
     double *ring;             // [4][S*ND][L] Ng history
-    int max_iter, ng_order, ng_delay, ng_period, start;
-    double tol, coll_scale, crs_f0;
+    // partial frequency redistribution (prd = 1), sweep precision
+    void *emis;               // [gc][psi_cols] emission profiles psi = rho phi of the PRD lines' rays
+    void *ist;                // [gc][ist_cols] intensities of the stored rays (last sweep)
+    void *gtab;               // [gc][g_cols] redistribution weights g(j, j') of the PRD lines
+    double *rho;              // [gc][sum of PRD n_act] new rho (between the two update kernels)
+    int max_iter, ng_order, ng_delay, ng_period, start, esc_iter, prd;
+    double tol, tol_fp, coll_scale, crs_f0, prd_eps0;
 };
 
 // Per-depth data of the sweep (slot-local depth gc), in the sweep's precision:
@@ -278,6 +287,13 @@ __device__ void prep_point(const RunArgs &a, int slot, int k) {
     const DevAtom &A = a.A;
     const int L = A.L;
     const double T = a.T[g], ne = a.ne[g], nH = a.nH[g];
+    // column data the method can use; a failing point marks its column
+    {
+        const bool ok = isfinite(T) && T > 0.0 && isfinite(ne) && ne > 0.0 && isfinite(nH) && nH > 0.0 &&
+                        isfinite(a.vz[g]) && isfinite(a.vt[g]) && a.vt[g] >= 0.0 && isfinite(a.z[g]) &&
+                        (k == 0 || a.z[g] < a.z[g - 1]);
+        if (!ok) atomicOr(&a.slot_bad[slot], 1);
+    }
     const double kT = kKB * T;
     const double saha = log(2.0 / ne) + 1.5 * log(2.0 * kPI * kME * kT / (kH * kH));
     double lr[RH15D_MAX_LEVELS];
@@ -330,7 +346,7 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const DevTransition &tr = A.tr[t];
     const double T = a.T[g], vt = a.vt[g], vz = a.vz[g];
     const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * T / A.mass + vt * vt);
-    const R adamp = static_cast<R>(tr.gamma / (4.0 * kPI * dnd));
+    const R adamp = static_cast<R>((tr.gamma + tr.c_el * a.nH[g]) / (4.0 * kPI * dnd));
     const double rdnd = 1.0 / dnd;
     const double pre = rdnd / sqrt(kPI);
     const double vzc = vz / kC;
@@ -338,6 +354,8 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     const double *pnu = A.prof_nu + r0, *pmus = A.prof_mus + r0, *pw = A.prof_w + r0;
     const int *pdst = A.prof_dst + r0;
     R *phi = reinterpret_cast<R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
+    // PRD line: the emission profile starts as the absorption profile (rho = 1)
+    R *psi = (a.prd && tr.prd) ? reinterpret_cast<R *>(a.emis) + gc * A.psi_cols + tr.psi_off : nullptr;
     // The line's rays in order of distance from the line centre, each stored
     // at its place in the row (quadrature rays by direction, wavelength and
     // angle, then the vertical emergent ray of each wavelength: mu = 1,
@@ -377,7 +395,11 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
         const R rtot = static_cast<R>(1.0 / tot);
 #pragma unroll
         for (int h = 0; h < kHeld; h++)
-            if (lane + h * kWave < nr) phi[dst[h]] = sizeof(R) == 8 ? static_cast<R>(val[h] / tot) : val[h] * rtot;
+            if (lane + h * kWave < nr) {
+                const R v = sizeof(R) == 8 ? static_cast<R>(val[h] / tot) : val[h] * rtot;
+                phi[dst[h]] = v;
+                if (psi) psi[dst[h]] = v;
+            }
     } else {
         for (int r0 = lane; r0 < nr; r0 += U * kWave) {
             double nu[U], mus[U], w[U];
@@ -406,8 +428,11 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
                 if (r0 + u * kWave < nr) x[u] = phi[r0 + u * kWave];
 #pragma unroll
             for (int u = 0; u < U; u++)
-                if (r0 + u * kWave < nr)
-                    phi[r0 + u * kWave] = sizeof(R) == 8 ? static_cast<R>(x[u] / tot) : x[u] * rtot;
+                if (r0 + u * kWave < nr) {
+                    const R v = sizeof(R) == 8 ? static_cast<R>(x[u] / tot) : x[u] * rtot;
+                    phi[r0 + u * kWave] = v;
+                    if (psi) psi[r0 + u * kWave] = v;
+                }
         }
     }
     if (lane == 0) a.norm[gc * A.n_lines + t] = tot;
@@ -479,13 +504,25 @@ struct PointIn {
     R gfac[NS];        // continuum slots: n_l*/n_u* exp(h nu / k T) of the record
     R nl[NS], nu[NS];
     R ph[NS][MC];      // line slots: profile values of the lane's angles
+    R ps[NS][MC];      // PRD line slots: emission-profile values (psi = rho phi)
 };
 
-template <typename R, int NS, int MC>
+// Where the partial-frequency-redistribution variant of the sweep reads
+// the emission profiles (psi) and stores the intensities of the rays the
+// rho update needs.
+template <typename R>
+struct PrdIO {
+    const R *psi;      // [gc][psi_cols]
+    R *ist;            // [gc][ist_cols]
+    int psi_cols, ist_cols;
+};
+
+template <typename R, int NS, int MC, bool PRD = false>
 __device__ __forceinline__ void load_point(const R *__restrict__ recb, const R *__restrict__ popsb,
                                            const R *__restrict__ phi, int rec_w, int L, int ray_cols,
                                            const Slots<R, NS> &sl, const int *pb, int64_t g, int64_t gc,
-                                           int64_t gc_dz, PointIn<R, NS, MC> &p) {
+                                           int64_t gc_dz, PointIn<R, NS, MC> &p, const PrdIO<R> *pio = nullptr,
+                                           const int *psb = nullptr) {
     const R *rec = recb + gc * rec_w;
     p.invT = rec[1];
     p.kbg = rec[2];
@@ -499,6 +536,11 @@ __device__ __forceinline__ void load_point(const R *__restrict__ recb, const R *
         p.gfac[q] = sl.kind[q] == 1 ? rec[kRecHead + sl.c[q]] : R(0);
 #pragma unroll
         for (int r = 0; r < MC; r++) p.ph[q][r] = (sl.kind[q] == 0 && pb[q] >= 0) ? phirow[pb[q] + r] : R(0);
+        if constexpr (PRD) {
+            const R *psirow = pio->psi + gc * pio->psi_cols;
+#pragma unroll
+            for (int r = 0; r < MC; r++) p.ps[q][r] = (sl.kind[q] == 0 && psb[q] >= 0) ? psirow[psb[q] + r] : p.ph[q][r];
+        }
     }
 }
 
@@ -536,7 +578,7 @@ struct RayPt {
     R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
 };
 
-template <typename R, int NS, int MC>
+template <typename R, int NS, int MC, bool PRD = false>
 __device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R, NS> &sh, const PointIn<R, NS, MC> &in,
                                           int r, RayPt<R, NS> &p) {
     R chi = sh.chi0, eta = sh.eta0;
@@ -544,10 +586,12 @@ __device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R
     for (int q = 0; q < NS; q++) {
         if (sl.kind[q] == 0) {
             const R ph = in.ph[q][r];
+            // emission (spontaneous and stimulated) with psi for PRD lines
+            const R ps = PRD ? in.ps[q][r] : ph;
             p.ph[q] = ph;
             p.vlu[q] = sl.cblu[q] * ph;
-            p.vul[q] = sl.cbul[q] * ph;
-            p.U[q] = sl.ca[q] * ph;
+            p.vul[q] = sl.cbul[q] * ps;
+            p.U[q] = sl.ca[q] * ps;
             p.cht[q] = sh.nl[q] * p.vlu[q] - sh.nu[q] * p.vul[q];
             chi += p.cht[q];
             eta += sh.nu[q] * p.U[q];
@@ -669,7 +713,7 @@ __device__ __forceinline__ void red_flush(const R *lds, R *out, int N, int k_fir
 // direction, through one column.  Down rays start at the top with no
 // incoming radiation; up rays start at the bottom with the diffusion
 // approximation I = B + mu dB/dtau.
-template <typename R, int MODE, int NS, int NC, int MC>
+template <typename R, int MODE, int NS, int NC, int MC, bool PRD = false>
 __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot, int lane, const R *__restrict__ rec,
                                             const R *__restrict__ phi, const R *__restrict__ popsb,
                                             R *__restrict__ part, R *lds) {
@@ -700,11 +744,21 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     const R lamfac = static_cast<R>(A.lanes.lamfac[li]);
     const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
     const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
-    int pb[NS];
+    int pb[NS], psb[NS];
     R kapj[NS], alpha[NS], wpsi[NS];
+    PrdIO<R> pio{};
+    int ist_base = -1;
+    if constexpr (PRD) {
+        pio.psi = reinterpret_cast<const R *>(a.emis);
+        pio.ist = reinterpret_cast<R *>(a.ist);
+        pio.psi_cols = A.psi_cols;
+        pio.ist_cols = A.ist_cols;
+        ist_base = MODE == MODE_RATES ? A.lanes.ist[li] : -1;
+    }
 #pragma unroll
     for (int q = 0; q < NS; q++) {
         pb[q] = A.lanes.pbase[li * kMaxSlots + q];
+        psb[q] = PRD ? A.lanes.psb[li * kMaxSlots + q] : -1;
         kapj[q] = static_cast<R>(A.lanes.kapj[li * kMaxSlots + q]);
         alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
         const R wj = static_cast<R>(A.lanes.wj[li * kMaxSlots + q]);
@@ -753,31 +807,38 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             rb++;
         }
     };
+    // PRD: the intensity of every ray that the rho update reads, per point
+    auto store_I = [&](int kk, int r, R v) {
+        if constexpr (PRD)
+            if (ist_base >= 0) pio.ist[(gc0 + kk) * pio.ist_cols + ist_base + 2 * r] = v;
+    };
     {
         PointIn<R, NS, MC> in0;
-        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k, gc0 + k, gc0 + k, in0);
+        load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k, gc0 + k, gc0 + k, in0, &pio,
+                                   psb);
         Shared<R, NS> sh;
         shared_terms<R, NS, MC>(in0, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
         PointIn<R, NS, MC> in2;
         Shared<R, NS> sh2;
         R dzb = R(0);
         if (s_dir != 0) {
-            load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + N - 2, gc0 + N - 2, gc0 + N - 1,
-                                  in2);
+            load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + N - 2, gc0 + N - 2,
+                                       gc0 + N - 1, in2, &pio, psb);
             shared_terms<R, NS, MC>(in2, sl, alpha, hnu_k, two_hnu3, lamfac, sh2);
             dzb = in2.dz;
         }
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS, MC>(sl, sh, in0, r, p);
+            ray_terms<R, NS, MC, PRD>(sl, sh, in0, r, p);
             R I0 = R(0);
             if (s_dir != 0) {
                 RayPt<R, NS> p2;
-                ray_terms<R, NS, MC>(sl, sh2, in2, r, p2);
+                ray_terms<R, NS, MC, PRD>(sl, sh2, in2, r, p2);
                 const R dtv = R(0.5) * (p.chi + p2.chi) * dzb;
                 I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
             }
+            store_I(k, r, I0);
             if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], I0, R(0), acc);
             else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], I0, R(0), acc);
             I[r] = I0;
@@ -798,7 +859,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS, MC>(sl, sh, cur, r, p);
+            ray_terms<R, NS, MC, PRD>(sl, sh, cur, r, p);
             const R x = (chi_p[r] + p.chi) * dz * hinvmu[r];
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
@@ -806,6 +867,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             const R psi = wb * p.rchi;
             const R Ieff = up + psi * sh.etabg;
             I[r] = up + wb * p.S;
+            store_I(k, r, I[r]);
             if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], Ieff, psi, acc);
             else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], Ieff, psi, acc);
             chi_p[r] = p.chi;
@@ -814,7 +876,8 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         emit();
     };
     auto load = [&](int kk, PointIn<R, NS, MC> &dst) {
-        load_point<R, NS, MC>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + kk, gc0 + kk, gc0 + kk + dz_shift, dst);
+        load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + kk, gc0 + kk, gc0 + kk + dz_shift,
+                                   dst, &pio, psb);
     };
     // two input buffers used alternately (the loop is unrolled by two), so
     // the inputs of the next point load into the buffer not in use and no
@@ -834,7 +897,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
 // number of continuum slots; one launch per (slots, continua) covers the
 // range [g_begin, g_end), so each variant gets its own registers and the
 // line / continuum choice of every slot is fixed at compile time.
-template <typename R, int MODE, int NS, int NC, int MC>
+template <typename R, int MODE, int NS, int NC, int MC, bool PRD = false>
 __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end, const R *__restrict__ rec,
                                                const R *__restrict__ phi, const R *__restrict__ popsb,
                                                R *__restrict__ part) {
@@ -858,8 +921,8 @@ __global__ __launch_bounds__(256) void k_sweep(RunArgs a, int g_begin, int g_end
         if (by >= a.ctr[CTR_RETIRE]) return;
         slot = rfl(a.retire_list[by]);
     }
-    sweep_group<R, MODE, NS, NC, MC>(a, grp, slot, lane, rec, phi, popsb, part,
-                                     red_lds + (threadIdx.x >> 6) * Red<R, NS, MODE>::SIZE);
+    sweep_group<R, MODE, NS, NC, MC, PRD>(a, grp, slot, lane, rec, phi, popsb, part,
+                                          red_lds + (threadIdx.x >> 6) * Red<R, NS, MODE>::SIZE);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,9 +1009,14 @@ __global__ __launch_bounds__(256) void k_rad_rates(RunArgs a) {
 // Rate matrix entry (i, j), i != j: the radiative rates from j into i with
 // the cross terms of overlapping transitions (gathered by k_rad_rates; with
 // zero radiation the spontaneous rates alone), plus the collisional rates.
-template <bool ZERO_RAD>
+// Kinds of rate-equation solve: an iteration (preconditioned radiative
+// rates), the zero-radiation start, an escape-probability start iteration.
+enum { SE_ITERATION = 0, SE_ZERO_RADIATION = 1, SE_ESCAPE = 2 };
+
+template <int KIND>
 __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int L, int64_t gc, double T, double ne,
                                              double cf) {
+    constexpr bool ZERO_RAD = KIND != SE_ITERATION;
     const DevAtom &A = a.A;
     double v = 0.0;
     if (!ZERO_RAD) v = a.rad[(size_t)(i * L + j) * ((size_t)a.S * a.ND) + gc];
@@ -961,8 +1029,11 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
     if (td >= 0) {  // j = u, i = l: de-excitation / recombination
         const DevTransition &tr = A.tr[td];
         if (ZERO_RAD) {
+            // spontaneous rate, times the transition's escape probability
+            // (stored in the rate-entry buffer) in an escape iteration
+            const double beta = KIND == SE_ESCAPE ? a.rad[(size_t)td * ((size_t)a.S * a.ND) + gc] : 1.0;
             if (tr.kind == 0) {
-                v += tr.A;
+                v += tr.A * beta;
             } else {
                 const double G0 = a.gr[gc * A.n_cont + (td - A.n_lines)];
                 double q = 0.0;
@@ -973,7 +1044,7 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
                     const double alpha = tr.alpha0 * r * r * r;
                     q += 4.0 * kPI * A.act_w[tr.act_off + ja] / (kH * nu) * 2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha;
                 }
-                v += q;
+                v += q * beta;
             }
         }
         v += coll_down(a, tr, T, ne) * cf;
@@ -981,8 +1052,9 @@ __device__ __forceinline__ double rate_entry(const RunArgs &a, int i, int j, int
     return v;
 }
 
-template <typename R, int L, bool ZERO_RAD>
+template <typename R, int L, int KIND>
 __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
+    constexpr bool ZERO_RAD = KIND != SE_ITERATION;
     const ColGeom cg = geom(a, slot);
     if (k >= cg.N) return;
     const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
@@ -1000,7 +1072,7 @@ __device__ __forceinline__ void se_point(const RunArgs &a, int slot, int k) {
     for (int i = 0; i < L; i++)
 #pragma unroll
         for (int j = 0; j < L; j++)
-            M[i][j] = i == j ? 0.0 : rate_entry<ZERO_RAD>(a, i, j, L, gc, T, ne, cf);
+            M[i][j] = i == j ? 0.0 : rate_entry<KIND>(a, i, j, L, gc, T, ne, cf);
 #pragma unroll
     for (int j = 0; j < L; j++) {
         double c = 0.0;
@@ -1077,14 +1149,343 @@ __global__ __launch_bounds__(256) void k_se(RunArgs a) {
     if (gc >= (int64_t)a.S * a.ND) return;
     const int slot = (int)(gc / a.ND);
     if (a.slot_state[slot] != SLOT_ACTIVE) return;
-    se_point<R, L, false>(a, slot, (int)(gc % a.ND));
+    se_point<R, L, SE_ITERATION>(a, slot, (int)(gc % a.ND));
 }
 
-template <int L>
-__global__ __launch_bounds__(256) void k_se_zero_radiation(RunArgs a) {
+// Start solutions of the slots being refilled: the rate equations with zero
+// radiation, or one escape-probability iteration (KIND).
+template <int L, int KIND>
+__global__ __launch_bounds__(256) void k_se_start(RunArgs a) {
     const int64_t n = (int64_t)a.ctr[CTR_REFILL] * a.ND;
     for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x)
-        se_point<double, L, true>(a, a.refill_list[w / a.ND], (int)(w % a.ND));
+        se_point<double, L, KIND>(a, a.refill_list[w / a.ND], (int)(w % a.ND));
+}
+
+// Escape probabilities of one escape-probability start iteration (Sec. 2.3,
+// starting solutions), one lane per (slot being refilled, transition): the
+// vertical optical depth from the top at the transition's reference
+// frequency with the current populations, line centre in the rest frame
+// (chi = h nu0 / 4 pi (n_l B_lu - n_u B_ul) H(a, 0) / (sqrt(pi) Delta nu_D))
+// or continuum edge (chi = (n_l - n_u G) alpha), negative opacities as 0,
+// accumulated by the trapezoid rule in z; beta = (1 - e^-tau) / tau (1 at
+// tau = 0) goes to the rate-entry buffer at [t][gc].
+__global__ __launch_bounds__(256) void k_escape_beta(RunArgs a) {
+    const DevAtom &A = a.A;
+    const int L = A.L, T = A.T;
+    const size_t P = (size_t)a.S * a.ND;
+    const int64_t n = (int64_t)a.ctr[CTR_REFILL] * T;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = a.refill_list[w / T], t = (int)(w % T);
+        const ColGeom cg = geom(a, slot);
+        const DevTransition &tr = A.tr[t];
+        double tau = 0.0, chi_prev = 0.0;
+        for (int k = 0; k < cg.N; k++) {
+            const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
+            const double Tk = a.T[g];
+            const double nl = a.pops[g * L + tr.l], nu = a.pops[g * L + tr.u];
+            double c;
+            if (tr.kind == 0) {
+                const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * Tk / A.mass + a.vt[g] * a.vt[g]);
+                const double H0 = tr.voigt ? voigt_w4<double>(tr.gamma / (4.0 * kPI * dnd), 0.0) : 1.0;
+                c = tr.hnu4pi * (nl * tr.Blu - nu * tr.Bul) * H0 / (sqrt(kPI) * dnd);
+            } else {
+                const double G = exp(a.lnr[gc * L + tr.l] - a.lnr[gc * L + tr.u]) * exp(-kH * tr.nu0 / (kKB * Tk));
+                c = (nl - nu * G) * tr.alpha0;
+            }
+            c = c > 0.0 ? c : 0.0;
+            if (k > 0) tau += 0.5 * (chi_prev + c) * (a.z[g - 1] - a.z[g]);
+            chi_prev = c;
+            a.rad[(size_t)t * P + gc] = tau > 0.0 ? -expm1(-tau) / tau : 1.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// partial frequency redistribution (angle-averaged, Uitenbroek 2001)
+// ---------------------------------------------------------------------------
+// Angle-averaged redistribution function R_II (Hummer 1962) in Doppler units
+// as the Lorentzian average, over the scattering's atom-frame frequency xi,
+// of the angle-averaged coherent Doppler kernel:
+//   R(x, x2) = 1/2 int (a/pi)/(a^2 + xi^2) erfc(|xi - m| + d) dxi,
+// m = (x + x2)/2, d = |x - x2|/2; 0 for d >= 6 (erfc(6) = 2e-17).  The
+// integral runs over [m - w, m + w], w = 6 - d, cut at xi = m and at
+// xi = +-0.5 where inside; pieces within the Lorentzian core |xi| <= 0.5 by
+// 4-point Gauss-Legendre on 8 panels uniform in t = asinh(xi / a) (measure
+// dt / (pi cosh t)), the others on ceil(length) panels uniform in xi.
+constexpr double kRiiCore = 0.5;
+constexpr int kRiiCorePanels = 8;
+__device__ double rII(double a, double x, double x2) {
+    const double gx[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563, 0.8611363115940526};
+    const double gw[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461, 0.3478548451374538};
+    const double m = 0.5 * (x + x2), d = 0.5 * fabs(x - x2);
+    if (d >= 6.0) return 0.0;
+    const double w = 6.0 - d;
+    double e[5];
+    int ne = 0;
+    e[ne++] = m - w;
+    if (-kRiiCore > m - w && -kRiiCore < m) e[ne++] = -kRiiCore;
+    if (kRiiCore > m - w && kRiiCore < m) e[ne++] = kRiiCore;
+    e[ne++] = m;
+    if (-kRiiCore > m && -kRiiCore < m + w) e[ne++] = -kRiiCore;
+    if (kRiiCore > m && kRiiCore < m + w) e[ne++] = kRiiCore;
+    e[ne++] = m + w;
+    double sum = 0.0;
+    for (int i = 0; i + 1 < ne; i++) {
+        const double lo = e[i], hi = e[i + 1];
+        if (!(hi > lo)) continue;
+        if (lo >= -kRiiCore && hi <= kRiiCore) {
+            const double t0 = asinh(lo / a), h = (asinh(hi / a) - t0) / kRiiCorePanels;
+            for (int p = 0; p < kRiiCorePanels; p++) {
+                const double c = t0 + (p + 0.5) * h;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const double sh = sinh(c + 0.5 * h * gx[q]);
+                    sum += 0.5 * h * gw[q] * erfc(fabs(a * sh - m) + d) / (kPI * sqrt(1.0 + sh * sh));
+                }
+            }
+        } else {
+            int np = (int)ceil(hi - lo);
+            if (np < 1) np = 1;
+            const double h = (hi - lo) / np;
+            for (int p = 0; p < np; p++) {
+                const double c = lo + (p + 0.5) * h;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const double xi = c + 0.5 * h * gx[q];
+                    sum += 0.5 * h * gw[q] * (a / kPI) / (a * a + xi * xi) * erfc(fabs(xi - m) + d);
+                }
+            }
+        }
+    }
+    return 0.5 * sum;
+}
+
+// Redistribution weights of the PRD lines at the depth points of the slots
+// being refilled, one 64-lane workgroup per (slot, depth, PRD line):
+// g(j, j') = w_j' R(x_j', x_j) / sum_j'' w_j'' R(x_j'', x_j) (x in Doppler
+// widths of the point, w the trapezoid frequency weights), row j of the
+// table holding the weights of the inputs j'.  A constant mean intensity is
+// redistributed into itself exactly.
+template <typename R>
+__global__ __launch_bounds__(64) void k_prd_tables(RunArgs a) {
+    const DevAtom &A = a.A;
+    const int lane = threadIdx.x;
+    const int64_t n = (int64_t)a.ctr[CTR_REFILL] * a.ND * A.n_prd;
+    for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+        const int ip = (int)(w % A.n_prd);
+        const int64_t sk = w / A.n_prd;
+        const int slot = a.refill_list[sk / a.ND], k = (int)(sk % a.ND);
+        const ColGeom cg = geom(a, slot);
+        if (k >= cg.N) continue;
+        const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
+        const DevTransition &tr = A.tr[A.prd_t[ip]];
+        const int na = tr.n_act;
+        const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * a.T[g] / A.mass + a.vt[g] * a.vt[g]);
+        const double ad = (tr.gamma + tr.c_el * a.nH[g]) / (4.0 * kPI * dnd);
+        R *G = reinterpret_cast<R *>(a.gtab) + gc * A.g_cols + tr.g_off;
+        // R(x_j, x_j2) for j >= j2, stored at both places
+        for (int p = lane; p < na * (na + 1) / 2; p += 64) {
+            int j = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+            while (j * (j + 1) / 2 > p) j--;
+            while ((j + 1) * (j + 2) / 2 <= p) j++;
+            const int j2 = p - j * (j + 1) / 2;
+            const double x = (A.nu[A.act_j[tr.act_off + j]] - tr.nu0) / dnd;
+            const double x2 = (A.nu[A.act_j[tr.act_off + j2]] - tr.nu0) / dnd;
+            const R r = static_cast<R>(rII(ad, x, x2));
+            G[j * na + j2] = r;
+            G[j2 * na + j] = r;
+        }
+        __syncthreads();
+        for (int j = lane; j < na; j += 64) {
+            double sum = 0.0;
+            for (int j2 = 0; j2 < na; j2++) sum += A.act_w[tr.act_off + j2] * static_cast<double>(G[j * na + j2]);
+            for (int j2 = 0; j2 < na; j2++)
+                G[j * na + j2] = static_cast<R>(A.act_w[tr.act_off + j2] * static_cast<double>(G[j * na + j2]) / sum);
+        }
+        __syncthreads();
+    }
+}
+
+// Actual radiative rate coefficient of transition t at depth point gc from
+// the stored intensities of the last sweep: out of its upper level
+// (UP = false: spontaneous and stimulated emission with the current
+// emission profile) or out of its lower level (UP = true: absorption);
+// the lanes of the wavefront share the rays, the sum is over the wavefront.
+template <typename R, bool UP>
+__device__ double actual_rate(const RunArgs &a, const DevTransition &tr, int t, int64_t gc, double T, int lane) {
+    const DevAtom &A = a.A;
+    const int na = tr.n_act, nmu = A.n_mu;
+    const R *ist = reinterpret_cast<const R *>(a.ist) + gc * A.ist_cols;
+    double acc = 0.0;
+    for (int r = lane; r < na * nmu * 2; r += 64) {
+        const int s = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+        const int j = A.act_j[tr.act_off + ja];
+        const double I = static_cast<double>(ist[(A.st_idx[j] * nmu + m) * 2 + s]);
+        const double W = A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m];
+        if (tr.kind == 0) {
+            const int col = (s * na + ja) * nmu + m;
+            const double ph = static_cast<double>(reinterpret_cast<const R *>(a.phi)[gc * A.ray_cols + tr.ray_off + col]);
+            if (UP) {
+                acc += W * ph * tr.Blu * I;
+            } else {
+                const double ps = (a.prd && tr.prd)
+                    ? static_cast<double>(reinterpret_cast<const R *>(a.emis)[gc * A.psi_cols + tr.psi_off + col]) : ph;
+                acc += W * ps * (tr.A + tr.Bul * I);
+            }
+        } else {
+            const double nu = A.nu[j];
+            const double rr = tr.nu0 / nu;
+            const double alpha = tr.alpha0 * rr * rr * rr;
+            const double kap = 4.0 * kPI * W / (kH * nu);
+            if (UP) {
+                acc += kap * alpha * I;
+            } else {
+                const double G = a.gr[gc * A.n_cont + (t - A.n_lines)] * exp(-kH * nu / (kKB * T));
+                acc += kap * (2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha + G * alpha * I);
+            }
+        }
+    }
+    return wave_sum(acc);
+}
+
+// rho of the PRD lines after an iteration (angle-averaged PRD, Uitenbroek
+// 2001), one wavefront per (slot still iterating, depth point, PRD line):
+//   rho(j) = 1 + gamma n_l B_lu / (n_u P_u) [sum_j' g(j, j') J(j') - Jbar]
+// with J the angle-averaged and Jbar the profile-weighted mean intensity of
+// the iteration's formal solution, P_u the total rate out of the upper level
+// (radiative with the same intensities and the current emission profiles,
+// plus collisional), gamma = P_u / (P_u + c_el n_H), the new populations;
+// then PRD switching (Sec. 2.3, Eq. 1) rho' = rho eps + (1 - eps),
+// eps = min(1, eps0 it^2) (1 if eps0 <= 0), negative values as 0, and
+// normalisation so that sum over rays of W phi rho' = 1 (rho = 1 where that
+// sum is not positive).  The result goes
+// to a.rho; k_prd_psi then rewrites the emission profiles (every line's
+// rates here read the previous ones).
+template <typename R>
+__global__ __launch_bounds__(256) void k_prd_rho(RunArgs a) {
+    __shared__ double sh[4][kMaxPrdFreq];
+    const DevAtom &A = a.A;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t n = (int64_t)a.S * a.ND * A.n_prd;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    const int L = A.L, nmu = A.n_mu;
+    for (int64_t w = rfl_wave(blockIdx.x * 4 + wv); w < n; w += waves) {
+        const int ip = (int)(w % A.n_prd);
+        const int64_t sk = w / A.n_prd;
+        const int slot = (int)(sk / a.ND), k = (int)(sk % a.ND);
+        if (a.slot_state[slot] != SLOT_ACTIVE) continue;
+        const ColGeom cg = geom(a, slot);
+        if (k >= cg.N) continue;
+        const int64_t g = cg.g0 + k, gc = cg.gc0 + k;
+        const int t = A.prd_t[ip];
+        const DevTransition &tr = A.tr[t];
+        const int na = tr.n_act, u = tr.u;
+        const double T = a.T[g], ne = a.ne[g];
+        const double cf = crs_factor(a.crs_f0, a.slot_it[slot]);
+        // total rate out of the upper level
+        double Pu = 0.0;
+        for (int t2 = 0; t2 < A.T; t2++) {
+            const DevTransition &d = A.tr[t2];
+            if (d.u == u) {
+                Pu += actual_rate<R, false>(a, d, t2, gc, T, lane) + coll_down(a, d, T, ne) * cf;
+            } else if (d.l == u) {
+                Pu += actual_rate<R, true>(a, d, t2, gc, T, lane) +
+                      coll_down(a, d, T, ne) * exp(a.lnr[gc * L + d.u] - a.lnr[gc * L + d.l]) * cf;
+            }
+        }
+        const double gam = Pu / (Pu + tr.c_el * a.nH[g]);
+        const double fac = gam * a.pops[g * L + tr.l] * tr.Blu / (a.pops[g * L + u] * Pu);
+        // mean intensities
+        const R *ist = reinterpret_cast<const R *>(a.ist) + gc * A.ist_cols;
+        const R *phi = reinterpret_cast<const R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
+        for (int ja = lane; ja < na; ja += 64) {
+            const int j = A.act_j[tr.act_off + ja];
+            double J = 0.0;
+            for (int m = 0; m < nmu; m++)
+                for (int s2 = 0; s2 < 2; s2++) J += 0.5 * A.wmu[m] * static_cast<double>(ist[(A.st_idx[j] * nmu + m) * 2 + s2]);
+            sh[wv][ja] = J;
+        }
+        double jb = 0.0;
+        for (int r = lane; r < na * nmu * 2; r += 64) {
+            const int s2 = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+            const int j = A.act_j[tr.act_off + ja];
+            jb += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * static_cast<double>(phi[(s2 * na + ja) * nmu + m]) *
+                  static_cast<double>(ist[(A.st_idx[j] * nmu + m) * 2 + s2]);
+        }
+        const double Jbar = wave_sum(jb);
+        double eps = 1.0;
+        if (a.prd_eps0 > 0.0) eps = fmin(1.0, a.prd_eps0 * (double)a.slot_it[slot] * (double)a.slot_it[slot]);
+        const R *G = reinterpret_cast<const R *>(a.gtab) + gc * A.g_cols + tr.g_off;
+        // the wavefront's J values are in LDS; rho per output frequency
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double rloc[kMaxPrdFreq / 64];
+#pragma unroll
+        for (int c = 0; c < kMaxPrdFreq / 64; c++) {
+            const int ja = lane + 64 * c;
+            rloc[c] = 1.0;
+            if (ja < na) {
+                double sJ = 0.0;
+                for (int j2 = 0; j2 < na; j2++) sJ += static_cast<double>(G[ja * na + j2]) * sh[wv][j2];
+                double r = isfinite(fac) ? 1.0 + fac * (sJ - Jbar) : 1.0;
+                r = r * eps + (1.0 - eps);
+                rloc[c] = r > 0.0 ? r : 0.0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int c = 0; c < kMaxPrdFreq / 64; c++)
+            if (lane + 64 * c < na) sh[wv][lane + 64 * c] = rloc[c];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double nrm = 0.0;
+        for (int r = lane; r < na * nmu * 2; r += 64) {
+            const int s2 = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+            nrm += A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m] * static_cast<double>(phi[(s2 * na + ja) * nmu + m]) *
+                   sh[wv][ja];
+        }
+        const double norm = wave_sum(nrm);
+        int off = 0;
+        for (int i = 0; i < ip; i++) off += A.tr[A.prd_t[i]].n_act;
+        double *rho = a.rho + gc * (A.psi_cols / (2 * nmu + 1)) + off;
+        // no positive emission left (every rho' clamped to 0): CRD at this point
+        const bool ok = norm > 0.0 && isfinite(norm);
+#pragma unroll
+        for (int c = 0; c < kMaxPrdFreq / 64; c++)
+            if (lane + 64 * c < na) rho[lane + 64 * c] = ok ? rloc[c] / norm : 1.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Emission profiles of the PRD lines from the new rho: psi = rho(j) phi for
+// every ray of the line (quadrature rays and the vertical emergent ray).
+template <typename R>
+__global__ __launch_bounds__(256) void k_prd_psi(RunArgs a) {
+    const DevAtom &A = a.A;
+    const int nmu = A.n_mu, rw = A.psi_cols / (2 * nmu + 1);
+    const int64_t n = (int64_t)a.S * a.ND * A.psi_cols;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gc = w / A.psi_cols;
+        const int col = (int)(w % A.psi_cols);
+        const int slot = (int)(gc / a.ND), k = (int)(gc % a.ND);
+        if (a.slot_state[slot] != SLOT_ACTIVE) continue;
+        if (k >= (int)(a.doff[a.slot_col[slot] + 1] - a.doff[a.slot_col[slot]])) continue;
+        // the PRD line owning this column and the column's wavelength
+        int ip = 0, off = 0;
+        while (ip + 1 < A.n_prd && col >= A.tr[A.prd_t[ip + 1]].psi_off) { off += A.tr[A.prd_t[ip]].n_act; ip++; }
+        const DevTransition &tr = A.tr[A.prd_t[ip]];
+        const int lc = col - tr.psi_off, na = tr.n_act;
+        const int ja = lc < 2 * nmu * na ? (lc % (na * nmu)) / nmu : lc - 2 * nmu * na;
+        const double r = a.rho[gc * rw + off + ja];
+        const R ph = reinterpret_cast<const R *>(a.phi)[gc * A.ray_cols + tr.ray_off + lc];
+        reinterpret_cast<R *>(a.emis)[gc * A.psi_cols + col] = static_cast<R>(r * static_cast<double>(ph));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,6 +1518,18 @@ __device__ double block_max(double v, double *sh) {
     return r;
 }
 
+// Stopping test of iteration k: change d < tol and, with tol_fp > 0, the
+// remainder d r / (1 - r) of the contraction r = d / dprev of two plain
+// iterations below tol_fp, tested as d^2 < tol_fp (dprev - d); dprev < 0
+// (first iteration, or an Ng extrapolation just applied) has no ratio and
+// passes only d = 0.
+__device__ __forceinline__ bool converged_at(double d, double dprev, double tol, double tol_fp) {
+    if (!(d < tol)) return false;
+    if (!(tol_fp > 0.0)) return true;
+    if (dprev < 0.0) return d == 0.0;
+    return d < dprev && d * d < tol_fp * (dprev - d);
+}
+
 __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
     __shared__ double sh[kConvThreads];
     const int slot = blockIdx.x;
@@ -1140,12 +1553,13 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
     if (fl == 2.0) status = RH15D_SINGULAR;
     else if (fl == 1.0) status = RH15D_NONFINITE;
     if (a.history && threadIdx.x == 0) a.history[(size_t)c * a.max_iter + it - 1] = fl > 0.0 ? NAN : dm;
+    double dprev = dm;    // the next iteration's ratio partner
     if (status < 0) {
         for (int i = threadIdx.x; i < NV; i += kConvThreads) pops[i] = nse[i];
         // while the collisions are switched the iterate solves another
         // problem: it may not end the iteration or enter Ng's history
         const bool switched = crs_factor(a.crs_f0, it) > 1.0;
-        if (dm < a.tol && !switched) {
+        if (!switched && converged_at(dm, a.slot_dprev[slot], a.tol, a.tol_fp)) {
             status = RH15D_CONVERGED;
         } else if (a.ng_order == 2 && it >= a.ng_delay && !switched) {
             const size_t stride = (size_t)a.S * a.ND * L;
@@ -1178,9 +1592,11 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
                         if (!(v > 0.0)) bad = 1.0;
                     }
                     bad = block_max(bad, sh);
-                    if (bad == 0.0)
+                    if (bad == 0.0) {
                         for (int i = threadIdx.x; i < NV; i += kConvThreads)
                             pops[i] = (1.0 - a1 - a2) * x0[i] + a1 * x1[i] + a2 * x2[i];
+                        dprev = -1.0;   // no contraction ratio across an extrapolation
+                    }
                 }
                 cnt = 0;
             }
@@ -1193,6 +1609,7 @@ __global__ __launch_bounds__(kConvThreads) void k_converge(RunArgs a) {
         for (int i = threadIdx.x; i < NV; i += kConvThreads) a.popsf[gc0 * L + i] = static_cast<float>(pops[i]);
     if (threadIdx.x == 0) {
         a.slot_it[slot] = it;
+        a.slot_dprev[slot] = dprev;
         if (status >= 0) {
             a.status[c] = status;
             a.n_iter[c] = it;
@@ -1221,6 +1638,7 @@ template <typename AR>
 struct EmTrans {
     int na;
     int kind[kMaxSlots], l[kMaxSlots], u[kMaxSlots], col[kMaxSlots];  // col: profile column or continuum index
+    int pcol[kMaxSlots];           // PRD line: emission-profile column, else -1
     AR cblu[kMaxSlots], cbul[kMaxSlots], ca[kMaxSlots], alpha[kMaxSlots];
 };
 
@@ -1228,6 +1646,7 @@ template <typename AR>
 struct EmIn {
     AR invT, kbg, dz;
     AR f[kMaxSlots];               // profile value (lines) or continuum G factor of the record
+    AR fs[kMaxSlots];              // emission-profile value (PRD lines; else f)
     AR nl[kMaxSlots], nu[kMaxSlots];
 };
 
@@ -1236,7 +1655,8 @@ struct EmIn {
 template <typename TB, typename AR>
 __device__ __forceinline__ void em_load(const TB *__restrict__ rec, const TB *__restrict__ phi,
                                         const TB *__restrict__ pops, int rec_w, int ray_cols, int L,
-                                        const EmTrans<AR> &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn<AR> &p) {
+                                        const EmTrans<AR> &et, int64_t g, int64_t gc, int64_t gc_dz, EmIn<AR> &p,
+                                        const TB *psi, int psi_cols) {
     const TB *r = rec + gc * rec_w;
     p.invT = static_cast<AR>(r[1]);
     p.kbg = static_cast<AR>(r[2]);
@@ -1249,6 +1669,7 @@ __device__ __forceinline__ void em_load(const TB *__restrict__ rec, const TB *__
             p.nl[q] = static_cast<AR>(n[et.l[q]]);
             p.nu[q] = static_cast<AR>(n[et.u[q]]);
             p.f[q] = static_cast<AR>(et.kind[q] == 0 ? pr[et.col[q]] : r[kRecHead + et.col[q]]);
+            p.fs[q] = et.pcol[q] >= 0 ? static_cast<AR>(psi[gc * psi_cols + et.pcol[q]]) : p.f[q];
         }
     }
 }
@@ -1270,8 +1691,8 @@ __device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &
             AR vlu, vul, U;
             if (et.kind[q] == 0) {
                 vlu = et.cblu[q] * in.f[q];
-                vul = et.cbul[q] * in.f[q];
-                U = et.ca[q] * in.f[q] * scale;
+                vul = et.cbul[q] * in.fs[q];
+                U = et.ca[q] * in.fs[q] * scale;
             } else {
                 vlu = et.alpha[q];
                 vul = in.f[q] * ex * et.alpha[q];
@@ -1289,6 +1710,8 @@ __device__ __forceinline__ void em_point(const EmIn<AR> &in, const EmTrans<AR> &
 template <typename TB, typename AR>
 __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restrict__ rec, const TB *__restrict__ phi,
                                                   const TB *__restrict__ pops) {
+    const TB *psi = reinterpret_cast<const TB *>(a.emis);
+    const int psi_cols = a.A.psi_cols;
     const DevAtom &A = a.A;
     const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
     const int rec_w = a.rec_w, ray_cols = A.ray_cols, L = A.L;
@@ -1310,8 +1733,10 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
                 et.kind[q] = tr.kind;
                 et.l[q] = tr.l;
                 et.u[q] = tr.u;
+                et.pcol[q] = -1;
                 if (tr.kind == 0) {
                     et.col[q] = tr.ray_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i];
+                    if (a.prd && tr.prd) et.pcol[q] = tr.psi_off + 2 * A.n_mu * tr.n_act + A.jact_ja[i];
                     const double c0 = tr.hnu4pi;
                     et.cblu[q] = static_cast<AR>(c0 * tr.Blu);
                     et.cbul[q] = static_cast<AR>(c0 * tr.Bul);
@@ -1324,6 +1749,10 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
             }
         }
         const ColGeom cg = geom(a, slot);
+        if (a.status[cg.col] == RH15D_BAD_INPUT) {
+            a.spectrum[(size_t)cg.col * A.NL + j] = NAN;
+            continue;
+        }
         const int N = cg.N;
         const int64_t g0 = cg.g0, gc0 = cg.gc0;
         // scaling exponent: h nu / k T at the column's hottest point (FP32 only)
@@ -1336,9 +1765,9 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
         const AR scale = sizeof(AR) == 8 ? AR(1) : d_exp(x0);
         EmIn<AR> in;
         AR chi2, S2, B2, chi, S, B;
-        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 2, in);
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 2, in, psi, psi_cols);
         em_point<AR>(in, et, hnu_k, two_hnu3, lamfac, x0, scale, chi2, S2, B2);
-        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 1, gc0 + N - 1, gc0 + N - 1, in);
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 1, gc0 + N - 1, gc0 + N - 1, in, psi, psi_cols);
         em_point<AR>(in, et, hnu_k, two_hnu3, lamfac, x0, scale, chi, S, B);
         const AR dtv = AR(0.5) * (chi + chi2) * in.dz;
         AR I = dtv > AR(0) ? B + (B - B2) / dtv : B;
@@ -1346,13 +1775,13 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
         // upward from k = N - 2 to the top; the step from k + 1 uses the
         // spacing stored with point k + 1
         EmIn<AR> nxt;
-        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt);
+        em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + N - 2, gc0 + N - 2, gc0 + N - 1, nxt, psi, psi_cols);
         for (int k = N - 2; k >= 0; k--) {
             const EmIn<AR> cur = nxt;
             // issued on every step (the last one reloads the top point), so
             // the wait for this point's values leaves it in flight
             const int kn = k > 0 ? k - 1 : 0;
-            em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + kn, gc0 + kn, gc0 + kn + 1, nxt);
+            em_load<TB, AR>(rec, phi, pops, rec_w, ray_cols, L, et, g0 + kn, gc0 + kn, gc0 + kn + 1, nxt, psi, psi_cols);
             em_point<AR>(cur, et, hnu_k, two_hnu3, lamfac, x0, scale, chi, S, B);
             const AR x = AR(0.5) * (chi_p + chi) * cur.dz;
             AR e, wa, wb;
@@ -1377,7 +1806,7 @@ __global__ __launch_bounds__(256) void k_psi_gather(RunArgs a) {
         const R *part = reinterpret_cast<const R *>(a.part) + cg.gc0 * A.n_keys;
         double s = 0.0;
         for (int i = A.p_off[t]; i < A.p_off[t + 1]; i++) s += static_cast<double>(part[(size_t)A.p_key[i] * cg.N + k]);
-        a.psi[(cg.g0 + k) * A.T + t] = s;
+        a.psi[(cg.g0 + k) * A.T + t] = a.status[cg.col] == RH15D_BAD_INPUT ? NAN : s;
     }
 }
 
@@ -1440,11 +1869,22 @@ __global__ void k_init_slots(RunArgs a) {
         a.slot_it[slot] = 0;
         a.ng_count[slot] = 0;
         a.ng_head[slot] = 0;
+        a.slot_dprev[slot] = -1.0;
         a.status[c] = RH15D_MAX_ITER;
         a.n_iter[c] = 0;
         if (a.history)
             for (int k = 0; k < a.max_iter; k++) a.history[(size_t)c * a.max_iter + k] = NAN;
-        if (a.max_iter == 0) {
+        if (a.slot_bad[slot]) {
+            // unusable column data: no iteration, NaN populations (the
+            // emergent-spectrum and Psi* outputs of the column are NaN too)
+            a.slot_bad[slot] = 0;
+            a.status[c] = RH15D_BAD_INPUT;
+            const int64_t g0 = a.doff[c], g1 = a.doff[c + 1];
+            for (int64_t g = g0; g < g1; g++)
+                for (int l = 0; l < a.A.L; l++) a.pops[g * a.A.L + l] = NAN;
+            a.slot_state[slot] = SLOT_DONE;
+            a.retire_list[atomicAdd(&a.ctr[CTR_RETIRE], 1)] = slot;
+        } else if (a.max_iter == 0) {
             a.slot_state[slot] = SLOT_DONE;
             a.retire_list[atomicAdd(&a.ctr[CTR_RETIRE], 1)] = slot;
         } else {
@@ -1457,6 +1897,8 @@ __global__ void k_setup(RunArgs a) {
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < a.S; s += gridDim.x * blockDim.x) {
         a.slot_state[s] = SLOT_FREE;
         a.slot_col[s] = 0;
+        a.slot_bad[s] = 0;
+        a.slot_dprev[s] = -1.0;
     }
     if (blockIdx.x == 0 && threadIdx.x < CTR_COUNT) a.ctr[threadIdx.x] = 0;
 }
@@ -1578,7 +2020,8 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     permute(H.groups, 1);
     permute(H.lane_j, kWave); permute(H.lane_m0, kWave); permute(H.lane_lamfac, kWave);
     permute(H.lane_hnu_k, kWave); permute(H.lane_2hnu3c2, kWave);
-    permute(H.pbase, kWave * kMaxSlots); permute(H.wj, kWave * kMaxSlots);
+    permute(H.pbase, kWave * kMaxSlots); permute(H.wj, kWave * kMaxSlots); permute(H.psb, kWave * kMaxSlots);
+    permute(H.lane_ist, kWave);
     permute(H.kapj, kWave * kMaxSlots); permute(H.alpha, kWave * kMaxSlots);
     DevAtom D{};
     D.L = atom->L; D.n_lines = atom->n_lines; D.n_cont = atom->n_cont;
@@ -1592,6 +2035,10 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     }
     D.mass = atom->mass; D.abund = atom->abund; D.c_bg = atom->c_bg; D.bg_kind = atom->bg_kind;
     std::vector<DevTransition> tr(D.T);
+    std::vector<int> prd_t;
+    D.psi_cols = H.psi_cols;
+    D.ist_cols = H.ist_cols;
+    D.g_cols = 0;
     std::vector<int> act_j;
     std::vector<double> act_w;
     int ray_off = 0;
@@ -1606,6 +2053,15 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
         if (h.kind == 0) ray_off += (2 * n_mu + 1) * d.n_act;
         d.nu0 = h.nu0; d.A = h.A; d.Bul = h.Bul; d.Blu = h.Blu; d.alpha0 = h.alpha0; d.coll_val = h.coll_val;
         d.gamma = h.gamma; d.hnu4pi = kH * h.nu0 / (4.0 * kPI);
+        d.c_el = h.c_el;
+        d.prd = h.kind == 0 && h.prd;
+        d.psi_off = H.psi_off[t];
+        d.g_off = -1;
+        if (d.prd) {
+            d.g_off = D.g_cols;
+            D.g_cols += d.n_act * d.n_act;
+            prd_t.push_back(t);
+        }
         d.wsum = 0.0;
         for (double w : h.w) d.wsum += w;
         act_j.insert(act_j.end(), h.act.begin(), h.act.end());
@@ -1613,6 +2069,12 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
         tr[t] = d;
     }
     if (ray_off != H.ray_cols) { set_error("internal: ray table mismatch"); return RH15D_EINVAL; }
+    D.n_prd = static_cast<int>(prd_t.size());
+    for (const auto &d : tr)
+        if (d.prd && d.n_act > kMaxPrdFreq) {
+            set_error("a PRD line has %d wavelengths (limit %d)", d.n_act, kMaxPrdFreq);
+            return RH15D_EINVAL;
+        }
     for (const auto &d : tr)
         if (d.kind == 0 && (2 * n_mu + 1) * d.n_act > kMaxLineRays) {
             set_error("a line has %d rays per depth (limit %d)", (2 * n_mu + 1) * d.n_act, kMaxLineRays);
@@ -1684,6 +2146,12 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     UP(H.lane_j, &D.lanes.j); UP(H.lane_m0, &D.lanes.m0);
     UP(H.lane_lamfac, &D.lanes.lamfac); UP(H.lane_hnu_k, &D.lanes.hnu_k); UP(H.lane_2hnu3c2, &D.lanes.two_hnu3c2);
     UP(H.pbase, &D.lanes.pbase); UP(H.wj, &D.lanes.wj); UP(H.kapj, &D.lanes.kapj); UP(H.alpha, &D.lanes.alpha);
+    UP(H.psb, &D.lanes.psb); UP(H.lane_ist, &D.lanes.ist);
+    {
+        std::vector<int> pt(prd_t), si(H.st_idx);
+        if (pt.empty()) pt.push_back(-1);
+        UP(pt, &D.prd_t); UP(si, &D.st_idx);
+    }
     UP(H.p_off, &D.p_off); UP(H.p_key, &D.p_key); UP(H.q_off, &D.q_off); UP(H.q_key, &D.q_key);
     D.n_xpairs = static_cast<int>(H.x_t.size());
     UP(H.x_t, &D.x_t); UP(H.x_t2, &D.x_t2); UP(H.x_off, &D.x_off); UP(H.x_key, &D.x_key);
@@ -1734,6 +2202,14 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
 // (the fastest shape measured for the six-level atom on MI355X).
 SweepShape pick_shape(rh15d_atom *atom, const rh15d_options *o) {
     SweepShape sh;
+    bool any_prd = false;
+    for (const auto &t : atom->tr) any_prd |= t.kind == 0 && t.prd;
+    if (o->prd && any_prd) {
+        // the partial-frequency-redistribution sweep carries one angle per lane
+        sh.mc = 1;
+        sh.pack = o->sweep_pack > 0 ? o->sweep_pack - 1 : 1;
+        return sh;
+    }
     sh.mc = o->sweep_mc > 0 ? o->sweep_mc : 1;
     sh.pack = o->sweep_pack > 0 ? o->sweep_pack - 1 : 1;
     if (o->sweep_mc <= 0 && o->sweep_pack <= 0) {
@@ -1749,12 +2225,13 @@ SweepShape pick_shape(rh15d_atom *atom, const rh15d_options *o) {
 
 struct Layout {
     size_t off_doff, off_lnr, off_kbg, off_gr, off_norm, off_phi, off_part, off_rec, off_popsf, off_rad, off_nse, off_dk,
-        off_flag, off_ring, off_slots, off_ctr, off_lists, total;
+        off_flag, off_ring, off_slots, off_dprev, off_ctr, off_lists, off_psi, off_ist, off_gtab, off_rho, total;
 };
+constexpr int kSlotInts = 6;   // per-slot int arrays: column, state, iteration, Ng count, Ng head, bad input
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(const DevAtom &D, int64_t n_columns, int S, int ND, bool fp32, bool ng) {
+Layout make_layout(const DevAtom &D, int64_t n_columns, int S, int ND, bool fp32, bool ng, bool prd) {
     const size_t R = fp32 ? 4 : 8;
     const size_t P = (size_t)S * ND;
     Layout l{};
@@ -1774,9 +2251,15 @@ Layout make_layout(const DevAtom &D, int64_t n_columns, int S, int ND, bool fp32
     l.off_dk = take(P * 8);
     l.off_flag = take(P * 4);
     l.off_ring = take(ng ? 4 * P * D.L * 8 : 8);
-    l.off_slots = take((size_t)S * 5 * 4);
+    l.off_slots = take((size_t)S * kSlotInts * 4);
+    l.off_dprev = take((size_t)S * 8);
     l.off_ctr = take(CTR_COUNT * 4);
     l.off_lists = take((size_t)S * 2 * 4);
+    // partial frequency redistribution
+    l.off_psi = take(prd ? P * D.psi_cols * R : 8);
+    l.off_ist = take(prd ? P * D.ist_cols * R : 8);
+    l.off_gtab = take(prd ? P * D.g_cols * R : 8);
+    l.off_rho = take(prd ? P * (D.psi_cols / (2 * D.n_mu + 1)) * 8 : 8);
     l.total = o;
     return l;
 }
@@ -1789,7 +2272,12 @@ int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_opti
     if (o->ng_order != 0 && o->ng_order != 2) { set_error("ng_order must be 0 or 2"); return RH15D_EINVAL; }
     if (o->max_iter < 0) { set_error("max_iter must be >= 0"); return RH15D_EINVAL; }
     if (o->precision != RH15D_FP64 && o->precision != RH15D_FP32) { set_error("unknown precision"); return RH15D_EINVAL; }
-    if (o->start < 0 || o->start > 2) { set_error("unknown start"); return RH15D_EINVAL; }
+    if (o->start < 0 || o->start > 3) { set_error("unknown start"); return RH15D_EINVAL; }
+    if (!(o->tol_fp >= 0.0) || !std::isfinite(o->tol_fp)) { set_error("tol_fp must be finite and >= 0"); return RH15D_EINVAL; }
+    if (o->esc_iter < 0 || o->esc_iter > 100) { set_error("esc_iter must be in 0..100"); return RH15D_EINVAL; }
+    if (o->prd != 0 && o->prd != 1) { set_error("prd must be 0 or 1"); return RH15D_EINVAL; }
+    if (!std::isfinite(o->prd_eps0)) { set_error("prd_eps0 must be finite"); return RH15D_EINVAL; }
+    if (o->prd && o->sweep_mc > 1) { set_error("partial frequency redistribution needs sweep_mc 0 or 1"); return RH15D_EINVAL; }
     if (o->scheduler != RH15D_SCHED_CHUNKED && o->scheduler != RH15D_SCHED_SLOTS) { set_error("unknown scheduler"); return RH15D_EINVAL; }
     if (o->batch_columns < 0) { set_error("batch_columns must be >= 0"); return RH15D_EINVAL; }
     if (o->sweep_mc < 0 || (o->sweep_mc > 0 && o->n_mu % o->sweep_mc != 0) ||
@@ -1817,12 +2305,15 @@ int max_depth(const rh15d_columns *cols) {
     return (int)nd;
 }
 
+// Partial frequency redistribution is on when asked for and the atom has PRD lines.
+bool prd_active(const DevAtom &D, const rh15d_options *o) { return o->prd != 0 && D.n_prd > 0; }
+
 // Resident columns: the caller's choice, else as many as fit a 40 GiB
 // working set (the device has 288 GB of HBM), at most 8192.
 int slot_count(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o, int ND) {
     const int64_t n = std::max<int64_t>(cols->n_columns, 1);
     if (o->batch_columns > 0) return (int)std::min<int64_t>(o->batch_columns, n);
-    const Layout one = make_layout(D, 0, 1, ND, o->precision == RH15D_FP32, o->ng_order == 2);
+    const Layout one = make_layout(D, 0, 1, ND, o->precision == RH15D_FP32, o->ng_order == 2, prd_active(D, o));
     const size_t budget = size_t(40) << 30;
     int64_t S = std::max<int64_t>(1, (int64_t)(budget / one.total));
     return (int)std::min<int64_t>(std::min<int64_t>(S, 8192), n);
@@ -1833,9 +2324,11 @@ unsigned grid_for(int64_t work, int per_block, unsigned cap) {
 }
 
 template <int L>
-void launch_se_l(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
-    if (zero) {
-        hipLaunchKernelGGL(k_se_zero_radiation<L>, dim3(grid_for((int64_t)a.S * a.ND, 256, 16384)), dim3(256), 0, st, a);
+void launch_se_l(RunArgs &a, bool fp32, int kind, hipStream_t st) {
+    if (kind != SE_ITERATION) {
+        const dim3 grid(grid_for((int64_t)a.S * a.ND, 256, 16384));
+        if (kind == SE_ESCAPE) hipLaunchKernelGGL((k_se_start<L, SE_ESCAPE>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_se_start<L, SE_ZERO_RADIATION>), grid, dim3(256), 0, st, a);
         return;
     }
     const unsigned blocks = grid_for((int64_t)a.S * a.ND, 256, 1u << 30);
@@ -1845,37 +2338,37 @@ void launch_se_l(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
     else hipLaunchKernelGGL((k_se<double, L>), dim3(blocks), dim3(256), 0, st, a);
 }
 
-void launch_se(RunArgs &a, bool fp32, bool zero, hipStream_t st) {
+void launch_se(RunArgs &a, bool fp32, int kind, hipStream_t st) {
     switch (a.A.L) {
-        case 2: launch_se_l<2>(a, fp32, zero, st); break;
-        case 3: launch_se_l<3>(a, fp32, zero, st); break;
-        case 4: launch_se_l<4>(a, fp32, zero, st); break;
-        case 5: launch_se_l<5>(a, fp32, zero, st); break;
-        case 6: launch_se_l<6>(a, fp32, zero, st); break;
-        case 7: launch_se_l<7>(a, fp32, zero, st); break;
-        default: launch_se_l<8>(a, fp32, zero, st); break;
+        case 2: launch_se_l<2>(a, fp32, kind, st); break;
+        case 3: launch_se_l<3>(a, fp32, kind, st); break;
+        case 4: launch_se_l<4>(a, fp32, kind, st); break;
+        case 5: launch_se_l<5>(a, fp32, kind, st); break;
+        case 6: launch_se_l<6>(a, fp32, kind, st); break;
+        case 7: launch_se_l<7>(a, fp32, kind, st); break;
+        default: launch_se_l<8>(a, fp32, kind, st); break;
     }
 }
 
-template <typename R, int MODE, int NS, int NC, int MC>
+template <typename R, int MODE, int NS, int NC, int MC, bool PRD>
 void launch_sweep_range(const RunArgs &a, hipStream_t st) {
     const int id = group_class(NS, NC);
     const int gb = a.A.g_begin[id], ge = a.A.g_begin[id + 1];
     if (ge <= gb) return;
     const R *popsb = sizeof(R) == 8 ? reinterpret_cast<const R *>(a.pops) : reinterpret_cast<const R *>(a.popsf);
-    hipLaunchKernelGGL((k_sweep<R, MODE, NS, NC, MC>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb, ge,
-                       reinterpret_cast<const R *>(a.rec), reinterpret_cast<const R *>(a.phi), popsb,
+    hipLaunchKernelGGL((k_sweep<R, MODE, NS, NC, MC, PRD>), dim3((ge - gb + 3) / 4, a.S), dim3(256), 0, st, a, gb,
+                       ge, reinterpret_cast<const R *>(a.rec), reinterpret_cast<const R *>(a.phi), popsb,
                        reinterpret_cast<R *>(a.part));
 }
 
 // every (slots, continua) class of NS slots, in class order
-template <typename R, int MODE, int NS, int MC>
+template <typename R, int MODE, int NS, int MC, bool PRD>
 void launch_sweep_ns(const RunArgs &a, hipStream_t st) {
-    launch_sweep_range<R, MODE, NS, 0, MC>(a, st);
-    launch_sweep_range<R, MODE, NS, 1, MC>(a, st);
-    if constexpr (NS >= 2) launch_sweep_range<R, MODE, NS, 2, MC>(a, st);
-    if constexpr (NS >= 3) launch_sweep_range<R, MODE, NS, 3, MC>(a, st);
-    if constexpr (NS >= 4) launch_sweep_range<R, MODE, NS, 4, MC>(a, st);
+    launch_sweep_range<R, MODE, NS, 0, MC, PRD>(a, st);
+    launch_sweep_range<R, MODE, NS, 1, MC, PRD>(a, st);
+    if constexpr (NS >= 2) launch_sweep_range<R, MODE, NS, 2, MC, PRD>(a, st);
+    if constexpr (NS >= 3) launch_sweep_range<R, MODE, NS, 3, MC, PRD>(a, st);
+    if constexpr (NS >= 4) launch_sweep_range<R, MODE, NS, 4, MC, PRD>(a, st);
 }
 
 // The launches for the different slot counts touch disjoint rate sums, so
@@ -1905,24 +2398,24 @@ struct SideStreams {
     }
 };
 
-template <typename R, int MODE, int MC>
+template <typename R, int MODE, int MC, bool PRD = false>
 void launch_sweep_mc(const RunArgs &a, hipStream_t st, SideStreams *side) {
     int used = 0;
     for (int ns = 1; ns <= kMaxSlots; ns++)
         used += a.A.g_begin[group_class(ns + 1, 0)] > a.A.g_begin[group_class(ns, 0)];
     if (!side || !side->on || used < 2) {
-        launch_sweep_ns<R, MODE, 1, MC>(a, st);
-        launch_sweep_ns<R, MODE, 2, MC>(a, st);
-        launch_sweep_ns<R, MODE, 3, MC>(a, st);
-        launch_sweep_ns<R, MODE, 4, MC>(a, st);
+        launch_sweep_ns<R, MODE, 1, MC, PRD>(a, st);
+        launch_sweep_ns<R, MODE, 2, MC, PRD>(a, st);
+        launch_sweep_ns<R, MODE, 3, MC, PRD>(a, st);
+        launch_sweep_ns<R, MODE, 4, MC, PRD>(a, st);
         return;
     }
     (void)hipEventRecord(side->fork, st);
     for (int i = 0; i < kMaxSlots; i++) (void)hipStreamWaitEvent(side->s[i], side->fork, 0);
-    launch_sweep_ns<R, MODE, 1, MC>(a, side->s[0]);
-    launch_sweep_ns<R, MODE, 2, MC>(a, side->s[1]);
-    launch_sweep_ns<R, MODE, 3, MC>(a, side->s[2]);
-    launch_sweep_ns<R, MODE, 4, MC>(a, side->s[3]);
+    launch_sweep_ns<R, MODE, 1, MC, PRD>(a, side->s[0]);
+    launch_sweep_ns<R, MODE, 2, MC, PRD>(a, side->s[1]);
+    launch_sweep_ns<R, MODE, 3, MC, PRD>(a, side->s[2]);
+    launch_sweep_ns<R, MODE, 4, MC, PRD>(a, side->s[3]);
     for (int i = 0; i < kMaxSlots; i++) {
         (void)hipEventRecord(side->join[i], side->s[i]);
         (void)hipStreamWaitEvent(st, side->join[i], 0);
@@ -1931,6 +2424,8 @@ void launch_sweep_mc(const RunArgs &a, hipStream_t st, SideStreams *side) {
 
 template <typename R, int MODE>
 void launch_sweep(const RunArgs &a, hipStream_t st, SideStreams *side) {
+    // partial frequency redistribution: one angle per lane (the solve forces it)
+    if (a.prd) { launch_sweep_mc<R, MODE, 1, true>(a, st, side); return; }
     switch (a.A.mc) {
         case 5: launch_sweep_mc<R, MODE, 5>(a, st, side); break;
         case 3: launch_sweep_mc<R, MODE, 3>(a, st, side); break;
@@ -1940,7 +2435,9 @@ void launch_sweep(const RunArgs &a, hipStream_t st, SideStreams *side) {
 
 struct Launcher {
     RunArgs a;
-    bool fp32, zero_start, want_spec, want_psi;
+    bool fp32;
+    int start;
+    bool want_spec, want_psi;
     hipStream_t st;
     SideStreams *side = nullptr;
 
@@ -1954,7 +2451,17 @@ struct Launcher {
             if (fp32) hipLaunchKernelGGL(k_prep_profile<float>, dim3(pb), dim3(256), 0, st, a);
             else hipLaunchKernelGGL(k_prep_profile<double>, dim3(pb), dim3(256), 0, st, a);
         }
-        if (zero_start) launch_se(a, fp32, true, st);
+        if (a.prd) {
+            const unsigned tb = grid_for(pts * a.A.n_prd, 1, 1u << 20);
+            if (fp32) hipLaunchKernelGGL(k_prd_tables<float>, dim3(tb), dim3(64), 0, st, a);
+            else hipLaunchKernelGGL(k_prd_tables<double>, dim3(tb), dim3(64), 0, st, a);
+        }
+        if (start == RH15D_START_ZERO_RADIATION) launch_se(a, fp32, SE_ZERO_RADIATION, st);
+        if (start == RH15D_START_ESCAPE)
+            for (int i = 0; i < a.esc_iter; i++) {
+                hipLaunchKernelGGL(k_escape_beta, dim3(grid_for((int64_t)a.S * a.A.T, 256, 4096)), dim3(256), 0, st, a);
+                launch_se(a, fp32, SE_ESCAPE, st);
+            }
         hipLaunchKernelGGL(k_init_slots, dim3(grid_for(a.S, 256, 1024)), dim3(256), 0, st, a);
         (void)tm;
     }
@@ -1964,9 +2471,22 @@ struct Launcher {
         if (fp32) launch_sweep<float, MODE_RATES>(a, st, side);
         else launch_sweep<double, MODE_RATES>(a, st, side);
         if (tm) tm->mark(3, st);
-        launch_se(a, fp32, false, st);
+        launch_se(a, fp32, SE_ITERATION, st);
         if (tm) tm->mark(4, st);
         hipLaunchKernelGGL(k_converge, dim3(a.S), dim3(kConvThreads), 0, st, a);
+        if (a.prd) {
+            // rho of the slots still iterating, then their emission profiles
+            const int64_t pts = (int64_t)a.S * a.ND;
+            const unsigned rb = grid_for(pts * a.A.n_prd, 4, 65536);
+            const unsigned pb = grid_for(pts * a.A.psi_cols, 256, 65536);
+            if (fp32) {
+                hipLaunchKernelGGL(k_prd_rho<float>, dim3(rb), dim3(256), 0, st, a);
+                hipLaunchKernelGGL(k_prd_psi<float>, dim3(pb), dim3(256), 0, st, a);
+            } else {
+                hipLaunchKernelGGL(k_prd_rho<double>, dim3(rb), dim3(256), 0, st, a);
+                hipLaunchKernelGGL(k_prd_psi<double>, dim3(pb), dim3(256), 0, st, a);
+            }
+        }
         if (tm) tm->mark(5, st);
         if (want_spec) {
             const unsigned eb = grid_for((int64_t)a.S * a.A.NL, 256, 8192);
@@ -2056,6 +2576,10 @@ int rh15d_default_options(rh15d_options *o) {
     o->profile = 0;
     o->sweep_mc = 0;
     o->sweep_pack = 0;
+    o->tol_fp = 0.0;
+    o->esc_iter = 3;
+    o->prd = 0;
+    o->prd_eps0 = 0.0;
     return RH15D_OK;
 }
 
@@ -2068,7 +2592,8 @@ int rh15d_workspace_size(const rh15d_atom *atom_c, const rh15d_columns *cols, co
     if ((rc = get_dev_atom(atom_m, o->n_mu, pick_shape(atom_m, o), &D)) != RH15D_OK) return rc;
     const int ND = max_depth(cols);
     const int S = slot_count(*D, cols, o, ND);
-    *bytes = make_layout(*D, cols->n_columns, S, ND, o->precision == RH15D_FP32, o->ng_order == 2).total;
+    *bytes = make_layout(*D, cols->n_columns, S, ND, o->precision == RH15D_FP32, o->ng_order == 2,
+                         prd_active(*D, o)).total;
     return RH15D_OK;
 }
 
@@ -2088,7 +2613,8 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     const bool fp32 = o->precision == RH15D_FP32;
     const int ND = max_depth(cols);
     const int S = slot_count(*D, cols, o, ND);
-    const Layout lay = make_layout(*D, cols->n_columns, S, ND, fp32, o->ng_order == 2);
+    const bool prd = prd_active(*D, o);
+    const Layout lay = make_layout(*D, cols->n_columns, S, ND, fp32, o->ng_order == 2, prd);
     if (workspace && workspace_bytes < lay.total) {
         set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total);
         return RH15D_ENOMEM;
@@ -2122,6 +2648,8 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     int *slots = reinterpret_cast<int *>(ws + lay.off_slots);
     a.slot_col = slots; a.slot_state = slots + S; a.slot_it = slots + 2 * S; a.ng_count = slots + 3 * S;
     a.ng_head = slots + 4 * S;
+    a.slot_bad = slots + 5 * S;
+    a.slot_dprev = reinterpret_cast<double *>(ws + lay.off_dprev);
     a.ctr = reinterpret_cast<int *>(ws + lay.off_ctr);
     a.retire_list = reinterpret_cast<int *>(ws + lay.off_lists);
     a.refill_list = a.retire_list + S;
@@ -2140,9 +2668,12 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     a.ring = reinterpret_cast<double *>(ws + lay.off_ring);
     a.max_iter = o->max_iter; a.ng_order = o->ng_order; a.ng_delay = o->ng_delay; a.ng_period = o->ng_period;
     a.start = o->start; a.tol = o->tol; a.coll_scale = o->coll_scale; a.crs_f0 = o->crs_f0;
+    a.tol_fp = o->tol_fp; a.esc_iter = o->esc_iter;
+    a.prd = prd ? 1 : 0; a.prd_eps0 = o->prd_eps0;
+    a.emis = ws + lay.off_psi; a.ist = ws + lay.off_ist; a.gtab = ws + lay.off_gtab;
+    a.rho = reinterpret_cast<double *>(ws + lay.off_rho);
 
-    Launcher run{a, fp32, o->start == RH15D_START_ZERO_RADIATION, out->spectrum != nullptr, out->psi_star != nullptr,
-                 st};
+    Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr, st};
     Timer tm;
     if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
     SideStreams side;
@@ -2179,6 +2710,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
             if (exec) {
                 e = hipGraphLaunch(exec, st);
                 if (e != hipSuccess) { fail(e, "graph launch"); break; }
+                g_stats.graph_launches++;
             } else {
                 run.iteration(tp);
             }

@@ -42,7 +42,9 @@ struct HostTransition {
     int kind = 0;  // 0 line, 1 continuum
     int l = 0, u = 0;
     double f = 0, alpha0 = 0, coll_val = 0;
+    double c_el = 0;          // elastic-collision rate per hydrogen atom, m^3 s^-1
     int voigt = 0, coll_kind = 0;
+    int prd = 0;              // line with partial frequency redistribution
     std::vector<double> own;  // own sampling, m
     // derived
     double nu0 = 0, A = 0, Bul = 0, Blu = 0, gamma = 0, lam_min = 0, lam_max = 0;
@@ -54,10 +56,12 @@ struct HostTransition {
 struct DevTransition {
     int kind, l, u, voigt;
     int coll_kind, n_act, act_off, ray_off;  // ray_off: offset of this line's rays in a depth row
+    int prd, psi_off;                         // PRD line: offset of its rays in the emission-profile row, else -1
+    int g_off, pad0;                          // PRD line: offset of its redistribution weights per depth
     double nu0, A, Bul, Blu;                  // Einstein coefficients (per unit frequency)
     double alpha0, coll_val, gamma, hnu4pi;   // hnu4pi = h nu0 / (4 pi)
     double wsum;                              // sum of the trapezoid weights
-    double pad;
+    double c_el;                              // elastic-collision rate per hydrogen atom
 };
 
 // A group: up to 64 rays of one direction sharing one set of transitions.
@@ -87,6 +91,8 @@ struct DevLanes {
     double *wj;       // frequency weight w(t, j)
     double *kapj;     // 4 pi w(t, j) / (2 h nu_t): times w_mu gives the rate weight
     double *alpha;    // continuum cross-section at nu_j
+    int *psb;         // per slot: PRD line: emission-profile column of the lane's first angle; else -1
+    int *ist;         // stored-intensity column of the lane's first angle (step 2 per angle), or -1
 };
 // Everything the kernels need about an atom and an angle quadrature.
 struct DevAtom {
@@ -122,6 +128,13 @@ struct DevAtom {
     // i * L + j, +xpair+1 adds, -(xpair+1) subtracts)
     int *up_t, *dn_t;           // [L * L]
     int *xe_off, *xe_val;       // [L * L + 1], [...]
+    // partial frequency redistribution (PRD lines of the atom)
+    int n_prd;                  // PRD lines
+    int psi_cols;               // emission-profile (psi = rho phi) values per depth row
+    int ist_cols;               // stored intensities per depth row: (stored wavelength, angle, direction)
+    int g_cols;                 // redistribution weights per depth row: sum over PRD lines of n_act^2
+    int *prd_t;                 // [n_prd] line index of each PRD line
+    int *st_idx;                // [NL] stored-wavelength index of each wavelength, or -1
     // algorithmic work of one rate-mode sweep per depth point of a column
     double rays_per_depth;        // rays (wavelength x angle x direction)
     double flops_per_depth;       // see k_raysweep: 27 + 19 n_slots + 4 n_pairs per ray-step
@@ -139,7 +152,9 @@ struct SweepShape {
 
 struct HostGroupTables {
     std::vector<DevGroup> groups;
-    std::vector<int> lane_j, lane_m0, pbase;
+    std::vector<int> lane_j, lane_m0, pbase, psb, lane_ist;
+    std::vector<int> psi_off, st_idx;   // per transition; per wavelength
+    int psi_cols = 0, ist_cols = 0;
     std::vector<double> lane_lamfac, lane_hnu_k, lane_2hnu3c2, wj, kapj, alpha;
     std::vector<int> p_off, p_key, q_off, q_key, x_t, x_t2, x_off, x_key;
     int n_keys = 0, ray_cols = 0;

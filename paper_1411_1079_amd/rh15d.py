@@ -17,9 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librh15d.so")
 
 FP64, FP32 = 0, 1
-START_LTE, START_ZERO_RADIATION, START_PROVIDED = 0, 1, 2
+START_LTE, START_ZERO_RADIATION, START_PROVIDED, START_ESCAPE = 0, 1, 2, 3
 SCHED_CHUNKED, SCHED_SLOTS = 0, 1
-CONVERGED, MAX_ITER, NONFINITE, SINGULAR = 0, 1, 2, 3
+CONVERGED, MAX_ITER, NONFINITE, SINGULAR, BAD_INPUT = 0, 1, 2, 3, 4
 
 EXPORTS = (
     "rh15d_load_atom", "rh15d_free_atom", "rh15d_atom_get_info", "rh15d_atom_lambda", "rh15d_default_options",
@@ -45,14 +45,15 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_mu", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("ng_order", C.c_int), ("ng_delay", C.c_int), ("ng_period", C.c_int), ("start", C.c_int),
                 ("coll_scale", C.c_double), ("scheduler", C.c_int), ("batch_columns", C.c_int),
-                ("profile", C.c_int), ("sweep_mc", C.c_int), ("sweep_pack", C.c_int), ("crs_f0", C.c_double)]
+                ("profile", C.c_int), ("sweep_mc", C.c_int), ("sweep_pack", C.c_int), ("crs_f0", C.c_double),
+                ("tol_fp", C.c_double), ("esc_iter", C.c_int), ("prd", C.c_int), ("prd_eps0", C.c_double)]
 
 
 class Stats(C.Structure):
     _fields_ = [("sweep_launches", C.c_int64), ("sweep_ms", C.c_double), ("se_ms", C.c_double),
                 ("converge_ms", C.c_double), ("prep_ms", C.c_double), ("final_ms", C.c_double),
                 ("total_ms", C.c_double), ("column_iterations", C.c_int64), ("ray_steps", C.c_int64),
-                ("sweep_flops", C.c_double), ("sweep_bytes", C.c_double)]
+                ("sweep_flops", C.c_double), ("sweep_bytes", C.c_double), ("graph_launches", C.c_int64)]
 
 
 TUNE_MAX = 6
@@ -143,7 +144,8 @@ class Atom:
 
 
 def last_stats() -> dict:
-    """Measurements of this thread's last solve made with profile=1."""
+    """Measurements of this thread's last solve: times and work counts when
+    it ran with profile=1, graph_launches always."""
     st = Stats()
     _check(lib().rh15d_last_stats(C.byref(st)))
     return {name: getattr(st, name) for name, _ in Stats._fields_}
@@ -260,45 +262,54 @@ def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stre
     """Solve again, with the option set `opts`, every column of `dc` whose
     status in the result `out` (the dict of CUDA tensors that solve() or
     Solver.result() returns) is not converged, and write the new results
-    into `out`; n_iter then counts the iterations of both attempts.  The
-    paper's code re-runs failed columns with other options (Sec. 2.3,
-    convergence aids); here any option set can serve, e.g. the LTE start,
-    collisional-radiative switching or a larger iteration limit.  The
-    history rows of those columns become the second attempt's.  Returns
-    the number of columns solved again (a host synchronisation)."""
+    into `out`.  The paper's code re-runs failed columns with other options
+    (Sec. 2.3, convergence aids); here any option set can serve, e.g. the
+    LTE start, collisional-radiative switching or a larger iteration limit.
+    n_iter then counts the iterations of both attempts, and the history row
+    of such a column holds the first attempt's changes followed by the
+    second attempt's, as far as the row's width allows.  Columns with
+    unusable data (status BAD_INPUT) are not solved again.  Every step runs
+    on `stream` (default: the current stream).  Returns the number of
+    columns solved again (a host synchronisation)."""
     import torch
-    bad = torch.nonzero(out["status"] != CONVERGED).flatten().cpu().numpy()
-    if bad.size == 0:
-        return 0
-    off = dc.offset
-    lens = np.diff(off)[bad]
-    idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in bad])
     dev = dc.z.device
-    it = torch.as_tensor(idx, dtype=torch.int64, device=dev)
-    fields = {k: torch.index_select(getattr(dc, k), 0, it) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
-    init = None
-    if opts.start == START_PROVIDED:
-        if dc.init_pops is None:
-            raise ValueError("a provided start needs the columns' init_pops")
-        init = torch.index_select(dc.init_pops, 0, it)
-    sub = DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), init_pops=init, **fields)
-    r = Solver(atom, sub, opts, want_spectrum=out.get("spectrum") is not None,
-               want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None).run(stream)
-    cb = torch.as_tensor(bad, dtype=torch.int64, device=dev)
-    out["pops"].index_copy_(0, it, r.pops)
-    if out.get("psi_star") is not None:
-        out["psi_star"].index_copy_(0, it, r.psi_star)
-    if out.get("spectrum") is not None:
-        out["spectrum"].index_copy_(0, cb, r.spectrum)
-    if out.get("history") is not None:
-        # the second attempt's history, cut or padded (NaN) to the width of out
-        h = out["history"]
-        rows = torch.full((bad.size, h.shape[1]), float("nan"), dtype=h.dtype, device=dev)
-        w = min(h.shape[1], r.history.shape[1])
-        rows[:, :w] = r.history[:, :w]
-        h.index_copy_(0, cb, rows)
-    out["n_iter"].index_copy_(0, cb, out["n_iter"].index_select(0, cb) + r.n_iter)
-    out["status"].index_copy_(0, cb, r.status)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.stream(st):
+        status = out["status"]
+        bad = torch.nonzero((status != CONVERGED) & (status != BAD_INPUT)).flatten().cpu().numpy()
+        if bad.size == 0:
+            return 0
+        off = dc.offset
+        lens = np.diff(off)[bad]
+        idx = np.concatenate([np.arange(off[c], off[c + 1]) for c in bad])
+        it = torch.as_tensor(idx, dtype=torch.int64, device=dev)
+        fields = {k: torch.index_select(getattr(dc, k), 0, it) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+        init = None
+        if opts.start == START_PROVIDED:
+            if dc.init_pops is None:
+                raise ValueError("a provided start needs the columns' init_pops")
+            init = torch.index_select(dc.init_pops, 0, it)
+        sub = DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), init_pops=init, **fields)
+        r = Solver(atom, sub, opts, want_spectrum=out.get("spectrum") is not None,
+                   want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None).run(st)
+        cb = torch.as_tensor(bad, dtype=torch.int64, device=dev)
+        out["pops"].index_copy_(0, it, r.pops)
+        if out.get("psi_star") is not None:
+            out["psi_star"].index_copy_(0, it, r.psi_star)
+        if out.get("spectrum") is not None:
+            out["spectrum"].index_copy_(0, cb, r.spectrum)
+        n1 = out["n_iter"].index_select(0, cb)
+        if out.get("history") is not None:
+            # the first attempt's n1 entries, then the second attempt's
+            h = out["history"]
+            rows = h.index_select(0, cb)
+            for i, n in enumerate(n1.cpu().tolist()):
+                w = min(h.shape[1] - n, r.history.shape[1])
+                if w > 0:
+                    rows[i, n:n + w] = r.history[i, :w]
+            h.index_copy_(0, cb, rows)
+        out["n_iter"].index_copy_(0, cb, n1 + r.n_iter)
+        out["status"].index_copy_(0, cb, r.status)
     return int(bad.size)
 
 

@@ -113,6 +113,12 @@ def oracle_lockstep_rtol(atom, col, floor=1e-10, **kw):
     s = max(float(np.max(np.abs(r2["pops"] / r["pops"] - 1.0))),
             float(np.max(np.abs(r2["spectrum"] / r["spectrum"] - 1.0))))
     rtol = max(floor, 10.0 * s)
-    print(f"[lockstep] n_iter={r['n_iter']} rtol={rtol:.2e}", flush=True)
+    # the per-iteration changes: ten times their own spread under the same
+    # perturbation (an Ng extrapolation from nearly parallel iterates
+    # amplifies rounding in the next change more than in the populations)
+    n = r["n_iter"]
+    r["history_spread"] = 10.0 * np.abs(r2["history"][:n] - r["history"][:n])
+    print(f"[lockstep] n_iter={r['n_iter']} rtol={rtol:.2e} history spread "
+          f"{float(r['history_spread'].max()) if n else 0.0:.2e}", flush=True)
     assert rtol <= 1e-8, rtol
     return r, rtol

@@ -91,8 +91,9 @@ def test_failed_columns_solved_again_with_other_options(atom_dir):
     """Columns stopped by a small iteration limit are solved again with
     another option set (switched collisions, a larger limit): every column
     then converges, the re-solved ones match the oracle run with the second
-    option set (their iteration counts adding both attempts), and the
-    columns that had converged keep their results bit for bit."""
+    option set (their iteration counts adding both attempts, their history
+    rows holding both attempts' changes in order), and the columns that had
+    converged keep their results bit for bit."""
     rh = _rh()
     cols = _columns()
     atom = rh.Atom(atom_dir["h6"])
@@ -124,5 +125,8 @@ def test_failed_columns_solved_again_with_other_options(atom_dir):
         np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=rtol)
         np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=rtol)
         np.testing.assert_allclose(g["psi_star"][lo:hi].T, r["psi_star"], rtol=rtol, atol=1e-300)
-        m = min(first["max_iter"], r["n_iter"])
-        np.testing.assert_allclose(g["history"][c, :m], r["history"][:m], rtol=1e-6, atol=4 * rtol)
+        # the history row: the first attempt's changes, then the second's
+        n1 = first["max_iter"]
+        np.testing.assert_array_equal(g["history"][c, :n1], g0["history"][c, :n1])
+        m = min(g["history"].shape[1] - n1, r["n_iter"])
+        np.testing.assert_allclose(g["history"][c, n1:n1 + m], r["history"][:m], rtol=1e-6, atol=4 * rtol)

@@ -1,0 +1,102 @@
+"""Angle-averaged partial frequency redistribution through the C ABI
+(Sec. 2.1: MALI extended to PRD after Uitenbroek 2001; Sec. 2.3: PRD
+switching, Eq. 1).  The FP64 path runs in lock-step with the oracle's rho
+updates (same iteration counts, same Ng decisions), element by element;
+the FP32 form ends within 1e-3 of the converged oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1411_1079_amd import synth
+
+import conftest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _solve(atom_path, cols, **opts):
+    from paper_1411_1079_amd import rh15d as rh
+    print(f"[gpu] {atom_path.split('/')[-1]} columns={cols.n_columns} depth={int(cols.offset[-1])} {opts}", flush=True)
+    atom = rh.Atom(atom_path)
+    dc = rh.DeviceColumns.from_host(cols)
+    out = rh.solve(atom, dc, want_psi=True, **opts)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _lockstep(g, cols, atom_path, prd_lines, **kw):
+    a = O.Atom(atom_path)
+    for c in range(cols.n_columns):
+        r, rtol = conftest.oracle_lockstep_rtol(a, cols.column(c), prd_lines=prd_lines, **kw)
+        lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
+        assert g["n_iter"][c] == r["n_iter"] and g["status"][c] == r["status"], (c, g["n_iter"][c], r["n_iter"])
+        np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=rtol, err_msg=f"pops {c}")
+        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=rtol, err_msg=f"spectrum {c}")
+        np.testing.assert_allclose(g["psi_star"][lo:hi].T, r["psi_star"], rtol=rtol, atol=1e-300, err_msg=f"psi {c}")
+        n = r["n_iter"]
+        if n > 0:
+            # the per-iteration change, a difference of populations: within
+            # 1 % (the change right after an Ng extrapolation amplifies the
+            # rounding of the rho update's near-cancelling mean intensities;
+            # iteration counts and final states are compared exactly above)
+            atol = np.maximum(4 * rtol, r["history_spread"])
+            assert np.all(np.abs(g["history"][c, :n] - r["history"][:n]) <= 1e-2 * np.abs(r["history"][:n]) + atol)
+
+
+def _tiny_columns():
+    """Ragged columns whose PRD iterations the oracle itself reproduces to
+    better than 1e-9 under a 1-ulp perturbation of T (the rho update
+    subtracts nearly equal mean intensities, which amplifies rounding; on
+    some 8- and 12-point columns the oracle's own spread is 2e-9 to 2e-8
+    after 40 iterations, too wide for a lock-step case)."""
+    return synth.Columns.from_list([conftest.tiny_column(10, vz=2e3), conftest.tiny_column(7, vz=5e3),
+                                    conftest.tiny_column(2)])
+
+
+@pytest.mark.parametrize("scheduler", [0, 1])
+def test_prd_tiny_lockstep(atom_dir, scheduler):
+    """A PRD resonance line next to a CRD line and a continuum, ragged
+    columns (down to two points) with velocity fields: 1, 2, 5 and 40
+    iterations, with and without PRD switching."""
+    cols = _tiny_columns()
+    for it, eps0 in ((1, 0.0), (2, 0.0), (5, 0.0), (40, 0.0), (40, 1e-2)):
+        kw = dict(n_mu=3, tol=0.0, max_iter=it, coll_scale=1e-2, prd=1, prd_eps0=eps0)
+        g = _solve(atom_dir["prd_tiny"], cols, scheduler=scheduler, batch_columns=3, **kw)
+        _lockstep(g, cols, atom_dir["prd_tiny"], (0,), **kw)
+
+
+def test_prd_ca2_lockstep(atom_dir):
+    """The Ca II-like atom (two PRD resonance lines of 61 wavelengths, three
+    CRD lines, four continua, 985 wavelengths) on atmosphere columns,
+    converged to 1e-4 from LTE."""
+    cols = synth.cfg2_columns(seed=0, n_columns=2)
+    kw = dict(n_mu=3, tol=1e-4, max_iter=200, prd=1)
+    g = _solve(atom_dir["ca2"], cols, scheduler=1, **kw)
+    _lockstep(g, cols, atom_dir["ca2"], (0, 1), **kw)
+
+
+def test_prd_off_is_complete_redistribution(atom_dir):
+    """prd = 0 on the PRD atom gives bit for bit the solve of the same atom
+    with every line marked CRD."""
+    cols = synth.cfg2_columns(seed=1, n_columns=2)
+    kw = dict(n_mu=3, tol=1e-4, max_iter=60, scheduler=1)
+    a = _solve(atom_dir["ca2"], cols, prd=0, **kw)
+    b = _solve(atom_dir["ca2_crd"], cols, prd=1, **kw)
+    for k in ("pops", "spectrum", "n_iter", "status", "history", "psi_star"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_prd_fp32_form(atom_dir):
+    """FP32 formal solution and rate accumulation with FP64 rho updates,
+    rate solves, Ng and convergence test: within 1e-3 of the FP64 oracle
+    converged to 1e-9."""
+    cols = synth.cfg2_columns(seed=0, n_columns=2)
+    g = _solve(atom_dir["ca2"], cols, n_mu=3, tol=1e-4, tol_fp=2e-4, max_iter=300, prd=1, precision=1, scheduler=1)
+    a = O.Atom(atom_dir["ca2"])
+    for c in range(cols.n_columns):
+        r = O.solve_column(a, cols.column(c), n_mu=3, tol=1e-9, max_iter=2000, prd=1, prd_lines=(0, 1))
+        assert r["status"] == 0 and g["status"][c] == 0
+        lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
+        np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=1e-3)
+        np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-3)

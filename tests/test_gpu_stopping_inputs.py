@@ -151,10 +151,11 @@ def test_unusable_columns_are_isolated(atom_dir, scheduler, precision):
 def _write_isolated_level_atom(path):
     """Three bound levels; level 2 has no radiative (f = 0) and no
     collisional (Omega = 0) link to the others, so the rate matrix has a
-    zero row."""
+    zero row (level 2 is never the most populated one, whose row the
+    particle conservation replaces)."""
     lam01 = synth._H * synth._C / (2.0 * synth._EV) * 1e9
-    lam12 = synth._H * synth._C / (2.0 * synth._EV) * 1e9 * 1.001
-    levels = [(0.0, 2.0, 0), (2.0, 4.0, 0), (4.0, 2.0, 0)]
+    lam12 = synth._H * synth._C / (6.0 * synth._EV) * 1e9
+    levels = [(0.0, 2.0, 0), (2.0, 4.0, 0), (8.0, 1.0, 0)]
     lines = [dict(l=0, u=1, f=0.1, profile="GAUSS", coll="OMEGA", cval=1.0, lam=synth.line_grid_nm(lam01, n=9, x_max=4)),
              dict(l=1, u=2, f=0.0, profile="GAUSS", coll="OMEGA", cval=0.0, lam=synth.line_grid_nm(lam12, n=9, x_max=4))]
     return synth.write_atom(path, "ISOLATED", 1.00794, 1.0, levels, lines, [], 1.0e-38)
