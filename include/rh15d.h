@@ -248,6 +248,30 @@ int rh15d_solve_columns(const rh15d_atom *atom, const rh15d_columns *cols,
                         const rh15d_options *opt, const rh15d_outputs *out,
                         void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rh15d_solve_columns with
+ * its workspace in a fixed device region of the library,
+ * rh15d_static_workspace_bytes() bytes (64 MiB) per device, held from the
+ * library's load until the process ends.  Arguments, outputs, per-column
+ * statuses and results are those of rh15d_solve_columns with workspace =
+ * NULL; results are bit for bit the same.  The call allocates nothing: no
+ * device, pinned-host or graph memory, no streams or events (the sweep's
+ * kernel classes run one after another on hip_stream; iterations are not
+ * captured as a graph).  It reads the done-counter back into a host buffer
+ * of the calling thread.  Requirements: the atom's device tables for this
+ * device, options.n_mu and sweep shape exist (any earlier
+ * rh15d_solve_columns or rh15d_workspace_size of the atom with the same
+ * options built them), else
+ * RH15D_EINVAL; options.profile = 0, else RH15D_EINVAL; as many columns
+ * stay resident as the region holds (options.batch_columns, if set, must
+ * fit), and if not even one column and the depth offsets fit, RH15D_ENOMEM
+ * with the size needed.  Every call on a device uses the same region: the
+ * solve clears what it needs at its start (nothing carries over between
+ * calls), and calls that overlap on one device race. */
+size_t rh15d_static_workspace_bytes(void);
+int rh15d_solve_columns_static(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *opt,
+                               const rh15d_outputs *out, void *hip_stream);
+
 /* Autotuner of the formal-solution kernel's shape.  Columns are
  * independent, so a pool of workers can take them in any grouping (Sec. 3.1,
  * pool mode); on the GPU the grouping of rays into wavefronts is free too.

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librh15d.so")
-SOURCES = [os.path.join(CSRC, "mali.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "atom_setup.cpp")]
+SOURCES = [os.path.join(CSRC, "mali.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "static_ws.hip"),
+           os.path.join(CSRC, "atom_setup.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1992,7 +1992,10 @@ int upload(rh15d_atom *atom, const std::vector<T> &v, T **out) {
     return RH15D_OK;
 }
 
-int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
+// The atom's device tables for (device, n_mu, shape), built and uploaded on
+// first use; with build = false an absent entry is an error instead (the
+// caller may not allocate).
+int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bool build = true) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (shape.mc != 1 && shape.mc != 3 && shape.mc != 5) { set_error("angles per lane must be 1, 3 or 5"); return RH15D_EINVAL; }
@@ -2001,6 +2004,11 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out) {
     auto key = std::make_pair(std::make_pair(dev, n_mu), shape);
     auto it = atom->dev.find(key);
     if (it != atom->dev.end()) { *out = &it->second; return RH15D_OK; }
+    if (!build) {
+        set_error("the atom has no device tables for this device, n_mu and sweep shape yet (run rh15d_solve_columns "
+                  "once with the same options first)");
+        return RH15D_EINVAL;
+    }
     HostGroupTables H;
     build_group_tables(*atom, n_mu, shape, H);
     if (H.overflow) { set_error("a wavelength has more than %d active transitions", kMaxSlots); return RH15D_EINVAL; }
@@ -2310,11 +2318,11 @@ bool prd_active(const DevAtom &D, const rh15d_options *o) { return o->prd != 0 &
 
 // Resident columns: the caller's choice, else as many as fit a 40 GiB
 // working set (the device has 288 GB of HBM), at most 8192.
-int slot_count(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o, int ND) {
+int slot_count(const DevAtom &D, const rh15d_columns *cols, const rh15d_options *o, int ND,
+               size_t budget = size_t(40) << 30) {
     const int64_t n = std::max<int64_t>(cols->n_columns, 1);
     if (o->batch_columns > 0) return (int)std::min<int64_t>(o->batch_columns, n);
     const Layout one = make_layout(D, 0, 1, ND, o->precision == RH15D_FP32, o->ng_order == 2, prd_active(D, o));
-    const size_t budget = size_t(40) << 30;
     int64_t S = std::max<int64_t>(1, (int64_t)(budget / one.total));
     return (int)std::min<int64_t>(std::min<int64_t>(S, 8192), n);
 }
@@ -2597,26 +2605,43 @@ int rh15d_workspace_size(const rh15d_atom *atom_c, const rh15d_columns *cols, co
     return RH15D_OK;
 }
 
-int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, const rh15d_options *o,
-                        const rh15d_outputs *out, void *workspace, size_t workspace_bytes, void *hip_stream) {
+}  // extern "C"
+
+namespace rh15d {
+
+// The solve.  fixed_ws: the workspace is a fixed device region of
+// workspace_bytes that the slot count must fit, and nothing is allocated
+// (no device, pinned-host or graph memory, no side streams, no events).
+int solve_columns_impl(const rh15d_atom *atom_c, const rh15d_columns *cols, const rh15d_options *o,
+                       const rh15d_outputs *out, void *workspace, size_t workspace_bytes, void *hip_stream,
+                       bool fixed_ws) {
     int rc = validate(atom_c, cols, o);
     if (rc != RH15D_OK) return rc;
     if (!out || (cols->n_columns > 0 && (!out->pops || !out->n_iter || !out->status))) {
         set_error("null output array"); return RH15D_EINVAL;
     }
+    if (fixed_ws && o->profile) { set_error("profiling needs events: not available without allocation"); return RH15D_EINVAL; }
     g_stats = rh15d_stats{};
     if (cols->n_columns == 0) return RH15D_OK;
     rh15d_atom *atom = const_cast<rh15d_atom *>(atom_c);
     DevAtom *D = nullptr;
-    if ((rc = get_dev_atom(atom, o->n_mu, pick_shape(atom, o), &D)) != RH15D_OK) return rc;
+    if ((rc = get_dev_atom(atom, o->n_mu, pick_shape(atom, o), &D, !fixed_ws)) != RH15D_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool fp32 = o->precision == RH15D_FP32;
     const int ND = max_depth(cols);
-    const int S = slot_count(*D, cols, o, ND);
     const bool prd = prd_active(*D, o);
+    int S = fixed_ws ? slot_count(*D, cols, o, ND, workspace_bytes) : slot_count(*D, cols, o, ND);
+    // a fixed region also holds the column offsets: fewer slots if needed
+    while (fixed_ws && o->batch_columns <= 0 && S > 1 &&
+           make_layout(*D, cols->n_columns, S, ND, fp32, o->ng_order == 2, prd).total > workspace_bytes)
+        S--;
     const Layout lay = make_layout(*D, cols->n_columns, S, ND, fp32, o->ng_order == 2, prd);
     if (workspace && workspace_bytes < lay.total) {
-        set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total);
+        if (fixed_ws)
+            set_error("these columns need %zu bytes of workspace (at least one resident column and the column "
+                      "offsets), more than the %zu bytes of the fixed region", lay.total, workspace_bytes);
+        else
+            set_error("workspace too small: %zu < %zu", workspace_bytes, lay.total);
         return RH15D_ENOMEM;
     }
     void *own = nullptr;
@@ -2631,8 +2656,17 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
         if (result == RH15D_OK) set_error("%s: %s", what, hipGetErrorString(e));
         result = RH15D_EDEVICE;
     };
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h_ctr), CTR_COUNT * sizeof(int), hipHostMallocDefault);
-    if (e != hipSuccess) { fail(e, "hipHostMalloc"); if (own) (void)hipFree(own); return result; }
+    // the done-counter read back every few iterations: pinned host memory,
+    // or with a fixed workspace this thread's own pageable buffer
+    thread_local int h_ctr_fixed[CTR_COUNT];
+    hipError_t e = hipSuccess;
+    if (fixed_ws) {
+        h_ctr = h_ctr_fixed;
+    } else {
+        e = hipHostMalloc(reinterpret_cast<void **>(&h_ctr), CTR_COUNT * sizeof(int), hipHostMallocDefault);
+        if (e != hipSuccess) { fail(e, "hipHostMalloc"); if (own) (void)hipFree(own); return result; }
+    }
+    auto free_host = [&]() { if (!fixed_ws) (void)hipHostFree(h_ctr); };
 
     RunArgs a{};
     a.A = *D;
@@ -2675,9 +2709,11 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
 
     Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr, st};
     Timer tm;
-    if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
+    if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { free_host(); if (own) (void)hipFree(own); return rc; }
+    // the sweep's classes run concurrently on side streams, or one after
+    // another on the caller's stream with a fixed workspace
     SideStreams side;
-    if ((rc = side.init()) != RH15D_OK) { (void)hipHostFree(h_ctr); if (own) (void)hipFree(own); return rc; }
+    if (!fixed_ws && (rc = side.init()) != RH15D_OK) { free_host(); if (own) (void)hipFree(own); return rc; }
     run.side = &side;
     Timer *tp = tm.on ? &tm : nullptr;
     tm.mark(0, st);
@@ -2691,7 +2727,7 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
     // live on the device; the slot scheduler captures it once as a graph.
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    const bool try_graph = o->scheduler == RH15D_SCHED_SLOTS && !tm.on && st != nullptr;
+    const bool try_graph = o->scheduler == RH15D_SCHED_SLOTS && !tm.on && st != nullptr && !fixed_ws;
     if (try_graph && result == RH15D_OK) {
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             run.iteration(nullptr);
@@ -2754,9 +2790,18 @@ int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, con
             }
         }
     }
-    (void)hipHostFree(h_ctr);
+    free_host();
     if (own) (void)hipFree(own);
     return result;
+}
+
+}  // namespace rh15d
+
+extern "C" {
+
+int rh15d_solve_columns(const rh15d_atom *atom_c, const rh15d_columns *cols, const rh15d_options *o,
+                        const rh15d_outputs *out, void *workspace, size_t workspace_bytes, void *hip_stream) {
+    return rh15d::solve_columns_impl(atom_c, cols, o, out, workspace, workspace_bytes, hip_stream, false);
 }
 
 int rh15d_autotune(rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *opt, void *hip_stream,

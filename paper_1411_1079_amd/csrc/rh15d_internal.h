@@ -188,4 +188,9 @@ void gauss_legendre_01(int n, std::vector<double> &x, std::vector<double> &w);
 void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGroupTables &out);
 void set_error(const char *fmt, ...);
 const char *last_error();
+// the solve (mali.hip); fixed_ws: workspace is a fixed region of
+// workspace_bytes and nothing is allocated
+int solve_columns_impl(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *o,
+                       const rh15d_outputs *out, void *workspace, size_t workspace_bytes, void *hip_stream,
+                       bool fixed_ws);
 }  // namespace rh15d

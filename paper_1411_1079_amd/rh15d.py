@@ -27,7 +27,7 @@ EXPORTS = (
     "rh15d_autotune", "rh15d_departures", "rh15d_pops_from_departures", "rh15d_mlp_create", "rh15d_mlp_free", "rh15d_mlp_n_params",
     "rh15d_mlp_get_params", "rh15d_mlp_set_params", "rh15d_mlp_get_grads", "rh15d_mlp_get_normalization",
     "rh15d_mlp_set_normalization", "rh15d_mlp_fit_normalization", "rh15d_mlp_features", "rh15d_mlp_forward",
-    "rh15d_mlp_gradients", "rh15d_mlp_train_step",
+    "rh15d_mlp_gradients", "rh15d_mlp_train_step", "rh15d_solve_columns_static", "rh15d_static_workspace_bytes",
 )
 
 
@@ -89,6 +89,10 @@ def lib():
         L.rh15d_solve_columns.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(Options), C.POINTER(Outputs),
                                           C.c_void_p, C.c_size_t, C.c_void_p]
         L.rh15d_last_error.restype = C.c_char_p
+        L.rh15d_solve_columns_static.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(Options),
+                                                 C.POINTER(Outputs), C.c_void_p]
+        L.rh15d_static_workspace_bytes.argtypes = []
+        L.rh15d_static_workspace_bytes.restype = C.c_size_t
         L.rh15d_last_stats.argtypes = [C.POINTER(Stats)]
         vp, fp = C.c_void_p, C.POINTER(C.c_float)
         L.rh15d_autotune.argtypes = [vp, C.POINTER(Columns), C.POINTER(Options), vp, C.POINTER(TuneResult)]
@@ -204,6 +208,11 @@ def _cols_struct(dc: DeviceColumns) -> Columns:
     return s
 
 
+def static_workspace_bytes() -> int:
+    """Size of the library's fixed workspace region per device."""
+    return int(lib().rh15d_static_workspace_bytes())
+
+
 def workspace_size(atom: Atom, dc: DeviceColumns, opts: Options) -> int:
     n = C.c_size_t()
     _check(lib().rh15d_workspace_size(atom._h, C.byref(_cols_struct(dc)), C.byref(opts), C.byref(n)))
@@ -245,6 +254,15 @@ class Solver:
         ws_al = (ws + 255) & ~255
         _check(lib().rh15d_solve_columns(self.atom._h, C.byref(self._cols), C.byref(self.opts), C.byref(self._out),
                                          C.c_void_p(ws_al), self.ws_bytes, C.c_void_p(st.cuda_stream)))
+        return self
+
+    def run_static(self, stream=None):
+        """The same solve through rh15d_solve_columns_static: the library's
+        fixed device region as workspace, nothing allocated."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream(self.dc.z.device)
+        _check(lib().rh15d_solve_columns_static(self.atom._h, C.byref(self._cols), C.byref(self.opts),
+                                                C.byref(self._out), C.c_void_p(st.cuda_stream)))
         return self
 
     def result(self) -> dict:
