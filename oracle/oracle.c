@@ -1325,3 +1325,74 @@ int orc_column_prd_rho(const orc_atom *a, int N, const double *z, const double *
     free(cs.mu); free(cs.wmu);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* grid optimisation                                                    */
+/* ------------------------------------------------------------------ */
+/* Re-gridding of one column (Sec. 2.3, "Grid optimisation": more points
+ * where temperature, velocity or optical depth change fast).  Reading (the
+ * paper gives no formula): each interval i between points i-1 and i gets the
+ * length
+ *   d_i = sqrt((w_z dz_i / H)^2 + (w_T d ln T_i)^2 + (w_v dv_i)^2
+ *              + (w_tau d ln(tau_i + tau_min))^2),
+ * H the column's height range, tau the optical depth from the top at the
+ * reference wavelength of the background law (trapezoid rule in z; 0 without
+ * a background), tau_min = 1e-5; the n_out new points divide the summed
+ * length into equal parts (first and last point kept), and every variable
+ * is interpolated linearly in that length within its interval: z, v_z and
+ * v_turb as they are, T, n_e and n_H in their logarithms.  The weights are
+ * w[0..3] = (w_z, w_T, w_v [s/m], w_tau), each >= 0; the input must have z
+ * strictly decreasing and T, n_e, n_H > 0, and the summed length must be
+ * positive (error -3 otherwise). */
+#define GRID_TAU_MIN 1.0e-5
+int orc_optimize_grid(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                      const double *nH, const double *vz, const double *vt, int n_out, const double *w,
+                      double *zo, double *To, double *neo, double *nHo, double *vzo, double *vto) {
+    if (N < 2 || n_out < 2) FAIL(-3, "need at least 2 points in and out");
+    for (int i = 0; i < 4; i++)
+        if (!(w[i] >= 0.0 && isfinite(w[i]))) FAIL(-3, "grid weights must be finite and >= 0");
+    for (int k = 0; k < N; k++) {
+        if (!(T[k] > 0.0 && ne[k] > 0.0 && nH[k] > 0.0) || !isfinite(T[k] + ne[k] + nH[k] + vz[k] + vt[k] + z[k]))
+            FAIL(-3, "depth point %d: T, n_e, n_H must be finite and > 0", k);
+        if (k > 0 && !(z[k] < z[k - 1])) FAIL(-3, "z must decrease strictly (point %d)", k);
+    }
+    double *M = malloc(sizeof(double) * N);
+    double H = z[0] - z[N - 1], tau = 0.0, kp = 0.0;
+    M[0] = 0.0;
+    for (int k = 0; k < N; k++) {
+        double kap = a->bg_kind == 1 ? a->c_bg * nH[k] * ne[k] * pow(T[k], -1.5) * exp(BG_THETA / T[k]) : 0.0;
+        if (k > 0) {
+            double tprev = tau;
+            tau += 0.5 * (kp + kap) * (z[k - 1] - z[k]);
+            double dz = w[0] * (z[k - 1] - z[k]) / H;
+            double dT = w[1] * (log(T[k]) - log(T[k - 1]));
+            double dv = w[2] * (vz[k] - vz[k - 1]);
+            double dt = w[3] * (log(tau + GRID_TAU_MIN) - log(tprev + GRID_TAU_MIN));
+            M[k] = M[k - 1] + sqrt(dz * dz + dT * dT + dv * dv + dt * dt);
+        }
+        kp = kap;
+    }
+    if (!(M[N - 1] > 0.0 && isfinite(M[N - 1]))) {
+        free(M);
+        FAIL(-3, "the column's grid length is zero or not finite (all weights zero?)");
+    }
+    int k = 1;
+    for (int j = 0; j < n_out; j++) {
+        double target = M[N - 1] * (double)j / (double)(n_out - 1);
+        if (j == n_out - 1) target = M[N - 1];
+        while (k < N - 1 && M[k] < target) k++;
+        double f = (target - M[k - 1]) / (M[k] - M[k - 1]);
+        zo[j] = z[k - 1] + f * (z[k] - z[k - 1]);
+        To[j] = exp(log(T[k - 1]) + f * (log(T[k]) - log(T[k - 1])));
+        neo[j] = exp(log(ne[k - 1]) + f * (log(ne[k]) - log(ne[k - 1])));
+        nHo[j] = exp(log(nH[k - 1]) + f * (log(nH[k]) - log(nH[k - 1])));
+        vzo[j] = vz[k - 1] + f * (vz[k] - vz[k - 1]);
+        vto[j] = vt[k - 1] + f * (vt[k] - vt[k - 1]);
+    }
+    /* the end points exactly */
+    zo[0] = z[0]; To[0] = T[0]; neo[0] = ne[0]; nHo[0] = nH[0]; vzo[0] = vz[0]; vto[0] = vt[0];
+    zo[n_out - 1] = z[N - 1]; To[n_out - 1] = T[N - 1]; neo[n_out - 1] = ne[N - 1]; nHo[n_out - 1] = nH[N - 1];
+    vzo[n_out - 1] = vz[N - 1]; vto[n_out - 1] = vt[N - 1];
+    free(M);
+    return 0;
+}

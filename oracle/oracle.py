@@ -66,6 +66,7 @@ def lib():
         L.orc_ng_step.argtypes = [C.c_int, C.c_int, C.POINTER(C.POINTER(C.c_double)), dp]
         L.orc_column_profile_norm.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp]
         L.orc_column_damping.argtypes = [C.c_void_p, C.c_int] + [dp] * 8
+        L.orc_optimize_grid.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp] + [dp] * 6
         _lib = L
     return _lib
 
@@ -201,6 +202,22 @@ def prd_rho_constant_field(atom: Atom, col: dict, n_mu: int, pops, I_const: floa
         res.append(out[o:o + N * n].reshape(N, n))
         o += N * n
     return res
+
+
+GRID_WEIGHTS = (1.0, 2.0, 2.0e-4, 0.2)     # w_z, w_T, w_v [s/m], w_tau
+
+
+def optimize_grid(atom: Atom, col: dict, n_out: int, weights=GRID_WEIGHTS) -> dict:
+    """Column re-gridded onto n_out points (see orc_optimize_grid)."""
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    out = {k: np.empty(n_out) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    rc = lib().orc_optimize_grid(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                 n_out, _p(w), *(_p(out[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out
 
 
 def crs_factor(f0: float, it: int) -> float:
