@@ -272,6 +272,55 @@ size_t rh15d_static_workspace_bytes(void);
 int rh15d_solve_columns_static(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_options *opt,
                                const rh15d_outputs *out, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Grid optimisation (Sec. 2.3, "Grid optimisation"): every column is
+ * re-interpolated onto a new depth grid that puts more points where
+ * temperature, vertical velocity or optical depth change fast; each column
+ * gets its own grid and may get its own number of points.  The paper gives
+ * no formula; this reading gives the interval between input points k-1
+ * and k the length
+ *   d_k = sqrt((w_z dz_k / H)^2 + (w_T d ln T_k)^2 + (w_v dv_z,k)^2
+ *              + (w_tau d ln(tau_k + 1e-5))^2),
+ * H the column's height range and tau the optical depth from the top in
+ * the atom's background law at its reference wavelength (trapezoid rule in
+ * z; zero if the atom has no background), and spreads the new points at
+ * equal steps of the summed length.  The first and last input points are
+ * kept exactly; inside an interval z, v_z and v_turb are interpolated
+ * linearly in the length, T, n_e and n_H linearly in their logarithms.
+ * ------------------------------------------------------------------------ */
+#define RH15D_GRID_MAX_INPUT 8192
+typedef struct {
+    double w_z;     /* weight of the height step, in units of the column's height range */
+    double w_T;     /* weight of the step in ln T */
+    double w_v;     /* weight of the step in v_z, s/m */
+    double w_tau;   /* weight of the step in ln(tau + 1e-5) */
+} rh15d_grid_options;
+
+typedef struct {
+    const int64_t *depth_offset;  /* HOST [n_columns+1] rows of each new column, offset[0] = 0,
+                                     2..RH15D_MAX_DEPTH rows per column */
+    double *z, *T, *n_e, *n_H, *v_z, *v_turb;  /* DEVICE [offset[n_columns]] the new columns, top down */
+    int32_t *status;              /* DEVICE [n_columns] 0, or RH15D_BAD_INPUT for a column with fewer
+                                     than 2 points, a non-finite value, a non-positive T, n_e or n_H,
+                                     z not strictly decreasing, or zero summed length; its new
+                                     values are NaN */
+} rh15d_grid_output;
+
+/* Defaults: w_z = 1, w_T = 2, w_v = 2e-4 s/m (5 km/s weigh as much as the
+ * height range), w_tau = 0.2. */
+int rh15d_default_grid_options(rh15d_grid_options *opt);
+
+/* Re-grid the columns in (init_pops is ignored; input columns may have up
+ * to RH15D_GRID_MAX_INPUT points) into out.  Output buffers are caller-owned
+ * and must not overlap the input.  The depth offsets are uploaded before
+ * the call returns (the call waits for work queued earlier on hip_stream);
+ * the re-gridding itself is asynchronous on hip_stream.  Errors:
+ * RH15D_EINVAL for a null pointer, a weight that is negative or not finite,
+ * all weights zero, or a column count outside the limits (checked before
+ * any launch); RH15D_EDEVICE on a HIP error. */
+int rh15d_optimize_grid(const rh15d_atom *atom, const rh15d_columns *in, const rh15d_grid_options *opt,
+                        const rh15d_grid_output *out, void *hip_stream);
+
 /* Autotuner of the formal-solution kernel's shape.  Columns are
  * independent, so a pool of workers can take them in any grouping (Sec. 3.1,
  * pool mode); on the GPU the grouping of rays into wavefronts is free too.

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librh15d.so")
 SOURCES = [os.path.join(CSRC, "mali.hip"), os.path.join(CSRC, "mlp.hip"), os.path.join(CSRC, "static_ws.hip"),
-           os.path.join(CSRC, "atom_setup.cpp")]
+           os.path.join(CSRC, "grid.hip"), os.path.join(CSRC, "atom_setup.cpp")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -28,6 +28,7 @@ EXPORTS = (
     "rh15d_mlp_get_params", "rh15d_mlp_set_params", "rh15d_mlp_get_grads", "rh15d_mlp_get_normalization",
     "rh15d_mlp_set_normalization", "rh15d_mlp_fit_normalization", "rh15d_mlp_features", "rh15d_mlp_forward",
     "rh15d_mlp_gradients", "rh15d_mlp_train_step", "rh15d_solve_columns_static", "rh15d_static_workspace_bytes",
+    "rh15d_default_grid_options", "rh15d_optimize_grid",
 )
 
 
@@ -64,6 +65,15 @@ class TuneResult(C.Structure):
                 ("cand_mc", C.c_int * TUNE_MAX), ("cand_pack", C.c_int * TUNE_MAX), ("ms", C.c_double * TUNE_MAX)]
 
 
+class GridOptions(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("w_z", "w_T", "w_v", "w_tau")]
+
+
+class GridOutput(C.Structure):
+    _fields_ = [("depth_offset", C.POINTER(C.c_int64))] + \
+        [(n, C.c_void_p) for n in ("z", "T", "n_e", "n_H", "v_z", "v_turb", "status")]
+
+
 class Outputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star")]
 
@@ -94,6 +104,9 @@ def lib():
         L.rh15d_static_workspace_bytes.argtypes = []
         L.rh15d_static_workspace_bytes.restype = C.c_size_t
         L.rh15d_last_stats.argtypes = [C.POINTER(Stats)]
+        L.rh15d_default_grid_options.argtypes = [C.POINTER(GridOptions)]
+        L.rh15d_optimize_grid.argtypes = [C.c_void_p, C.POINTER(Columns), C.POINTER(GridOptions),
+                                          C.POINTER(GridOutput), C.c_void_p]
         vp, fp = C.c_void_p, C.POINTER(C.c_float)
         L.rh15d_autotune.argtypes = [vp, C.POINTER(Columns), C.POINTER(Options), vp, C.POINTER(TuneResult)]
         L.rh15d_departures.argtypes = [vp, C.POINTER(Columns), vp, vp, vp]
@@ -353,6 +366,38 @@ def _stream(stream=None):
     import torch
     st = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(st.cuda_stream)
+
+
+def default_grid_options(**kw) -> GridOptions:
+    o = GridOptions()
+    _check(lib().rh15d_default_grid_options(C.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def optimize_grid(atom: Atom, dc: DeviceColumns, n_out, stream=None, **weights):
+    """Re-grid every column (rh15d_optimize_grid): n_out is one point count
+    for all columns or one per column.  Returns (DeviceColumns of the new
+    grids, per-column status tensor)."""
+    import torch
+    n = dc.n_columns
+    counts = np.broadcast_to(np.asarray(n_out, dtype=np.int64), (n,))
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    dev = dc.z.device
+    new = {k: torch.empty(int(off[-1]), dtype=torch.float64, device=dev)
+           for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    o = GridOutput()
+    o.depth_offset = off.ctypes.data_as(C.POINTER(C.c_int64))
+    for k, t in new.items():
+        setattr(o, k, t.data_ptr())
+    o.status = status.data_ptr()
+    opts = default_grid_options(**weights)
+    _check(lib().rh15d_optimize_grid(atom._h, C.byref(_cols_struct(dc)), C.byref(opts), C.byref(o), _stream(stream)))
+    return DeviceColumns(offset=off, **new), status
 
 
 def departures(atom: Atom, dc: DeviceColumns, pops, out=None, stream=None):

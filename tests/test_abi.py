@@ -91,3 +91,36 @@ def test_invalid_depths_rejected(atom_dir, nd):
     with pytest.raises(rh15d.RH15DError) as e:
         rh15d.workspace_size(a, _fake_columns(nd), rh15d.default_options())
     assert "depth points" in str(e.value)
+
+
+def _grid_call(atom, nd_in, nd_out, **weights):
+    """rh15d_optimize_grid on host arrays standing in for device buffers
+    (every case here fails validation before any HIP call)."""
+    dc = _fake_columns(nd_in)
+    off = np.concatenate([[0], np.cumsum(nd_out)]).astype(np.int64)
+    bufs = [np.zeros(max(int(off[-1]), 1)) for _ in range(6)] + [np.zeros(len(nd_out), dtype=np.int32)]
+    o = rh15d.GridOutput()
+    o.depth_offset = off.ctypes.data_as(C.POINTER(C.c_int64))
+    for name, b in zip(("z", "T", "n_e", "n_H", "v_z", "v_turb", "status"), bufs):
+        setattr(o, name, b.ctypes.data)
+    opts = rh15d.default_grid_options(**weights)
+    return rh15d.lib().rh15d_optimize_grid(atom._h, C.byref(rh15d._cols_struct(dc)), C.byref(opts), C.byref(o), None)
+
+
+@pytest.mark.parametrize("case", [
+    dict(w_T=-1.0), dict(w_z=0.0, w_T=0.0, w_v=0.0, w_tau=0.0), dict(w_v=float("nan")), dict(w_tau=float("inf")),
+    dict(nd_out=[1, 5]), dict(nd_out=[5, 1025]), dict(nd_in=[8193, 4]),
+])
+def test_grid_optimisation_rejects_bad_arguments(atom_dir, case):
+    a = rh15d.Atom(atom_dir["h6"])
+    case = dict(case)
+    nd_in, nd_out = case.pop("nd_in", [6, 4]), case.pop("nd_out", [5, 5])
+    assert _grid_call(a, nd_in, nd_out, **case) == -1
+    assert rh15d.lib().rh15d_last_error()
+
+
+def test_grid_defaults_and_empty_call(atom_dir):
+    o = rh15d.default_grid_options()
+    assert (o.w_z, o.w_T, o.w_v, o.w_tau) == (1.0, 2.0, 2.0e-4, 0.2)
+    a = rh15d.Atom(atom_dir["h6"])
+    assert _grid_call(a, [], []) == 0   # nothing to do, nothing launched
