@@ -1316,33 +1316,39 @@ __device__ double actual_rate(const RunArgs &a, const DevTransition &tr, int t, 
     const DevAtom &A = a.A;
     const int na = tr.n_act, nmu = A.n_mu;
     const R *ist = reinterpret_cast<const R *>(a.ist) + gc * A.ist_cols;
+    const R *phi = reinterpret_cast<const R *>(a.phi) + gc * A.ray_cols + tr.ray_off;
+    const R *psi = (a.prd && tr.prd) ? reinterpret_cast<const R *>(a.emis) + gc * A.psi_cols + tr.psi_off : phi;
     double acc = 0.0;
-    for (int r = lane; r < na * nmu * 2; r += 64) {
-        const int s = r / (na * nmu), rem = r % (na * nmu), ja = rem / nmu, m = rem % nmu;
+    // one wavelength per lane, its angles and directions in turn: the
+    // wavelength's factors (and a continuum's exponential) once per lane
+    for (int ja = lane; ja < na; ja += 64) {
         const int j = A.act_j[tr.act_off + ja];
-        const double I = static_cast<double>(ist[(A.st_idx[j] * nmu + m) * 2 + s]);
-        const double W = A.act_w[tr.act_off + ja] * 0.5 * A.wmu[m];
+        const R *Ij = ist + A.st_idx[j] * nmu * 2;
+        const double wj = A.act_w[tr.act_off + ja] * 0.5;
         if (tr.kind == 0) {
-            const int col = (s * na + ja) * nmu + m;
-            const double ph = static_cast<double>(reinterpret_cast<const R *>(a.phi)[gc * A.ray_cols + tr.ray_off + col]);
-            if (UP) {
-                acc += W * ph * tr.Blu * I;
-            } else {
-                const double ps = (a.prd && tr.prd)
-                    ? static_cast<double>(reinterpret_cast<const R *>(a.emis)[gc * A.psi_cols + tr.psi_off + col]) : ph;
-                acc += W * ps * (tr.A + tr.Bul * I);
-            }
+            for (int s = 0; s < 2; s++)
+                for (int m = 0; m < nmu; m++) {
+                    const int col = (s * na + ja) * nmu + m;
+                    const double W = wj * A.wmu[m], I = static_cast<double>(Ij[m * 2 + s]);
+                    if (UP) acc += W * static_cast<double>(phi[col]) * tr.Blu * I;
+                    else acc += W * static_cast<double>(psi[col]) * (tr.A + tr.Bul * I);
+                }
         } else {
             const double nu = A.nu[j];
             const double rr = tr.nu0 / nu;
             const double alpha = tr.alpha0 * rr * rr * rr;
-            const double kap = 4.0 * kPI * W / (kH * nu);
-            if (UP) {
-                acc += kap * alpha * I;
-            } else {
-                const double G = a.gr[gc * A.n_cont + (t - A.n_lines)] * exp(-kH * nu / (kKB * T));
-                acc += kap * (2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha + G * alpha * I);
+            const double kap = 4.0 * kPI * wj / (kH * nu);
+            double G = 0.0, spont = 0.0;
+            if (!UP) {
+                G = a.gr[gc * A.n_cont + (t - A.n_lines)] * exp(-kH * nu / (kKB * T));
+                spont = 2.0 * kH * nu * nu * nu / (kC * kC) * G * alpha;
             }
+            for (int s = 0; s < 2; s++)
+                for (int m = 0; m < nmu; m++) {
+                    const double I = static_cast<double>(Ij[m * 2 + s]);
+                    if (UP) acc += kap * A.wmu[m] * alpha * I;
+                    else acc += kap * A.wmu[m] * (spont + G * alpha * I);
+                }
         }
     }
     return wave_sum(acc);
@@ -2460,7 +2466,8 @@ struct Launcher {
             else hipLaunchKernelGGL(k_prep_profile<double>, dim3(pb), dim3(256), 0, st, a);
         }
         if (a.prd) {
-            const unsigned tb = grid_for(pts * a.A.n_prd, 1, 1u << 20);
+            // one 64-lane workgroup per item, grid-stride (most iterations refill few slots)
+            const unsigned tb = grid_for(pts * a.A.n_prd, 1, 16384);
             if (fp32) hipLaunchKernelGGL(k_prd_tables<float>, dim3(tb), dim3(64), 0, st, a);
             else hipLaunchKernelGGL(k_prd_tables<double>, dim3(tb), dim3(64), 0, st, a);
         }
