@@ -42,15 +42,15 @@ sys.path.insert(0, ROOT)
 METRIC = "converged columns/s @1e-3 rel. accuracy: plain FP64 vs batched FP32+warm start"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per FP32 sweep stage from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (calibrated on a 1 GiB copy), valid only for the kernel source they were
+# HBM bytes per FP32 sweep stage of the learned-start form from rocprofv3
+# FETCH_SIZE / WRITE_SIZE (calibrated on a 1 GiB copy), valid only for the kernel source they were
 # taken on: the JSON line reports null once that source has changed.
 SWEEP_TRAFFIC = {
     "source": "paper_1411_1079_amd/csrc/mali.hip",
-    "sha256": "faa7bd61e2052098e6276862805a998627bf5da4d46d569ee81efc2b3cafaeb6",
-    "read_bytes": 25.75e9,
-    "written_bytes": 5.14e9,
-    "summary": "profiles/k_sweep_fp32_cube256_counters.md",
+    "sha256": "1232baf3d362d9b94d3a7db6f15bc348dee2d6ef9477945251d33cd7605b405d",
+    "read_bytes": 23.42e9,
+    "written_bytes": 4.62e9,
+    "summary": "profiles/k_sweep_fp32_learned_start_cube256_counters.md",
 }
 
 
@@ -328,6 +328,31 @@ def accuracy(results, form, batches, cols, lockstep=False):
     return out
 
 
+def grid_measure(rh, torch, atom, cols, fields, n_out=300, reps=5):
+    """Grid optimisation of the whole cube (every column onto n_out points)
+    in one call, timed with HIP events on the launch stream; algorithmic
+    bytes = six FP64 values read per input point and written per output
+    point, plus the status per column."""
+    dc = rh.DeviceColumns(offset=np.ascontiguousarray(cols.offset, dtype=np.int64), **fields)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        rh.optimize_grid(atom, dc, n_out, stream=st)      # warm-up
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(st)
+            new, status = rh.optimize_grid(atom, dc, n_out, stream=st)
+            b.record(st)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+    nbytes = 48.0 * (cols.offset[-1] + cols.n_columns * n_out) + 4.0 * cols.n_columns
+    return dict(columns=cols.n_columns, input_points=int(cols.offset[-1]), output_points_per_column=n_out,
+                bad_input_columns=int((status != 0).sum().item()), median_ms=ms,
+                algorithmic_bytes=nbytes, achieved_GBps=nbytes / (ms / 1e3) / 1e9,
+                hbm_frac=nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                timing_note=("median of 5 calls between HIP events on the launch stream; each call also uploads "
+                             "the 1 MB of depth offsets and waits for it"))
+
+
 def prd_workload(args):
     """The partial-frequency-redistribution workload: the Ca II-like atom
     (two PRD resonance lines, three CRD lines, four continua, 985
@@ -415,6 +440,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (a reference kernel of known traffic for "
                          "hardware byte counters) and exit")
+    ap.add_argument("--save-network", default="", metavar="NPZ",
+                    help="write the trained start-solution network (parameters and input normalisation) here")
+    ap.add_argument("--load-network", default="", metavar="NPZ",
+                    help="use a network written by --save-network instead of training one (for profiler runs, "
+                         "where the training's many small launches would dominate)")
     ap.add_argument("--prd", action="store_true",
                     help="measure the partial-frequency-redistribution workload instead (Ca II-like atom)")
     ap.add_argument("--prd-nx", type=int, default=64)
@@ -478,10 +508,20 @@ def main():
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     log(f"workspace {ws_bytes / 2**30:.2f} GiB, {len(batches)} batches of <= {args.batch} columns")
     net = train_info = None
-    if "fp32w" in forms:
+    if "fp32w" in forms and args.load_network:
+        z = np.load(args.load_network)
+        net = rh.MLP(int(z["n_hidden"]), int(z["n_layers"]), atom.n_levels, 0)
+        net.set_params(z["params"])
+        net.set_normalization(z["mean"], z["std"])
+        train_info = dict(loaded=args.load_network)
+        log(f"network loaded from {args.load_network}")
+    elif "fp32w" in forms:
         log(f"train the start-solution network on cube seed {args.train_seed}")
         net, train_info = train_network(rh, torch, atom, args)
         log(f"network: {train_info}")
+        if args.save_network:
+            mean, std = net.get_normalization()
+            np.savez(args.save_network, params=net.get_params(), mean=mean, std=std, n_hidden=256, n_layers=3)
     res = {}
     for f in forms:
         log(f"form {f}: warmup {args.warmup}, steps {args.steps}")
@@ -538,7 +578,7 @@ def main():
                           "the device code) FP32 vector code can reach 78.6 TFLOP/s"),
             "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": sweep_traffic() if headline != "fp64" else None,
+            "traffic": sweep_traffic() if headline == "fp32w" else None,
             "traffic_note": ("HBM bytes per sweep stage, rocprofv3 FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (factors "
                              "from a 1 GiB copy); null when the kernel source differs from the one measured"),
             "timing_note": ("HIP events recorded by the library on the launch stream around each iteration's "
@@ -568,6 +608,8 @@ def main():
             out["forms"][f]["mlp"] = r["mlp"]
     if train_info is not None:
         out["network_training"] = train_info
+    out["grid_optimisation"] = grid_measure(rh, torch, atom, cols, fields)
+    log(f"grid optimisation: {out['grid_optimisation']}")
     if tune:
         out["autotune"] = tune
     if not args.no_cpu_baseline:
