@@ -73,6 +73,11 @@ typedef struct {
     double c_el;        /* line: elastic-collision rate per hydrogen atom, m^3 s^-1
                            (Q_E = c_el n_H; broadens the line and sets its coherence) */
     int prd;            /* line: partial frequency redistribution (angle-averaged R_II) */
+    /* line: Zeeman pattern (both levels carry J and a Lande factor), else n_zc = 0 */
+    int n_zc;
+    int *zq;            /* q = M_l - M_u of each component: -1, 0, +1 */
+    double *zshift;     /* g_u M_u - g_l M_l: the component's shift in Larmor frequencies */
+    double *zstr;       /* relative strength; the strengths of each q sum to 1 */
     int n_own;
     double *lam_own;    /* the transition's own wavelengths, m */
     /* derived */
@@ -88,6 +93,8 @@ typedef struct orc_atom {
     int L;
     double *E, *g;
     int *stage;
+    int *twoJ;                /* 2 J of each level, -1 if the atom gives none */
+    double *gL;               /* Lande factor of each level */
     int n_lines, n_cont, T;   /* transitions: lines first, then continua */
     orc_trans *tr;
     int bg_kind;              /* 0 none, 1 H-minus-like law */
@@ -155,8 +162,11 @@ static int cmp_double(const void *a, const void *b) {
 
 void orc_atom_free(orc_atom *a) {
     if (!a) return;
-    for (int t = 0; t < a->T; t++) { free(a->tr[t].lam_own); free(a->tr[t].act); free(a->tr[t].wnu); }
-    free(a->tr); free(a->E); free(a->g); free(a->stage); free(a->lam); free(a->nu);
+    for (int t = 0; t < a->T; t++) {
+        free(a->tr[t].lam_own); free(a->tr[t].act); free(a->tr[t].wnu);
+        free(a->tr[t].zq); free(a->tr[t].zshift); free(a->tr[t].zstr);
+    }
+    free(a->tr); free(a->E); free(a->g); free(a->stage); free(a->lam); free(a->nu); free(a->twoJ); free(a->gL);
     free(a);
 }
 
@@ -182,6 +192,70 @@ static int parse_transition(tokstream *ts, orc_trans *t, int kind, int L) {
         t->lam_own[i] *= 1e-9;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Zeeman patterns                                                      */
+/* ------------------------------------------------------------------ */
+static double fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; i++) f *= i;
+    return f;
+}
+
+/* Wigner 3j symbol (j1 j2 j3; m1 m2 m3) from Racah's single-sum formula;
+ * arguments are twice the angular momenta and projections. */
+double orc_wigner3j(int tj1, int tj2, int tj3, int tm1, int tm2, int tm3) {
+    if (tm1 + tm2 + tm3 != 0) return 0.0;
+    if (tj3 < abs(tj1 - tj2) || tj3 > tj1 + tj2 || ((tj1 + tj2 + tj3) & 1)) return 0.0;
+    if (abs(tm1) > tj1 || abs(tm2) > tj2 || abs(tm3) > tj3) return 0.0;
+    if (((tj1 + tm1) & 1) || ((tj2 + tm2) & 1) || ((tj3 + tm3) & 1)) return 0.0;
+    /* integer combinations (halves of sums of the doubled arguments) */
+    int a1 = (tj1 + tj2 - tj3) / 2, a2 = (tj1 - tj2 + tj3) / 2, a3 = (-tj1 + tj2 + tj3) / 2;
+    int a4 = (tj1 + tj2 + tj3) / 2 + 1;
+    double tri = fact(a1) * fact(a2) * fact(a3) / fact(a4);
+    double pre = fact((tj1 + tm1) / 2) * fact((tj1 - tm1) / 2) * fact((tj2 + tm2) / 2) * fact((tj2 - tm2) / 2) *
+                 fact((tj3 + tm3) / 2) * fact((tj3 - tm3) / 2);
+    int b1 = (tj3 - tj2 + tm1) / 2, b2 = (tj3 - tj1 - tm2) / 2;   /* k + b1 >= 0, k + b2 >= 0 */
+    int c1 = (tj1 + tj2 - tj3) / 2, c2 = (tj1 - tm1) / 2, c3 = (tj2 + tm2) / 2;  /* k <= c */
+    int kmin = 0;
+    if (-b1 > kmin) kmin = -b1;
+    if (-b2 > kmin) kmin = -b2;
+    int kmax = c1;
+    if (c2 < kmax) kmax = c2;
+    if (c3 < kmax) kmax = c3;
+    double sum = 0.0;
+    for (int k = kmin; k <= kmax; k++) {
+        double d = fact(k) * fact(k + b1) * fact(k + b2) * fact(c1 - k) * fact(c2 - k) * fact(c3 - k);
+        sum += ((k & 1) ? -1.0 : 1.0) / d;
+    }
+    int ph = (tj1 - tj2 - tm3) / 2;
+    return ((ph & 1) ? -1.0 : 1.0) * sqrt(tri * pre) * sum;
+}
+
+/* Anomalous Zeeman pattern of a dipole line between a lower level (J_l,
+ * g_l) and an upper level (J_u, g_u) (Sec. 2.1: Zeeman splitting of
+ * bound-bound transitions).  Components are the pairs (M_u, M_l) with
+ * q = M_l - M_u in {-1, 0, 1}; each is shifted by (g_u M_u - g_l M_l)
+ * Larmor frequencies e B / (4 pi m_e) and has the strength
+ * 3 (J_u J_l 1; -M_u M_l -q)^2, which sums to 1 over the components of each
+ * q.  Components of zero strength are left out.  Arguments are 2J; returns
+ * the number of components (at most max), or -1. */
+int orc_zeeman_pattern(int twoJl, double gl, int twoJu, double gu, int max, int *q, double *shift, double *strength) {
+    int n = 0;
+    for (int tmu = -twoJu; tmu <= twoJu; tmu += 2)
+        for (int tml = -twoJl; tml <= twoJl; tml += 2) {
+            int tq = tml - tmu;
+            if (tq < -2 || tq > 2) continue;
+            double w = orc_wigner3j(twoJu, twoJl, 2, -tmu, tml, -tq);
+            if (w == 0.0) continue;
+            if (n >= max) return -1;
+            q[n] = tq / 2;
+            shift[n] = gu * 0.5 * tmu - gl * 0.5 * tml;
+            strength[n] = 3.0 * w * w;
+            n++;
+        }
+    return n;
 }
 
 int orc_atom_load(const char *path, orc_atom **out) {
@@ -231,6 +305,23 @@ int orc_atom_load(const char *path, orc_atom **out) {
         }
         if (!(tk = next_tok(&ts))) goto bad;
     }
+    a->twoJ = malloc(sizeof(int) * a->L);
+    a->gL = calloc(a->L, sizeof(double));
+    for (int i = 0; i < a->L; i++) a->twoJ[i] = -1;
+    if (!strcmp(tk, "ZEEMAN")) {
+        int nz;
+        if (tok_int(&ts, &nz) || nz < 0) goto bad;
+        for (int i = 0; i < nz; i++) {
+            int li, tj;
+            double gl;
+            if (tok_int(&ts, &li) || li < 0 || li >= a->L || tok_int(&ts, &tj) || tj < 0 || tj > 40 ||
+                tok_double(&ts, &gl))
+                goto bad;
+            a->twoJ[li] = tj;
+            a->gL[li] = gl;
+        }
+        if (!(tk = next_tok(&ts))) goto bad;
+    }
     if (strcmp(tk, "BACKGROUND") || !(tk = next_tok(&ts))) goto bad;
     if (!strcmp(tk, "NONE")) a->bg_kind = 0;
     else if (!strcmp(tk, "HMINUS")) { a->bg_kind = 1; if (tok_double(&ts, &a->c_bg)) goto bad; }
@@ -268,6 +359,16 @@ bad:
             if (a->tr[s].u == tr->l) gam += a->tr[s].Aul;
         }
         tr->gamma_rad = gam;
+    }
+    /* Zeeman patterns of the lines whose two levels carry J and g */
+    for (int t = 0; t < a->n_lines; t++) {
+        orc_trans *tr = &a->tr[t];
+        int jl = a->twoJ[tr->l], ju = a->twoJ[tr->u];
+        if (jl < 0 || ju < 0) continue;
+        int mx = (jl + 1) * (ju + 1);
+        tr->zq = malloc(sizeof(int) * mx); tr->zshift = malloc(sizeof(double) * mx); tr->zstr = malloc(sizeof(double) * mx);
+        tr->n_zc = orc_zeeman_pattern(jl, a->gL[tr->l], ju, a->gL[tr->u], mx, tr->zq, tr->zshift, tr->zstr);
+        if (tr->n_zc <= 0) { orc_atom_free(a); FAIL(-2, "line %d: J values allow no dipole transition", t); }
     }
     /* union wavelength grid: all own points, sorted, exact duplicates merged */
     int tot = 0;
@@ -346,9 +447,11 @@ int orc_gauss_legendre(int n, double *x, double *w) {
     return 0;
 }
 
-/* Voigt function H(a, v) = Re w(v + i a) by Humlicek (1982) rational
- * approximation W4 (four regions in s = |v| + a). */
-double orc_voigt_H(double a, double v) {
+/* Faddeeva function w(v + i a) = H(a, v) + i L(a, v) by Humlicek (1982)
+ * rational approximation W4 (four regions in s = |v| + a): H is the Voigt
+ * function, L the (odd) dispersion function, so that the absorption and
+ * magneto-optical profiles per unit v are H / sqrt(pi) and L / sqrt(pi). */
+void orc_voigt_w(double a, double v, double *H, double *L) {
     double x = v, y = a;
     double s = fabs(x) + y;
     /* t = y - i x */
@@ -393,8 +496,15 @@ double orc_voigt_H(double a, double v) {
         double eu = exp(ur);
         wr = eu * cos(ui) - fr; wi = eu * sin(ui) - fi;
     }
-    (void)wi;
-    return wr;
+    *H = wr;
+    *L = wi;
+}
+
+/* Voigt function H(a, v) = Re w(v + i a). */
+double orc_voigt_H(double a, double v) {
+    double H, L;
+    orc_voigt_w(a, v, &H, &L);
+    return H;
 }
 
 /* Angle-averaged redistribution function R_II (Hummer 1962) in Doppler
@@ -1394,5 +1504,202 @@ int orc_optimize_grid(const orc_atom *a, int N, const double *z, const double *T
     zo[n_out - 1] = z[N - 1]; To[n_out - 1] = T[N - 1]; neo[n_out - 1] = ne[N - 1]; nHo[n_out - 1] = nH[N - 1];
     vzo[n_out - 1] = vz[N - 1]; vto[n_out - 1] = vt[N - 1];
     free(M);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* polarised emergent spectrum                                          */
+/* ------------------------------------------------------------------ */
+/* Vertical, upward formal solution of the Stokes vector (I, Q, U, V) at one
+ * wavelength (Sec. 2.1: the full Stokes vector from Zeeman splitting; the
+ * paper names no polarised solver).  Reading: DELO with a linear effective
+ * source function (Rees, Durrant & Murphy 1989).  With chi_I the total
+ * opacity, K' = K / chi_I - 1 (zero diagonal) and S' = eps / chi_I, the
+ * transfer equation along the optical depth reads dI/dtau = I - (S' - K' I);
+ * taking the bracket linear in tau over each interval gives, from the
+ * deeper point k+1 to point k with the short-characteristic weights of the
+ * unpolarised solver (step x, e = exp(-x), w_a, w_b),
+ *   (1 + w_b K'_k) I_k = (e - w_a K'_{k+1}) I_{k+1} + w_a S'_{k+1} + w_b S'_k,
+ * a 4 x 4 system solved at every point.  The propagation matrix is
+ *   K = [[eI, eQ, eU, eV], [eQ, eI, rV, -rU], [eU, -rV, eI, rQ], [eV, rU, -rQ, eI]].
+ * Inputs per point: z, chi_I, K6 = (eQ, eU, eV, rQ, rU, rV) and
+ * eps = (eps_I, eps_Q, eps_U, eps_V); Ibot enters at the bottom point. */
+static void kprime(const double *K6, double chiI, double *Kp) {
+    double eQ = K6[0] / chiI, eU = K6[1] / chiI, eV = K6[2] / chiI;
+    double rQ = K6[3] / chiI, rU = K6[4] / chiI, rV = K6[5] / chiI;
+    double M[16] = {0.0, eQ, eU, eV,
+                    eQ, 0.0, rV, -rU,
+                    eU, -rV, 0.0, rQ,
+                    eV, rU, -rQ, 0.0};
+    memcpy(Kp, M, sizeof M);
+}
+
+int orc_stokes_formal(int N, const double *z, const double *chiI, const double *K6, const double *eps,
+                      const double *Ibot, double *Itop) {
+    double I[4] = {Ibot[0], Ibot[1], Ibot[2], Ibot[3]};
+    for (int k = N - 2; k >= 0; k--) {
+        double x = 0.5 * (chiI[k + 1] + chiI[k]) * (z[k] - z[k + 1]);
+        double e, wa, wb;
+        orc_sc_coefficients(x, &e, &wa, &wb);
+        double Kd[16], Kc[16];
+        kprime(&K6[(k + 1) * 6], chiI[k + 1], Kd);
+        kprime(&K6[k * 6], chiI[k], Kc);
+        double rhs[4], M[16];
+        for (int i = 0; i < 4; i++) {
+            double s = e * I[i];
+            for (int c = 0; c < 4; c++) s -= wa * Kd[i * 4 + c] * I[c];
+            rhs[i] = s + wa * eps[(k + 1) * 4 + i] / chiI[k + 1] + wb * eps[k * 4 + i] / chiI[k];
+            for (int c = 0; c < 4; c++) M[i * 4 + c] = (i == c ? 1.0 : 0.0) + wb * Kc[i * 4 + c];
+        }
+        if (gauss_solve(4, M, rhs)) FAIL(-3, "singular DELO system at point %d", k);
+        for (int i = 0; i < 4; i++) I[i] = rhs[i];
+    }
+    for (int i = 0; i < 4; i++) Itop[i] = I[i];
+    return 0;
+}
+
+/* Stokes vector of the vertical emergent spectrum of a column whose
+ * populations n are given (the unpolarised emergent spectrum's opacities
+ * and emissivities, the same profile normalisation and PRD ratio rho),
+ * with a magnetic field of strength B [T], inclination incl to the
+ * vertical (the line of sight) and azimuth azim [rad] at every depth.  A
+ * line whose Zeeman pattern the atom gives contributes, per absorption
+ * and emission coefficient (the scalar coefficients of the unpolarised
+ * solve), the Zeeman profiles phi_q = sum of strength * H(a, v - shift v_L)
+ * / (sqrt(pi) dnu_D) and psi_q (the same with the dispersion function L),
+ * v_L the Larmor frequency in Doppler widths, combined as
+ *   eta_I = [phi_0 sin^2(theta) + (phi_{+1} + phi_{-1})(1 + cos^2(theta))/2] / 2,
+ *   eta_Q = [phi_0 - (phi_{+1} + phi_{-1})/2] sin^2(theta) cos(2 chi) / 2,
+ *   eta_U = the same with sin(2 chi),  eta_V = (phi_{+1} - phi_{-1}) cos(theta) / 2,
+ * and rho_Q, rho_U, rho_V likewise from psi_q; eps = emission coefficient
+ * times (eta_I, eta_Q, eta_U, eta_V).  Other transitions and the background
+ * are unpolarised.  Bottom: (B_nu + dB/dtau, 0, 0, 0), as the unpolarised
+ * spectrum.  out: [NL][4]. */
+/* Opacity chi_I, K6 and eps of one point k at wavelength j (see above). */
+static void stokes_point(const colstate *cs, const double *n, const double *Bf, const double *incl,
+                         const double *azim, int j, int k, double *chi, double *kk, double *ee, double *Bnu) {
+    const orc_atom *a = cs->a;
+    int N = cs->N, L = a->L;
+    double nu = a->nu[j];
+    double c = cs->kbg[k] * (a->lam[j] / BG_LAMBDA_REF);
+    *Bnu = planck(nu, cs->T[k]);
+    for (int i = 0; i < 6; i++) kk[i] = 0.0;
+    ee[0] = c * *Bnu; ee[1] = ee[2] = ee[3] = 0.0;
+    for (int t = 0; t < a->T; t++) {
+        const orc_trans *tr = &a->tr[t];
+        if (!(a->lam[j] >= tr->lam_min && a->lam[j] <= tr->lam_max)) continue;
+        if (tr->kind == 0) {
+            double rho = 1.0;
+            if (cs->rho && cs->rho[t]) {
+                int ja = 0;
+                while (tr->act[ja] != j) ja++;
+                rho = cs->rho[t][(size_t)k * tr->n_act + ja];
+            }
+            double cc = PH * tr->nu0 / (4.0 * PPI) / cs->norm[t * N + k];
+            double cabs = cc * (n[k * L + tr->l] * tr->Blu - n[k * L + tr->u] * tr->Bul * rho);
+            double cem = cc * n[k * L + tr->u] * tr->Aul * rho;
+            if (tr->n_zc == 0) {
+                double p = line_profile(a, t, cs, k, nu, 1.0);
+                c += cabs * p;
+                ee[0] += cem * p;
+                continue;
+            }
+            double dnd = cs->dnuD[t * N + k], ad = cs->adamp[t * N + k];
+            double v = (nu - tr->nu0 * (1.0 + cs->vz[k] / PC)) / dnd;
+            double vL = PQE * Bf[k] / (4.0 * PPI * PME) / dnd;
+            double ph[3] = {0, 0, 0}, ps[3] = {0, 0, 0};
+            for (int i = 0; i < tr->n_zc; i++) {
+                double vc = v - tr->zshift[i] * vL, H, Lf;
+                orc_voigt_w(tr->voigt ? ad : 0.0, vc, &H, &Lf);
+                if (!tr->voigt) H = exp(-vc * vc);
+                ph[tr->zq[i] + 1] += tr->zstr[i] * H;
+                ps[tr->zq[i] + 1] += tr->zstr[i] * Lf;
+            }
+            for (int q = 0; q < 3; q++) { ph[q] /= sqrt(PPI) * dnd; ps[q] /= sqrt(PPI) * dnd; }
+            double ct = cos(incl[k]), st = sin(incl[k]), s2 = st * st;
+            double c2 = cos(2.0 * azim[k]), sn2 = sin(2.0 * azim[k]);
+            /* q = +1 is ph[2], q = -1 is ph[0] */
+            double pI = 0.5 * (ph[1] * s2 + 0.5 * (ph[2] + ph[0]) * (1.0 + ct * ct));
+            double pl = 0.5 * (ph[1] - 0.5 * (ph[2] + ph[0])) * s2;
+            double pV = 0.5 * (ph[2] - ph[0]) * ct;
+            double rl = 0.5 * (ps[1] - 0.5 * (ps[2] + ps[0])) * s2;
+            double rV = 0.5 * (ps[2] - ps[0]) * ct;
+            c += cabs * pI;
+            kk[0] += cabs * pl * c2; kk[1] += cabs * pl * sn2; kk[2] += cabs * pV;
+            kk[3] += cabs * rl * c2; kk[4] += cabs * rl * sn2; kk[5] += cabs * rV;
+            ee[0] += cem * pI; ee[1] += cem * pl * c2; ee[2] += cem * pl * sn2; ee[3] += cem * pV;
+        } else {
+            double alpha = tr->alpha0 * pow(tr->nu0 / nu, 3.0);
+            double G = exp(cs->lnr[k * L + tr->l] - cs->lnr[k * L + tr->u]) * exp(-PH * nu / (PKB * cs->T[k]));
+            c += n[k * L + tr->l] * alpha - n[k * L + tr->u] * G * alpha;
+            ee[0] += n[k * L + tr->u] * 2.0 * PH * nu * nu * nu / (PC * PC) * G * alpha;
+        }
+    }
+    *chi = c;
+}
+
+static int stokes_emergent(const colstate *cs, const double *n, const double *Bf, const double *incl,
+                           const double *azim, double *out) {
+    const orc_atom *a = cs->a;
+    int N = cs->N;
+    double *chi = malloc(sizeof(double) * N), *K6 = malloc(sizeof(double) * N * 6);
+    double *eps = malloc(sizeof(double) * N * 4), *B = malloc(sizeof(double) * N);
+    int rc = 0;
+    for (int j = 0; j < a->NL && !rc; j++) {
+        for (int k = 0; k < N; k++) stokes_point(cs, n, Bf, incl, azim, j, k, &chi[k], &K6[k * 6], &eps[k * 4], &B[k]);
+        double dtv = 0.5 * (chi[N - 1] + chi[N - 2]) * (cs->z[N - 2] - cs->z[N - 1]);
+        double Ib[4] = {(dtv > 0.0) ? B[N - 1] + (B[N - 1] - B[N - 2]) / dtv : B[N - 1], 0.0, 0.0, 0.0};
+        rc = orc_stokes_formal(N, cs->z, chi, K6, eps, Ib, &out[(size_t)j * 4]);
+    }
+    free(chi); free(K6); free(eps); free(B);
+    return rc;
+}
+
+/* The Stokes spectrum of one column from given populations pops [N][L]
+ * (and, for the lines the atom marks PRD, their final rho as
+ * orc_solve_column returns it, or NULL for rho = 1), with the profile
+ * normalisation of an n_mu-angle quadrature; stokes: [NL][4] (tests and
+ * the benchmark's CPU leg only). */
+int orc_stokes_column(const orc_atom *a, int N, const double *z, const double *T, const double *ne, const double *nH,
+                      const double *vz, const double *vt, int n_mu, const double *Bf, const double *incl,
+                      const double *azim, const double *pops, const double *prd_rho, double *stokes) {
+    if (!column_valid(N, z, T, ne, nH, vz, vt)) FAIL(-3, "column data cannot be used");
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * n_mu); cs.wmu = malloc(sizeof(double) * n_mu);
+    orc_gauss_legendre(n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    if (prd_rho) {
+        cs.rho = calloc(a->n_lines ? a->n_lines : 1, sizeof(double *));
+        cs.gII = calloc(a->n_lines ? a->n_lines : 1, sizeof(double *));
+        for (int t = 0; t < a->n_lines; t++)
+            if (a->tr[t].prd) {
+                size_t m = (size_t)N * a->tr[t].n_act;
+                cs.rho[t] = malloc(sizeof(double) * m);
+                memcpy(cs.rho[t], prd_rho, sizeof(double) * m);
+                prd_rho += m;
+            }
+    }
+    int rc = stokes_emergent(&cs, pops, Bf, incl, azim, stokes);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return rc;
+}
+
+/* chi_I, K6 and eps (11 values) of point k at wavelength j of a column
+ * with populations pops and rho = 1 (tests only). */
+int orc_stokes_coefficients(const orc_atom *a, int N, const double *z, const double *T, const double *ne,
+                            const double *nH, const double *vz, const double *vt, int n_mu, const double *Bf,
+                            const double *incl, const double *azim, const double *pops, int j, int k, double *out) {
+    if (j < 0 || j >= a->NL || k < 0 || k >= N) FAIL(-3, "point out of range");
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * n_mu); cs.wmu = malloc(sizeof(double) * n_mu);
+    orc_gauss_legendre(n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    double Bnu;
+    stokes_point(&cs, pops, Bf, incl, azim, j, k, &out[0], &out[1], &out[7], &Bnu);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
     return 0;
 }

@@ -67,6 +67,15 @@ def lib():
         L.orc_column_profile_norm.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp]
         L.orc_column_damping.argtypes = [C.c_void_p, C.c_int] + [dp] * 8
         L.orc_optimize_grid.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp] + [dp] * 6
+        L.orc_wigner3j.argtypes = [C.c_int] * 6
+        L.orc_wigner3j.restype = C.c_double
+        L.orc_zeeman_pattern.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, ip, dp, dp]
+        L.orc_voigt_w.argtypes = [C.c_double, C.c_double, dp, dp]
+        L.orc_voigt_w.restype = None
+        L.orc_stokes_formal.argtypes = [C.c_int] + [dp] * 6
+        L.orc_stokes_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int] + [dp] * 6
+        L.orc_stokes_coefficients.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int] + [dp] * 4 + \
+            [C.c_int, C.c_int, dp]
         _lib = L
     return _lib
 
@@ -266,3 +275,77 @@ def solve_columns(atom: Atom, columns, threads: int | None = None, **kw) -> list
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
         futs = [ex.submit(solve_column, atom, columns.column(c), **kw) for c in range(columns.n_columns)]
         return [f.result() for f in futs]
+
+
+def wigner3j(j1, j2, j3, m1, m2, m3) -> float:
+    """Wigner 3j symbol (half-integers allowed)."""
+    return lib().orc_wigner3j(*(int(round(2 * x)) for x in (j1, j2, j3, m1, m2, m3)))
+
+
+def zeeman_pattern(J_l, g_l, J_u, g_u) -> dict:
+    """Zeeman components of a line: q = M_l - M_u, shift (g_u M_u - g_l M_l)
+    in Larmor frequencies, strength."""
+    mx = int(round((2 * J_l + 1) * (2 * J_u + 1)))
+    q = np.zeros(mx, dtype=np.int32)
+    sh, st = np.zeros(mx), np.zeros(mx)
+    n = lib().orc_zeeman_pattern(int(round(2 * J_l)), g_l, int(round(2 * J_u)), g_u, mx,
+                                 q.ctypes.data_as(C.POINTER(C.c_int)), _p(sh), _p(st))
+    if n < 0:
+        raise ValueError("no pattern")
+    return dict(q=q[:n].copy(), shift=sh[:n].copy(), strength=st[:n].copy())
+
+
+def voigt_w(a: float, v: float) -> complex:
+    """Humlicek W4 value of w(v + i a) = H + i L."""
+    H, L = C.c_double(), C.c_double()
+    lib().orc_voigt_w(a, v, C.byref(H), C.byref(L))
+    return complex(H.value, L.value)
+
+
+def stokes_formal(z, chiI, K6, eps, Ibot) -> np.ndarray:
+    """Emergent (top) Stokes vector of the polarised formal solver given
+    per-point opacity chi_I, K6 = (eta_Q, eta_U, eta_V, rho_Q, rho_U, rho_V)
+    and eps = (eps_I, eps_Q, eps_U, eps_V), top first."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    chiI = np.ascontiguousarray(chiI, dtype=np.float64)
+    K6 = np.ascontiguousarray(K6, dtype=np.float64).reshape(-1, 6)
+    eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1, 4)
+    Ib = np.ascontiguousarray(Ibot, dtype=np.float64)
+    out = np.empty(4)
+    rc = lib().orc_stokes_formal(len(z), _p(z), _p(chiI), _p(K6), _p(eps), _p(Ib), _p(out))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out
+
+
+def stokes_column(atom: Atom, col: dict, pops, n_mu: int, B, incl, azim, prd_rho=None) -> np.ndarray:
+    """Vertical emergent Stokes spectrum [NL][4] of a column from given
+    populations (see orc_stokes_column); prd_rho: the list of rho arrays
+    solve_column returns, or None."""
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    f = [np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (N,))) for x in (B, incl, azim)]
+    n = np.ascontiguousarray(pops, dtype=np.float64).reshape(N, -1)
+    rho = None if prd_rho is None or len(prd_rho) == 0 else np.ascontiguousarray(
+        np.concatenate([np.asarray(r, dtype=np.float64).ravel() for r in prd_rho]))
+    out = np.empty((atom.n_lambda, 4))
+    rc = lib().orc_stokes_column(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                 n_mu, *(_p(x) for x in f), _p(n), _p(rho), _p(out))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out
+
+
+def stokes_coefficients(atom: Atom, col: dict, pops, n_mu: int, B, incl, azim, j: int, k: int) -> dict:
+    """chi_I, (eta_Q, eta_U, eta_V, rho_Q, rho_U, rho_V) and (eps_I..eps_V)
+    of one point and wavelength (rho = 1)."""
+    N = len(col["z"])
+    cols = {kk: np.ascontiguousarray(col[kk], dtype=np.float64) for kk in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    f = [np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (N,))) for x in (B, incl, azim)]
+    n = np.ascontiguousarray(pops, dtype=np.float64).reshape(N, -1)
+    out = np.empty(11)
+    rc = lib().orc_stokes_coefficients(atom._h, N, *(_p(cols[kk]) for kk in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                       n_mu, *(_p(x) for x in f), _p(n), j, k, _p(out))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return dict(chi=out[0], K6=out[1:7], eps=out[7:11])

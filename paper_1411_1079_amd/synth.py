@@ -127,12 +127,14 @@ def continuum_grid_nm(edge_nm: float, n: int = 20) -> np.ndarray:
     return _C / nu * 1e9
 
 
-def write_atom(path, name, mass_amu, abundance, levels, lines, continua, background, elastic=None):
+def write_atom(path, name, mass_amu, abundance, levels, lines, continua, background, elastic=None, zeeman=None):
     """Write an atom file. levels: [(E_eV, g, stage)]; lines: dicts with
     l, u, f, profile (GAUSS|VOIGT), coll (OMEGA|EPS), cval, lam [nm];
     continua: dicts with l, u, alpha [m^2], coll, cval, lam [nm];
     background: None or the C_bg of the H-minus-like law; elastic: None or
-    [(line index, c_el [m^3 s^-1], "PRD" | "CRD")]."""
+    [(line index, c_el [m^3 s^-1], "PRD" | "CRD")]; zeeman: None or
+    [(level index, J, Lande g)] (a line is Zeeman split when both of its
+    levels are listed)."""
     out = ["RH15D-ATOM 1", f"NAME {name}", f"MASS_AMU {_fmt(mass_amu)}", f"ABUNDANCE {_fmt(abundance)}",
            f"LEVELS {len(levels)}", "#  E[eV]  g  stage"]
     for E, g, st in levels:
@@ -151,6 +153,11 @@ def write_atom(path, name, mass_amu, abundance, levels, lines, continua, backgro
         out.append(f"ELASTIC {len(elastic)}")
         for li, c, kind in elastic:
             out.append(f"  {int(li)} {_fmt(c)} {kind}")
+    if zeeman:
+        out.append(f"ZEEMAN {len(zeeman)}")
+        out.append("#  level 2J g_Lande")
+        for li, J, gl in zeeman:
+            out.append(f"  {int(li)} {int(round(2 * J))} {_fmt(gl)}")
     if background is None:
         out.append("BACKGROUND NONE")
     else:
@@ -229,6 +236,9 @@ CA_LINES = [  # (l, u, f, PRD)
     (1, 2, 0.03, False),
     (0, 1, 1.0e-8, False),  # weak forbidden-like line
 ]
+# J and L-S Lande factors of the fine-structure levels (the 3d level, a
+# merged D3/2 + D5/2 term, carries none: its lines are not split)
+CA_ZEEMAN = [(0, 0.5, 2.0), (2, 0.5, 2.0 / 3.0), (3, 1.5, 4.0 / 3.0)]
 CA_MASS_AMU = 40.078
 CA_ABUNDANCE = 2.2e-6
 CA_C_ELASTIC = 1.0e-14      # m^3 s^-1: Q_E = 1e9 s^-1 at n_H = 1e23 m^-3
@@ -240,7 +250,8 @@ def write_ca_atom(path: str, c_bg: float | None, n_prd: int = 61, n_crd: int = 4
     frequency redistribution (n_prd wavelengths each, sinh grid over +-300
     km/s), two infrared lines and a weak forbidden line with complete
     redistribution, Voigt profiles, elastic collisions on the four strong
-    lines, and four bound-free continua (n_cont wavelengths each): about
+    lines, Zeeman patterns of the two resonance lines (2S1/2 - 2P3/2 and
+    2S1/2 - 2P1/2 levels), and four bound-free continua (n_cont wavelengths each): about
     1000 wavelengths with the defaults.  prd=False writes the same atom
     with every line in complete redistribution."""
     lines, conts, el = [], [], []
@@ -255,7 +266,8 @@ def write_ca_atom(path: str, c_bg: float | None, n_prd: int = 61, n_crd: int = 4
         dE = (CA_LEVELS[4][0] - CA_LEVELS[lo][0]) * _EV
         edge = _H * _C / dE * 1e9
         conts.append(dict(l=lo, u=4, alpha=alpha, coll="OMEGA", cval=0.1, lam=np.sort(continuum_grid_nm(edge, n=n_cont))))
-    return write_atom(path, "CA2", CA_MASS_AMU, CA_ABUNDANCE, CA_LEVELS, lines, conts, c_bg, elastic=el)
+    return write_atom(path, "CA2", CA_MASS_AMU, CA_ABUNDANCE, CA_LEVELS, lines, conts, c_bg, elastic=el,
+                      zeeman=CA_ZEEMAN)
 
 
 # ----------------------------------------------------------------------------

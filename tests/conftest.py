@@ -29,7 +29,40 @@ def atom_dir(tmp_path_factory):
     paths["prd_tiny_gamma0"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny_gamma0.atom"), c_el=1.0e3)
     paths["prd_tiny_gamma0_crd"] = write_prd_tiny_atom(os.path.join(str(d), "prd_tiny_gamma0_crd.atom"), c_el=1.0e3,
                                                        prd=False)
+    paths["zeeman_tiny"] = write_zeeman_tiny_atom(os.path.join(str(d), "zeeman_tiny.atom"))
+    paths["zeeman_tiny_nobg"] = write_zeeman_tiny_atom(os.path.join(str(d), "zeeman_tiny_nobg.atom"), c_bg=None)
+    paths["zeeman_tiny_prd"] = write_zeeman_tiny_atom(os.path.join(str(d), "zeeman_tiny_prd.atom"), prd=True)
     return paths
+
+
+# levels of the Zeeman test atom: (E [eV], statistical weight, stage), J, Lande g
+ZEEMAN_TINY_LEVELS = [((0.0, 2.0, 0), 0.5, 2.0), ((3.0, 2.0, 0), 0.5, 2.0 / 3.0), ((3.05, 4.0, 0), 1.5, 4.0 / 3.0),
+                      ((5.0, 2.0, 0), 0.5, 2.0), ((6.5, 1.0, 1), None, None)]
+
+
+def write_zeeman_tiny_atom(path, c_bg=1.0e-38, prd=False):
+    """Five-level atom with three Zeeman-split Voigt lines: two resonance
+    lines like the alkali D lines (2S1/2 - 2P1/2, J 1/2 -> 1/2, and
+    2S1/2 - 2P3/2, J 1/2 -> 3/2) and a line from 2P3/2 up to a J = 1/2
+    level (J 3/2 -> 1/2), on 21-point grids over +-6 Doppler widths, and
+    one continuum far away; prd=True makes the D2-like line PRD."""
+    levels = [lv for lv, _, _ in ZEEMAN_TINY_LEVELS]
+    ev = synth._EV
+    hc = synth._H * synth._C
+
+    def lam0(lo, hi):
+        return hc / ((levels[hi][0] - levels[lo][0]) * ev) * 1e9
+
+    lines = [dict(l=0, u=1, f=0.3, profile="VOIGT", coll="OMEGA", cval=1.0,
+                  lam=synth.line_grid_nm(lam0(0, 1), n=21, x_max=6.0)),
+             dict(l=0, u=2, f=0.6, profile="VOIGT", coll="OMEGA", cval=1.0,
+                  lam=synth.line_grid_nm(lam0(0, 2), n=21, x_max=6.0)),
+             dict(l=2, u=3, f=0.2, profile="VOIGT", coll="OMEGA", cval=1.0,
+                  lam=synth.line_grid_nm(lam0(2, 3), n=21, x_max=6.0))]
+    conts = [dict(l=0, u=4, alpha=1e-22, coll="OMEGA", cval=0.1, lam=np.sort(synth.continuum_grid_nm(lam0(0, 4), n=4)))]
+    zee = [(i, J, g) for i, (_, J, g) in enumerate(ZEEMAN_TINY_LEVELS) if J is not None]
+    el = [(1, 1.0e-16, "PRD")] if prd else None
+    return synth.write_atom(path, "ZTINY", TINY_MASS, 1.0, levels, lines, conts, c_bg, elastic=el, zeeman=zee)
 
 
 def write_prd_tiny_atom(path, prd=True, c_el=1.0e-16, n_line=13, x_max=6.0):
