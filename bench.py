@@ -353,14 +353,31 @@ def grid_measure(rh, torch, atom, cols, fields, n_out=300, reps=5):
                              "the 1 MB of depth offsets and waits for it"))
 
 
+def cube_field(cols, seed):
+    """Magnetic field of the full-stack workload: per column a strength
+    uniform in 0-2 kG and an isotropic direction (cosine of the inclination
+    uniform in [-1, 1], azimuth uniform in [0, 2 pi)), constant along the
+    column."""
+    rng = np.random.default_rng(seed)
+    n = cols.n_columns
+    B = rng.uniform(0.0, 0.2, n)
+    inc = np.arccos(rng.uniform(-1.0, 1.0, n))
+    az = rng.uniform(0.0, 2.0 * np.pi, n)
+    nd = np.diff(cols.offset)
+    return tuple(np.repeat(x, nd) for x in (B, inc, az))
+
+
 def prd_workload(args):
-    """The partial-frequency-redistribution workload: the Ca II-like atom
-    (two PRD resonance lines, three CRD lines, four continua, 985
-    wavelengths) on a synthetic cube of args.prd_nx^2 columns, 5 angles,
-    solved to the change test 1e-4 plus the fixed-point bound, in FP64
-    (plain path, chunked) and FP32 (slot scheduler); one JSON line with
-    converged columns/s, iterations, statuses and the per-kernel times of
-    a profiled solve of the same columns."""
+    """The full-stack workload: the Ca II-like atom (two PRD resonance lines
+    with Zeeman patterns, three CRD lines, four continua, 985 wavelengths)
+    on a synthetic cube of args.prd_nx^2 columns with a magnetic field
+    (cube_field), 5 angles, solved to the change test 1e-4 plus the
+    fixed-point bound, then the emergent Stokes vector; in FP64 (plain
+    path, chunked) and FP32 (slot scheduler).  One JSON line with converged
+    columns/s, iterations, statuses, the per-kernel times of a profiled solve
+    of the same columns, and the time of the polarised formal solution
+    alone (final stage from the converged populations with and without the
+    Stokes output)."""
     import torch
 
     from paper_1411_1079_amd import rh15d as rh
@@ -368,12 +385,12 @@ def prd_workload(args):
     tmp = tempfile.mkdtemp()
     atoms = synth.write_atoms(tmp)
     cols = synth.cube_columns(args.seed, args.prd_nx, args.prd_nx)
-    dc = rh.DeviceColumns.from_host(cols)
+    dc = rh.DeviceColumns.from_host(cols, field=cube_field(cols, args.seed + 100))
     atom = rh.Atom(atoms["ca2"])
     res = {}
     for name, kw in (("fp64", dict(precision=0, scheduler=0)), ("fp32", dict(precision=1, scheduler=1))):
         o = rh.default_options(n_mu=5, tol=1e-4, tol_fp=args.tol_fp, max_iter=args.prd_max_iter, prd=1, **kw)
-        s = rh.Solver(atom, dc, o)
+        s = rh.Solver(atom, dc, o, want_stokes=True)
         st = torch.cuda.Stream()
         with torch.cuda.stream(st):
             s.run(st)                      # warm-up (builds the tables)
@@ -386,7 +403,7 @@ def prd_workload(args):
         status = s.status.cpu().numpy()
         it = s.n_iter.cpu().numpy()
         o.profile = 1
-        p = rh.Solver(atom, dc, o, workspace=s.workspace)
+        p = rh.Solver(atom, dc, o, workspace=s.workspace, want_stokes=True)
         p.run()
         torch.cuda.synchronize()
         stats = rh.last_stats()
@@ -396,18 +413,40 @@ def prd_workload(args):
                          profiled_kernel_ms={k: stats[k] for k in ("prep_ms", "sweep_ms", "se_ms", "converge_ms",
                                                                    "final_ms", "total_ms")},
                          sweep_tflops=stats["sweep_flops"] / (stats["sweep_ms"] / 1e3) / 1e12 if stats["sweep_ms"] else 0.0)
+        pol = torch.sqrt((s.stokes[:, :, 1:] ** 2).sum(dim=2)) / s.stokes[:, :, 0]
+        res[name]["max_polarisation_degree"] = float(torch.nan_to_num(pol, nan=0.0).max().item())
+        if name == "fp64":
+            # the final stage alone, from the converged populations: with and
+            # without the Stokes output
+            dcp = rh.DeviceColumns(offset=dc.offset, z=dc.z, T=dc.T, n_e=dc.n_e, n_H=dc.n_H, v_z=dc.v_z,
+                                   v_turb=dc.v_turb, init_pops=s.pops.clone(), B=dc.B, B_incl=dc.B_incl,
+                                   B_azim=dc.B_azim)
+            fin = {}
+            for want in (False, True):
+                o0 = rh.default_options(n_mu=5, max_iter=0, start=rh.START_PROVIDED, prd=1, profile=1, **kw)
+                q = rh.Solver(atom, dcp, o0, want_stokes=want)
+                q.run()
+                q.run()
+                torch.cuda.synchronize()
+                fin[want] = rh.last_stats()["final_ms"]
+            steps = float(cols.offset[-1]) * atom.n_lambda
+            res[name]["stokes_ms"] = fin[True] - fin[False]
+            res[name]["stokes_point_wavelengths_per_s"] = steps / ((fin[True] - fin[False]) / 1e3)
         log(f"prd {name}: {res[name]}")
-    out = dict(metric="converged columns/s, angle-averaged PRD (Ca II-like atom)", unit="columns/s",
+    out = dict(metric="converged columns/s, angle-averaged PRD + Zeeman Stokes (Ca II-like atom)", unit="columns/s",
                value=res["fp64"]["columns_per_s"], n_gpus=1, higher_is_better=True, data="synthetic",
                dtype="f64",
                config={"workload": (f"synthetic 3D cube {args.prd_nx}x{args.prd_nx} columns (seed {args.seed}), "
-                                    f"200-400 depth points, Ca II-like 5-level atom (2 PRD lines of 61 wavelengths, "
-                                    f"3 CRD lines, 4 continua, 985 wavelengths), 5 angles, tol 1e-4, fixed-point bound "
-                                    f"{args.tol_fp:g}, at most {args.prd_max_iter} iterations"),
+                                    f"200-400 depth points, Ca II-like 5-level atom (2 PRD lines of 61 wavelengths "
+                                    f"with Zeeman patterns, 3 CRD lines, 4 continua, 985 wavelengths), 5 angles, "
+                                    f"tol 1e-4, fixed-point bound {args.tol_fp:g}, at most {args.prd_max_iter} "
+                                    f"iterations; field 0-2 kG uniform, isotropic direction, per column; emergent "
+                                    f"Stokes vector"),
                        "parallelism": "1 GPU"},
                forms=res,
                note=("converge_ms includes the rho update kernels (k_prd_rho, k_prd_psi), which run after the "
-                     "convergence test; prep_ms includes the R_II tables (k_prd_tables)"))
+                     "convergence test; prep_ms includes the R_II tables (k_prd_tables); final_ms includes the "
+                     "emergent spectrum and the Stokes formal solution (k_stokes, FP64 in both forms)"))
     print(json.dumps(out), flush=True)
 
 

@@ -105,6 +105,13 @@ typedef struct {
                                      conditions gets status RH15D_BAD_INPUT) */
     const double *init_pops;      /* DEVICE [total_depth][n_levels] start populations
                                      (read only when start = RH15D_START_PROVIDED) */
+    /* Magnetic field, read only for the Stokes spectrum (rh15d_outputs.stokes):
+       all three NULL (no field) or all three DEVICE [total_depth]; a column
+       with a non-finite value gets a NaN Stokes spectrum. */
+    const double *B;              /* field strength, T */
+    const double *B_incl;         /* inclination to the vertical (the line of sight), rad */
+    const double *B_azim;         /* azimuth of the field's horizontal part, rad (the reference
+                                     direction of Stokes Q is azimuth 0) */
 } rh15d_columns;
 
 typedef struct {
@@ -202,6 +209,33 @@ typedef struct {
                            final populations averaged over each transition's rays
                            (weights W phi for lines, W / sum W for continua), m;
                            may be NULL */
+    double *stokes;     /* DEVICE [n_columns][n_lambda][4] emergent vertical Stokes vector
+                           (I, Q, U, V) at the top, W m^-2 Hz^-1 sr^-1, with the
+                           Zeeman effect of the columns' magnetic field; may be NULL.
+                           Sec. 2.1 (the full Stokes vector from Zeeman splitting).
+                           Populations are unpolarised: the field enters only this
+                           final formal solution, computed in FP64 in both
+                           precisions from the final populations (and the final
+                           rho of PRD lines).  Lines whose two levels the atom file
+                           gives J and a Lande factor (section ZEEMAN) are split
+                           into their anomalous Zeeman pattern (components of
+                           strength normalised per q = M_l - M_u, shifted by
+                           (g_u M_u - g_l M_l) e B / (4 pi m_e)); each contributes
+                           the absorption matrix
+                             eta_I = [phi_0 sin^2 t + (phi_+1 + phi_-1)(1 + cos^2 t)/2]/2,
+                             eta_Q, eta_U = [phi_0 - (phi_+1 + phi_-1)/2] sin^2 t (cos, sin)(2 a)/2,
+                             eta_V = (phi_+1 - phi_-1) cos t / 2,
+                           rho_Q, rho_U, rho_V alike from the dispersion profiles
+                           (phi + i psi = w(v + i a) / sqrt(pi), w the Faddeeva
+                           function), times the line's scalar absorption
+                           coefficient, and the emission vector of the same
+                           combinations times its emission coefficient (t the
+                           inclination, a the azimuth); other transitions and the
+                           background are unpolarised.  The transfer equation is
+                           integrated upward with DELO and a linear effective
+                           source function (Rees, Durrant & Murphy 1989) on the
+                           depth points; the bottom enters as (B_nu + dB_nu/dtau,
+                           0, 0, 0).  With no field it equals (spectrum, 0, 0, 0). */
 } rh15d_outputs;
 
 /* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, tol_fp 0, 200

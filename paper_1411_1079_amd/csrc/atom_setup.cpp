@@ -96,6 +96,40 @@ bool read_transition(Tokens &tk, HostTransition &t, int kind, int L) {
 
 }  // namespace
 
+// Zeeman pattern of a dipole line (Sec. 2.1: Zeeman splitting), from the
+// Condon & Shortley relative strengths of the components for J_u - J_l =
+// +1, 0, -1 (J, M of the lower level; M_u = M, M + 1, M - 1), normalised
+// to unit sum per q = M_l - M_u; the component M_u -> M_l is shifted by
+// g_u M_u - g_l M_l Larmor frequencies.  Nothing for |J_u - J_l| > 1 or
+// J_u = J_l = 0.
+void zeeman_components(int twoJl, double gl, int twoJu, double gu, HostTransition &t) {
+    t.zq.clear(); t.zshift.clear(); t.zstr.clear();
+    const int d2 = twoJu - twoJl;
+    if (d2 != 2 && d2 != 0 && d2 != -2) return;
+    const double J = 0.5 * twoJl, Ju = 0.5 * twoJu;
+    double sum[3] = {0, 0, 0};
+    for (int tm = -twoJl; tm <= twoJl; tm += 2) {
+        const double M = 0.5 * tm;
+        for (int q = -1; q <= 1; q++) {
+            const double Mu = M - q;
+            if (std::fabs(Mu) > Ju + 1e-9) continue;
+            double s;
+            if (d2 == 2) s = q == 0 ? (J + 1) * (J + 1) - M * M
+                           : q == -1 ? 0.25 * (J + M + 1) * (J + M + 2) : 0.25 * (J - M + 1) * (J - M + 2);
+            else if (d2 == 0) s = q == 0 ? M * M : q == -1 ? 0.25 * (J - M) * (J + M + 1) : 0.25 * (J + M) * (J - M + 1);
+            else s = q == 0 ? J * J - M * M : q == -1 ? 0.25 * (J - M) * (J - M - 1) : 0.25 * (J + M) * (J + M - 1);
+            if (!(s > 0.0)) continue;
+            t.zq.push_back(q);
+            t.zshift.push_back(gu * Mu - gl * M);
+            t.zstr.push_back(s);
+            sum[q + 1] += s;
+        }
+    }
+    for (size_t i = 0; i < t.zq.size(); i++) t.zstr[i] /= sum[t.zq[i] + 1];
+    // a pattern needs components of every q (J_u = J_l = 0 has none)
+    if (!(sum[0] > 0 && sum[1] > 0 && sum[2] > 0)) { t.zq.clear(); t.zshift.clear(); t.zstr.clear(); }
+}
+
 int parse_atom_file(const char *path, rh15d_atom *a, std::string &err) {
     std::ifstream in(path);
     if (!in) { err = std::string("cannot open ") + path; return RH15D_EIO; }
@@ -140,6 +174,22 @@ int parse_atom_file(const char *path, rh15d_atom *a, std::string &err) {
         }
         if (!tk.word(w)) { err = "malformed atom file"; return RH15D_EIO; }
     }
+    a->twoJ.assign(a->L, -1);
+    a->gL.assign(a->L, 0.0);
+    if (w == "ZEEMAN") {
+        int nz;
+        if (!tk.integer(nz) || nz < 0) { err = "malformed ZEEMAN"; return RH15D_EIO; }
+        for (int i = 0; i < nz; i++) {
+            int li, tj;
+            double gl;
+            if (!tk.integer(li) || li < 0 || li >= a->L || !tk.integer(tj) || tj < 0 || tj > 40 || !tk.num(gl)) {
+                err = "malformed ZEEMAN row"; return RH15D_EIO;
+            }
+            a->twoJ[li] = tj;
+            a->gL[li] = gl;
+        }
+        if (!tk.word(w)) { err = "malformed atom file"; return RH15D_EIO; }
+    }
     if (w != "BACKGROUND" || !tk.word(w)) { err = "malformed BACKGROUND"; return RH15D_EIO; }
     if (w == "NONE") a->bg_kind = 0;
     else if (w == "HMINUS") { a->bg_kind = 1; if (!tk.num(a->c_bg)) { err = "malformed HMINUS"; return RH15D_EIO; } }
@@ -169,6 +219,12 @@ int parse_atom_file(const char *path, rh15d_atom *a, std::string &err) {
         for (const auto &s : a->tr)
             if (s.kind == 0 && (s.u == t.u || s.u == t.l)) gam += s.A;
         t.gamma = gam;
+    }
+    // Zeeman patterns of the lines whose two levels carry J and g
+    for (auto &t : a->tr) {
+        if (t.kind != 0 || a->twoJ[t.l] < 0 || a->twoJ[t.u] < 0) continue;
+        zeeman_components(a->twoJ[t.l], a->gL[t.l], a->twoJ[t.u], a->gL[t.u], t);
+        if (t.zq.empty()) { err = "a Zeeman-split line whose J values allow no dipole transition"; return RH15D_EIO; }
     }
     // union wavelength grid
     std::vector<double> all;

@@ -33,6 +33,8 @@ using namespace rh15d;
 namespace {
 
 constexpr double kTauMin = 1.0e-5;
+// LDS of one block when the input columns are staged (up to 1170 points)
+constexpr size_t kStageLds = 64 * 1024;
 
 struct GridArgs {
     const int64_t *in_off, *out_off;  // [n_columns + 1] each, device
@@ -42,6 +44,7 @@ struct GridArgs {
     double wz, wT, wv, wtau;
     double c_bg;      // background coefficient; 0 without the background law
     int64_t n_columns;
+    int max_in;       // longest input column of the launch
 };
 
 // Exclusive prefix sum over the wavefront.  Every shuffle runs with all 64
@@ -57,25 +60,43 @@ __device__ __forceinline__ double scan_excl(double v, int lane) {
     return lane > 0 ? prev : 0.0;
 }
 
-__device__ __forceinline__ double bg_opacity(const GridArgs &g, int64_t i) {
-    if (g.c_bg == 0.0) return 0.0;
-    const double T = g.T[i];
-    return g.c_bg * g.nH[i] * g.ne[i] * pow(T, -1.5) * exp(kBgTheta / T);
+__device__ __forceinline__ double bg_opacity(double c_bg, double T, double ne, double nH) {
+    if (c_bg == 0.0) return 0.0;
+    return c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T);
 }
 
+// kStage: the column's six input fields are first copied to LDS with
+// coalesced loads (six arrays of g.max_in values after M), so that the
+// three passes over the column and the interpolation read LDS instead of
+// re-reading HBM; used when the longest input column of the launch fits.
+template <bool kStage>
 __global__ __launch_bounds__(kWave) void k_optimize_grid(GridArgs g) {
-    extern __shared__ double M[];  // [max input points of the launch]
+    extern __shared__ double M[];  // [max input points of the launch] (+ 6 staged fields)
     const int lane = threadIdx.x;
     for (int64_t c = blockIdx.x; c < g.n_columns; c += gridDim.x) {
         const int64_t i0 = g.in_off[c], o0 = g.out_off[c];
         const int N = (int)(g.in_off[c + 1] - i0), n_out = (int)(g.out_off[c + 1] - o0);
-        const double *z = g.z + i0, *T = g.T + i0, *vz = g.vz + i0;
+        const double *z, *T, *ne, *nH, *vz, *vt;
+        if (kStage) {
+            double *S = M + g.max_in;
+            for (int k = lane; k < N; k += kWave) {
+                S[k] = g.z[i0 + k];
+                S[g.max_in + k] = g.T[i0 + k];
+                S[2 * g.max_in + k] = g.ne[i0 + k];
+                S[3 * g.max_in + k] = g.nH[i0 + k];
+                S[4 * g.max_in + k] = g.vz[i0 + k];
+                S[5 * g.max_in + k] = g.vt[i0 + k];
+            }
+            __syncthreads();
+            z = S; T = S + g.max_in; ne = S + 2 * g.max_in; nH = S + 3 * g.max_in; vz = S + 4 * g.max_in;
+            vt = S + 5 * g.max_in;
+        } else {
+            z = g.z + i0; T = g.T + i0; ne = g.ne + i0; nH = g.nH + i0; vz = g.vz + i0; vt = g.vt + i0;
+        }
         // input checks, as the solve makes them (microturbulence only finite)
         int bad = N < 2;
         for (int k = lane; k < N; k += kWave) {
-            const int64_t i = i0 + k;
-            if (!(g.T[i] > 0.0 && g.ne[i] > 0.0 && g.nH[i] > 0.0) ||
-                !isfinite(g.T[i] + g.ne[i] + g.nH[i] + g.vz[i] + g.vt[i] + g.z[i]))
+            if (!(T[k] > 0.0 && ne[k] > 0.0 && nH[k] > 0.0) || !isfinite(T[k] + ne[k] + nH[k] + vz[k] + vt[k] + z[k]))
                 bad = 1;
             if (k > 0 && !(z[k] < z[k - 1])) bad = 1;
         }
@@ -88,9 +109,9 @@ __global__ __launch_bounds__(kWave) void k_optimize_grid(GridArgs g) {
             // optical depth: local partial sums of the trapezoid increments
             double s = 0.0;
             if (k0 < hi) {
-                double kp = bg_opacity(g, i0 + k0 - 1);
+                double kp = bg_opacity(g.c_bg, T[k0 - 1], ne[k0 - 1], nH[k0 - 1]);
                 for (int k = k0; k < hi; k++) {
-                    const double kk = bg_opacity(g, i0 + k);
+                    const double kk = bg_opacity(g.c_bg, T[k], ne[k], nH[k]);
                     s += 0.5 * (kp + kk) * (z[k - 1] - z[k]);
                     M[k] = s;
                     kp = kk;
@@ -123,7 +144,6 @@ __global__ __launch_bounds__(kWave) void k_optimize_grid(GridArgs g) {
             for (int j = lane; j < n_out; j += kWave)
                 zo[j] = To[j] = neo[j] = nHo[j] = vzo[j] = vto[j] = NAN;
         } else {
-            const double *ne = g.ne + i0, *nH = g.nH + i0, *vt = g.vt + i0;
             for (int j = lane; j < n_out; j += kWave) {
                 if (j == 0 || j == n_out - 1) {
                     const int k = j == 0 ? 0 : N - 1;
@@ -233,9 +253,13 @@ int rh15d_optimize_grid(const rh15d_atom *atom, const rh15d_columns *in, const r
     g.wz = w[0]; g.wT = w[1]; g.wv = w[2]; g.wtau = w[3];
     g.c_bg = atom->bg_kind == 1 ? atom->c_bg : 0.0;
     g.n_columns = n;
+    g.max_in = (int)std::max<int64_t>(max_in, 1);
     const unsigned blocks = (unsigned)std::min<int64_t>(n, 1 << 20);
-    const size_t lds = (size_t)std::max<int64_t>(max_in, 1) * sizeof(double);
-    hipLaunchKernelGGL(k_optimize_grid, dim3(blocks), dim3(kWave), lds, st, g);
+    const size_t lds = (size_t)g.max_in * sizeof(double);
+    if (7 * lds <= kStageLds)
+        hipLaunchKernelGGL(k_optimize_grid<true>, dim3(blocks), dim3(kWave), 7 * lds, st, g);
+    else
+        hipLaunchKernelGGL(k_optimize_grid<false>, dim3(blocks), dim3(kWave), lds, st, g);
     e = hipGetLastError();
     (void)hipFreeAsync(doff, st);
     if (e != hipSuccess) { set_error("grid optimisation launch: %s", hipGetErrorString(e)); return RH15D_EDEVICE; }

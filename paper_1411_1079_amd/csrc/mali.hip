@@ -225,8 +225,10 @@ struct RunArgs {
     int rec_w;
     // inputs (global depth index)
     const double *z, *T, *ne, *nH, *vz, *vt, *init;
+    const double *Bf, *Bincl, *Bazim;   // magnetic field (NULL: none), read for the Stokes spectrum
     // outputs (global depth / column index)
     double *pops, *history, *spectrum, *psi;
+    double *stokes;           // [n_columns][NL][4] or NULL
     int32_t *n_iter, *status;
     // per slot
     int *slot_col, *slot_state, *slot_it, *ng_count, *ng_head;
@@ -1799,6 +1801,253 @@ __global__ __launch_bounds__(256) void k_emergent(RunArgs a, const TB *__restric
     }
 }
 
+// ---------------------------------------------------------------------------
+// polarised emergent spectrum (Zeeman effect), FP64
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ cplx_t<F> cdiv(cplx_t<F> a, cplx_t<F> b) {
+    const F d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+
+// Faddeeva function w(v + i a) = H + i L by the same four-region W4
+// approximation as voigt_w4, keeping the imaginary part (the dispersion
+// function L, odd in v), in FP64.
+__device__ __noinline__ cplx_t<double> faddeeva_w4(double a, double v) {
+    using C = cplx_t<double>;
+    const C t = {a, -v};
+    const double s = fabs(v) + a;
+    if (s >= 15.0) return cdiv(C{0.5641896 * t.r, 0.5641896 * t.i}, cadd(cmul(t, t), 0.5));
+    if (s >= 5.5) {
+        const C u = cmul(t, t);
+        const C num = cmul(t, cadd(C{0.5641896 * u.r, 0.5641896 * u.i}, 1.410474));
+        const C den = cadd(cmul(u, cadd(u, 3.0)), 0.75);
+        return cdiv(num, den);
+    }
+    if (a >= 0.195 * fabs(v) - 0.176) {
+        C num = {0.5642236, 0.0};
+        num = cadd(cmul(num, t), 3.778987);
+        num = cadd(cmul(num, t), 11.96482);
+        num = cadd(cmul(num, t), 20.20933);
+        num = cadd(cmul(num, t), 16.4955);
+        C den = {1.0, 0.0};
+        den = cadd(cmul(den, t), 6.699398);
+        den = cadd(cmul(den, t), 21.69274);
+        den = cadd(cmul(den, t), 39.27121);
+        den = cadd(cmul(den, t), 38.82363);
+        den = cadd(cmul(den, t), 16.4955);
+        return cdiv(num, den);
+    }
+    const C u = cmul(t, t);
+    C p = {0.56419, 0.0};
+    p = cadd(cmul(p, u), -1.320522);
+    p = cadd(cmul(p, u), 35.76683);
+    p = cadd(cmul(p, u), -219.0313);
+    p = cadd(cmul(p, u), 1540.787);
+    p = cadd(cmul(p, u), -3321.9905);
+    p = cadd(cmul(p, u), 36183.31);
+    C q = {-1.0, 0.0};
+    q = cadd(cmul(q, u), 1.841439);
+    q = cadd(cmul(q, u), -61.57037);
+    q = cadd(cmul(q, u), 364.2191);
+    q = cadd(cmul(q, u), -2186.181);
+    q = cadd(cmul(q, u), 9022.228);
+    q = cadd(cmul(q, u), -24322.84);
+    q = cadd(cmul(q, u), 32066.6);
+    const C f = cdiv(cmul(t, p), q);
+    const double eu = exp(u.r);
+    return {eu * cos(u.i) - f.r, eu * sin(u.i) - f.i};
+}
+
+// Absorption-matrix entries, emission vector and Planck function of one
+// depth point at one wavelength.
+struct StkPoint {
+    double chi;       // eta_I, total opacity
+    double k[6];      // eta_Q, eta_U, eta_V, rho_Q, rho_U, rho_V
+    double e[4];      // emission vector
+    double B;
+};
+
+// The transitions active at a lane's wavelength (up to kMaxSlots).
+struct StkTrans {
+    int na;
+    int t[kMaxSlots];
+    int rho_i[kMaxSlots];   // PRD line: index of this wavelength in the depth row of rho, else -1
+};
+
+__device__ void stokes_point(const RunArgs &a, const StkTrans &st, int64_t g, int64_t gc, int j, double nu,
+                             double lamfac, double hnu_k, double two_hnu3, double Bk, double ik, double ak,
+                             StkPoint &p) {
+    const DevAtom &A = a.A;
+    const int L = A.L;
+    const double T = a.T[g];
+    const double x = hnu_k / T;
+    p.B = two_hnu3 / expm1(x);
+    double chi = a.kbg[gc] * lamfac;
+    for (int i = 0; i < 6; i++) p.k[i] = 0.0;
+    p.e[0] = chi * p.B;
+    p.e[1] = p.e[2] = p.e[3] = 0.0;
+    const double ct = cos(ik), sn = sin(ik), s2 = sn * sn, c2 = cos(2.0 * ak), sn2 = sin(2.0 * ak);
+    const int rw = A.psi_cols / (2 * A.n_mu + 1);
+    for (int q = 0; q < st.na; q++) {
+        const DevTransition &tr = A.tr[st.t[q]];
+        const double nl = a.pops[g * L + tr.l], nup = a.pops[g * L + tr.u];
+        if (tr.kind != 0) {
+            const double r = tr.nu0 / nu;
+            const double alpha = tr.alpha0 * r * r * r;
+            const double G = a.gr[gc * A.n_cont + (st.t[q] - A.n_lines)] * exp(-x);
+            chi += (nl - nup * G) * alpha;
+            p.e[0] += nup * two_hnu3 * G * alpha;
+            continue;
+        }
+        const double rho = st.rho_i[q] >= 0 ? a.rho[gc * rw + st.rho_i[q]] : 1.0;
+        const double cc = tr.hnu4pi / a.norm[gc * A.n_lines + st.t[q]];
+        const double cabs = cc * (nl * tr.Blu - nup * tr.Bul * rho);
+        const double cem = cc * nup * tr.A * rho;
+        const double dnd = tr.nu0 / kC * sqrt(2.0 * kKB * T / A.mass + a.vt[g] * a.vt[g]);
+        const double ad = (tr.gamma + tr.c_el * a.nH[g]) / (4.0 * kPI * dnd);
+        const double v = (nu - tr.nu0 * (1.0 + a.vz[g] / kC)) / dnd;
+        const double pre = 1.0 / (sqrt(kPI) * dnd);
+        if (tr.n_zc == 0) {
+            const double H = tr.voigt ? faddeeva_w4(ad, v).r : exp(-v * v);
+            chi += cabs * H * pre;
+            p.e[0] += cem * H * pre;
+            continue;
+        }
+        const double vL = kQE * Bk / (4.0 * kPI * kME) / dnd;
+        double ph[3] = {0.0, 0.0, 0.0}, ps[3] = {0.0, 0.0, 0.0};
+        for (int c = tr.zc_off; c < tr.zc_off + tr.n_zc; c++) {
+            const double vc = v - A.zshift[c] * vL;
+            const cplx_t<double> w = faddeeva_w4(tr.voigt ? ad : 0.0, vc);
+            const double H = tr.voigt ? w.r : exp(-vc * vc);
+            const int iq = A.zq[c] + 1;
+            ph[iq] += A.zstr[c] * H;
+            ps[iq] += A.zstr[c] * w.i;
+        }
+        for (int i = 0; i < 3; i++) { ph[i] *= pre; ps[i] *= pre; }
+        // index 2: q = +1, index 0: q = -1
+        const double pI = 0.5 * (ph[1] * s2 + 0.5 * (ph[2] + ph[0]) * (1.0 + ct * ct));
+        const double pl = 0.5 * (ph[1] - 0.5 * (ph[2] + ph[0])) * s2;
+        const double pV = 0.5 * (ph[2] - ph[0]) * ct;
+        const double rl = 0.5 * (ps[1] - 0.5 * (ps[2] + ps[0])) * s2;
+        const double rV = 0.5 * (ps[2] - ps[0]) * ct;
+        chi += cabs * pI;
+        p.k[0] += cabs * pl * c2; p.k[1] += cabs * pl * sn2; p.k[2] += cabs * pV;
+        p.k[3] += cabs * rl * c2; p.k[4] += cabs * rl * sn2; p.k[5] += cabs * rV;
+        p.e[0] += cem * pI; p.e[1] += cem * pl * c2; p.e[2] += cem * pl * sn2; p.e[3] += cem * pV;
+    }
+    p.chi = chi;
+}
+
+// One DELO step (linear effective source function) from the deeper point d
+// to the point c, optical step x: solves
+//   (1 + wb K'_c) I_c = (e - wa K'_d) I_d + wa S'_d + wb S'_c,
+// K' = K / chi - 1, S' = eps / chi, in closed form: with the Q, U, V parts
+// e = wb (eta_Q, eta_U, eta_V) / chi and r = wb (rho_Q, rho_U, rho_V) / chi,
+// the system is x0 + e.x = y0, e x0 + x + x * r = y (x * r the cross
+// product), and (I + [. * r])^-1 b = (b - b * r + (b.r) r) / (1 + r.r)
+// with a Sherman-Morrison correction for the e e^T term.
+__device__ __forceinline__ void delo_step(const StkPoint &d, const StkPoint &c, double x, double I[4]) {
+    double e, wa, wb;
+    sc_weights<double>(x, e, wa, wb);
+    const double id = 1.0 / d.chi, ic = 1.0 / c.chi;
+    const double dQ = d.k[0] * id, dU = d.k[1] * id, dV = d.k[2] * id;
+    const double dq = d.k[3] * id, du = d.k[4] * id, dv = d.k[5] * id;
+    // K'_d I
+    const double k0 = dQ * I[1] + dU * I[2] + dV * I[3];
+    const double k1 = dQ * I[0] + dv * I[2] - du * I[3];
+    const double k2 = dU * I[0] - dv * I[1] + dq * I[3];
+    const double k3 = dV * I[0] + du * I[1] - dq * I[2];
+    const double y0 = e * I[0] - wa * k0 + wa * d.e[0] * id + wb * c.e[0] * ic;
+    const double y1 = e * I[1] - wa * k1 + wa * d.e[1] * id + wb * c.e[1] * ic;
+    const double y2 = e * I[2] - wa * k2 + wa * d.e[2] * id + wb * c.e[2] * ic;
+    const double y3 = e * I[3] - wa * k3 + wa * d.e[3] * id + wb * c.e[3] * ic;
+    const double wc = wb * ic;
+    const double e1 = c.k[0] * wc, e2 = c.k[1] * wc, e3 = c.k[2] * wc;
+    const double r1 = c.k[3] * wc, r2 = c.k[4] * wc, r3 = c.k[5] * wc;
+    const double b1 = y1 - e1 * y0, b2 = y2 - e2 * y0, b3 = y3 - e3 * y0;
+    const double rr = 1.0 / (1.0 + r1 * r1 + r2 * r2 + r3 * r3);
+    // A^-1 v = (v - v * r + (v.r) r) / (1 + r.r)
+    const double br = b1 * r1 + b2 * r2 + b3 * r3;
+    const double ab1 = (b1 - (b2 * r3 - b3 * r2) + br * r1) * rr;
+    const double ab2 = (b2 - (b3 * r1 - b1 * r3) + br * r2) * rr;
+    const double ab3 = (b3 - (b1 * r2 - b2 * r1) + br * r3) * rr;
+    const double er = e1 * r1 + e2 * r2 + e3 * r3;
+    const double ae1 = (e1 - (e2 * r3 - e3 * r2) + er * r1) * rr;
+    const double ae2 = (e2 - (e3 * r1 - e1 * r3) + er * r2) * rr;
+    const double ae3 = (e3 - (e1 * r2 - e2 * r1) + er * r3) * rr;
+    const double f = (e1 * ab1 + e2 * ab2 + e3 * ab3) / (1.0 - (e1 * ae1 + e2 * ae2 + e3 * ae3));
+    I[1] = ab1 + ae1 * f;
+    I[2] = ab2 + ae2 * f;
+    I[3] = ab3 + ae3 * f;
+    I[0] = y0 - (e1 * I[1] + e2 * I[2] + e3 * I[3]);
+}
+
+// One lane per (retired column, wavelength): the vertical upward Stokes
+// vector through the column's depth points.
+__global__ __launch_bounds__(256) void k_stokes(RunArgs a) {
+    const DevAtom &A = a.A;
+    const int64_t n = (int64_t)a.ctr[CTR_RETIRE] * A.NL;
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = a.retire_list[w / A.NL];
+        const int j = (int)(w % A.NL);
+        const ColGeom cg = geom(a, slot);
+        double *out = a.stokes + ((size_t)cg.col * A.NL + j) * 4;
+        if (a.status[cg.col] == RH15D_BAD_INPUT) {
+            out[0] = out[1] = out[2] = out[3] = NAN;
+            continue;
+        }
+        const double nu = A.nu[j];
+        const double lamfac = A.lam[j] / kBgLambdaRef;
+        const double hnu_k = kH * nu / kKB;
+        const double two_hnu3 = 2.0 * kH * nu * nu * nu / (kC * kC);
+        StkTrans st;
+        st.na = A.jact_off[j + 1] - A.jact_off[j];
+        for (int q = 0; q < kMaxSlots; q++) {
+            st.t[q] = 0;
+            st.rho_i[q] = -1;
+            if (q >= st.na) continue;
+            const int i = A.jact_off[j] + q;
+            const int t = A.jact_t[i];
+            st.t[q] = t;
+            if (a.prd && A.tr[t].prd) {
+                int off = 0;
+                for (int ip = 0; ip < A.n_prd && A.prd_t[ip] != t; ip++) off += A.tr[A.prd_t[ip]].n_act;
+                st.rho_i[q] = off + A.jact_ja[i];
+            }
+        }
+        const int N = cg.N;
+        const int64_t g0 = cg.g0, gc0 = cg.gc0;
+        bool ok = true;
+        auto field = [&](int k, double &Bk, double &ik, double &ak) {
+            if (a.Bf) {
+                Bk = a.Bf[g0 + k]; ik = a.Bincl[g0 + k]; ak = a.Bazim[g0 + k];
+                if (!isfinite(Bk + ik + ak)) { ok = false; Bk = ik = ak = 0.0; }
+            } else {
+                Bk = ik = ak = 0.0;
+            }
+        };
+        StkPoint pd, pc;
+        double Bk, ik, ak;
+        field(N - 1, Bk, ik, ak);
+        stokes_point(a, st, g0 + N - 1, gc0 + N - 1, j, nu, lamfac, hnu_k, two_hnu3, Bk, ik, ak, pd);
+        field(N - 2, Bk, ik, ak);
+        stokes_point(a, st, g0 + N - 2, gc0 + N - 2, j, nu, lamfac, hnu_k, two_hnu3, Bk, ik, ak, pc);
+        const double dtv = 0.5 * (pd.chi + pc.chi) * (a.z[g0 + N - 2] - a.z[g0 + N - 1]);
+        double I[4] = {dtv > 0.0 ? pd.B + (pd.B - pc.B) / dtv : pd.B, 0.0, 0.0, 0.0};
+        for (int k = N - 2; k >= 0; k--) {
+            if (k < N - 2) {
+                field(k, Bk, ik, ak);
+                stokes_point(a, st, g0 + k, gc0 + k, j, nu, lamfac, hnu_k, two_hnu3, Bk, ik, ak, pc);
+            }
+            const double x = 0.5 * (pd.chi + pc.chi) * (a.z[g0 + k] - a.z[g0 + k + 1]);
+            delo_step(pd, pc, x, I);
+            pd = pc;
+        }
+        for (int i = 0; i < 4; i++) out[i] = ok ? I[i] : NAN;
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_psi_gather(RunArgs a) {
     const DevAtom &A = a.A;
@@ -2055,6 +2304,8 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bo
     D.g_cols = 0;
     std::vector<int> act_j;
     std::vector<double> act_w;
+    std::vector<int> zq;
+    std::vector<double> zshift, zstr;
     int ray_off = 0;
     for (int t = 0; t < D.T; t++) {
         const auto &h = atom->tr[t];
@@ -2068,6 +2319,11 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bo
         d.nu0 = h.nu0; d.A = h.A; d.Bul = h.Bul; d.Blu = h.Blu; d.alpha0 = h.alpha0; d.coll_val = h.coll_val;
         d.gamma = h.gamma; d.hnu4pi = kH * h.nu0 / (4.0 * kPI);
         d.c_el = h.c_el;
+        d.n_zc = static_cast<int>(h.zq.size());
+        d.zc_off = static_cast<int>(zq.size());
+        zq.insert(zq.end(), h.zq.begin(), h.zq.end());
+        zshift.insert(zshift.end(), h.zshift.begin(), h.zshift.end());
+        zstr.insert(zstr.end(), h.zstr.begin(), h.zstr.end());
         d.prd = h.kind == 0 && h.prd;
         d.psi_off = H.psi_off[t];
         d.g_off = -1;
@@ -2099,6 +2355,7 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bo
     std::vector<int> st(atom->stage);
 #define UP(vec, dst) do { if ((rc = upload(atom, vec, dst)) != RH15D_OK) return rc; } while (0)
     UP(E, &D.E); UP(g, &D.g); UP(st, &D.stage); UP(tr, &D.tr);
+    UP(zq, &D.zq); UP(zshift, &D.zshift); UP(zstr, &D.zstr);
     std::vector<double> lam(atom->lam), nu(atom->nu);
     UP(lam, &D.lam); UP(nu, &D.nu); UP(act_j, &D.act_j); UP(act_w, &D.act_w);
     UP(H.mu, &D.mu); UP(H.wmu, &D.wmu);
@@ -2310,6 +2567,9 @@ int validate(const rh15d_atom *atom, const rh15d_columns *cols, const rh15d_opti
     if (cols->n_columns > 0 && (!cols->z || !cols->T || !cols->n_e || !cols->n_H || !cols->v_z || !cols->v_turb)) {
         set_error("null column array"); return RH15D_EINVAL;
     }
+    if ((cols->B != nullptr) != (cols->B_incl != nullptr) || (cols->B != nullptr) != (cols->B_azim != nullptr)) {
+        set_error("the magnetic field needs all of B, B_incl and B_azim, or none"); return RH15D_EINVAL;
+    }
     return RH15D_OK;
 }
 
@@ -2451,7 +2711,7 @@ struct Launcher {
     RunArgs a;
     bool fp32;
     int start;
-    bool want_spec, want_psi;
+    bool want_spec, want_psi, want_stokes;
     hipStream_t st;
     SideStreams *side = nullptr;
 
@@ -2513,6 +2773,8 @@ struct Launcher {
                                    reinterpret_cast<const double *>(a.rec), reinterpret_cast<const double *>(a.phi),
                                    a.pops);
         }
+        if (want_stokes)
+            hipLaunchKernelGGL(k_stokes, dim3(grid_for((int64_t)a.S * a.A.NL, 256, 8192)), dim3(256), 0, st, a);
         if (want_psi) {
             if (fp32) launch_sweep<float, MODE_PSI>(a, st, side);
             else launch_sweep<double, MODE_PSI>(a, st, side);
@@ -2684,6 +2946,8 @@ int solve_columns_impl(const rh15d_atom *atom_c, const rh15d_columns *cols, cons
     a.rec_w = rec_width(D->n_cont);
     a.z = cols->z; a.T = cols->T; a.ne = cols->n_e; a.nH = cols->n_H; a.vz = cols->v_z; a.vt = cols->v_turb;
     a.init = cols->init_pops;
+    a.Bf = cols->B; a.Bincl = cols->B_incl; a.Bazim = cols->B_azim;
+    a.stokes = out->stokes;
     a.pops = out->pops; a.history = out->history; a.spectrum = out->spectrum; a.psi = out->psi_star;
     a.n_iter = out->n_iter; a.status = out->status;
     int *slots = reinterpret_cast<int *>(ws + lay.off_slots);
@@ -2714,7 +2978,7 @@ int solve_columns_impl(const rh15d_atom *atom_c, const rh15d_columns *cols, cons
     a.emis = ws + lay.off_psi; a.ist = ws + lay.off_ist; a.gtab = ws + lay.off_gtab;
     a.rho = reinterpret_cast<double *>(ws + lay.off_rho);
 
-    Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr, st};
+    Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr, out->stokes != nullptr, st};
     Timer tm;
     if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { free_host(); if (own) (void)hipFree(own); return rc; }
     // the sweep's classes run concurrently on side streams, or one after

@@ -45,6 +45,10 @@ struct HostTransition {
     double c_el = 0;          // elastic-collision rate per hydrogen atom, m^3 s^-1
     int voigt = 0, coll_kind = 0;
     int prd = 0;              // line with partial frequency redistribution
+    // Zeeman components of a line whose levels carry J and g: q = M_l - M_u,
+    // shift g_u M_u - g_l M_l (Larmor frequencies), strength (sums to 1 per q)
+    std::vector<int> zq;
+    std::vector<double> zshift, zstr;
     std::vector<double> own;  // own sampling, m
     // derived
     double nu0 = 0, A = 0, Bul = 0, Blu = 0, gamma = 0, lam_min = 0, lam_max = 0;
@@ -62,6 +66,7 @@ struct DevTransition {
     double alpha0, coll_val, gamma, hnu4pi;   // hnu4pi = h nu0 / (4 pi)
     double wsum;                              // sum of the trapezoid weights
     double c_el;                              // elastic-collision rate per hydrogen atom
+    int n_zc, zc_off;                         // Zeeman components (0: not split) and their offset
 };
 
 // A group: up to 64 rays of one direction sharing one set of transitions.
@@ -135,6 +140,9 @@ struct DevAtom {
     int g_cols;                 // redistribution weights per depth row: sum over PRD lines of n_act^2
     int *prd_t;                 // [n_prd] line index of each PRD line
     int *st_idx;                // [NL] stored-wavelength index of each wavelength, or -1
+    // Zeeman components of the split lines, concatenated (DevTransition.zc_off)
+    int *zq;
+    double *zshift, *zstr;
     // algorithmic work of one rate-mode sweep per depth point of a column
     double rays_per_depth;        // rays (wavelength x angle x direction)
     double flops_per_depth;       // see k_raysweep: 27 + 19 n_slots + 4 n_pairs per ray-step
@@ -171,6 +179,8 @@ struct rh15d_atom {
     int L = 0, n_lines = 0, n_cont = 0;
     std::vector<double> E, g;
     std::vector<int> stage;
+    std::vector<int> twoJ;                  // 2 J per level, -1 if the atom gives none
+    std::vector<double> gL;                 // Lande factor per level
     std::vector<rh15d::HostTransition> tr;  // lines, then continua
     std::vector<double> lam, nu;            // union grid
     std::vector<int> jact_off, jact_t;
@@ -185,6 +195,7 @@ namespace rh15d {
 // host setup (atom_setup.cpp)
 int parse_atom_file(const char *path, rh15d_atom *a, std::string &err);
 void gauss_legendre_01(int n, std::vector<double> &x, std::vector<double> &w);
+void zeeman_components(int twoJl, double gl, int twoJu, double gu, HostTransition &t);
 void build_group_tables(const rh15d_atom &a, int n_mu, SweepShape shape, HostGroupTables &out);
 void set_error(const char *fmt, ...);
 const char *last_error();

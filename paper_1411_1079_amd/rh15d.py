@@ -39,7 +39,8 @@ class AtomInfo(C.Structure):
 
 class Columns(C.Structure):
     _fields_ = [("n_columns", C.c_int64), ("depth_offset", C.POINTER(C.c_int64))] + \
-               [(n, C.c_void_p) for n in ("z", "T", "n_e", "n_H", "v_z", "v_turb", "init_pops")]
+               [(n, C.c_void_p) for n in ("z", "T", "n_e", "n_H", "v_z", "v_turb", "init_pops", "B", "B_incl",
+                                          "B_azim")]
 
 
 class Options(C.Structure):
@@ -75,7 +76,7 @@ class GridOutput(C.Structure):
 
 
 class Outputs(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star")]
+    _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes")]
 
 
 _lib = None
@@ -190,6 +191,9 @@ class DeviceColumns:
     v_z: object
     v_turb: object
     init_pops: object = None
+    B: object = None          # magnetic field strength [T], inclination and azimuth [rad] (all or none)
+    B_incl: object = None
+    B_azim: object = None
 
     @property
     def n_columns(self):
@@ -200,12 +204,14 @@ class DeviceColumns:
         return int(self.offset[-1])
 
     @staticmethod
-    def from_host(cols, device="cuda", init_pops=None):
+    def from_host(cols, device="cuda", init_pops=None, field=None):
+        """field: None or (B, B_incl, B_azim) host arrays [total_depth]."""
         import torch
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+        f = (None, None, None) if field is None else tuple(t(x) for x in field)
         return DeviceColumns(offset=np.ascontiguousarray(cols.offset, dtype=np.int64), z=t(cols.z), T=t(cols.T),
                              n_e=t(cols.n_e), n_H=t(cols.n_H), v_z=t(cols.v_z), v_turb=t(cols.v_turb),
-                             init_pops=None if init_pops is None else t(init_pops))
+                             init_pops=None if init_pops is None else t(init_pops), B=f[0], B_incl=f[1], B_azim=f[2])
 
 
 def _cols_struct(dc: DeviceColumns) -> Columns:
@@ -218,6 +224,11 @@ def _cols_struct(dc: DeviceColumns) -> Columns:
         assert ten.dtype.is_floating_point and ten.element_size() == 8 and ten.is_contiguous()
         setattr(s, n, ten.data_ptr())
     s.init_pops = dc.init_pops.data_ptr() if dc.init_pops is not None else None
+    for n in ("B", "B_incl", "B_azim"):
+        ten = getattr(dc, n, None)
+        if ten is not None:
+            assert ten.dtype.is_floating_point and ten.element_size() == 8 and ten.is_contiguous()
+        setattr(s, n, ten.data_ptr() if ten is not None else None)
     return s
 
 
@@ -236,7 +247,7 @@ class Solver:
     """Reusable output and workspace buffers for repeated solves."""
 
     def __init__(self, atom: Atom, dc: DeviceColumns, opts: Options, want_spectrum=True, want_psi=False,
-                 want_history=True, workspace=None):
+                 want_history=True, workspace=None, want_stokes=False):
         import torch
         self.atom, self.dc, self.opts = atom, dc, opts
         dev = dc.z.device
@@ -248,6 +259,7 @@ class Solver:
         self.spectrum = torch.empty((n, atom.n_lambda), dtype=torch.float64, device=dev) if want_spectrum else None
         self.psi_star = (torch.empty((dc.total_depth, atom.n_transitions), dtype=torch.float64, device=dev)
                          if want_psi else None)
+        self.stokes = torch.empty((n, atom.n_lambda, 4), dtype=torch.float64, device=dev) if want_stokes else None
         self.ws_bytes = workspace_size(atom, dc, opts)
         if workspace is None:
             workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
@@ -256,7 +268,7 @@ class Solver:
         self.workspace = workspace
         self._cols = _cols_struct(dc)
         self._out = Outputs()
-        for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star"):
+        for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes"):
             ten = getattr(self, name)
             setattr(self._out, name, ten.data_ptr() if ten is not None else None)
 
@@ -286,6 +298,8 @@ class Solver:
             out["spectrum"] = self.spectrum
         if self.psi_star is not None:
             out["psi_star"] = self.psi_star
+        if self.stokes is not None:
+            out["stokes"] = self.stokes
         return out
 
 
@@ -320,15 +334,21 @@ def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stre
             if dc.init_pops is None:
                 raise ValueError("a provided start needs the columns' init_pops")
             init = torch.index_select(dc.init_pops, 0, it)
+        if dc.B is not None:
+            for k in ("B", "B_incl", "B_azim"):
+                fields[k] = torch.index_select(getattr(dc, k), 0, it)
         sub = DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), init_pops=init, **fields)
         r = Solver(atom, sub, opts, want_spectrum=out.get("spectrum") is not None,
-                   want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None).run(st)
+                   want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None,
+                   want_stokes=out.get("stokes") is not None).run(st)
         cb = torch.as_tensor(bad, dtype=torch.int64, device=dev)
         out["pops"].index_copy_(0, it, r.pops)
         if out.get("psi_star") is not None:
             out["psi_star"].index_copy_(0, it, r.psi_star)
         if out.get("spectrum") is not None:
             out["spectrum"].index_copy_(0, cb, r.spectrum)
+        if out.get("stokes") is not None:
+            out["stokes"].index_copy_(0, cb, r.stokes)
         n1 = out["n_iter"].index_select(0, cb)
         if out.get("history") is not None:
             # the first attempt's n1 entries, then the second attempt's
@@ -344,11 +364,11 @@ def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stre
     return int(bad.size)
 
 
-def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, **opts) -> dict:
+def solve(atom: Atom, dc: DeviceColumns, want_spectrum=True, want_psi=False, want_stokes=False, **opts) -> dict:
     """Solve every column; returns CUDA tensors (pops, history, n_iter,
-    status, spectrum, psi_star)."""
+    status, spectrum, psi_star, stokes)."""
     o = default_options(**opts)
-    return Solver(atom, dc, o, want_spectrum=want_spectrum, want_psi=want_psi).run().result()
+    return Solver(atom, dc, o, want_spectrum=want_spectrum, want_psi=want_psi, want_stokes=want_stokes).run().result()
 
 
 def autotune(atom: Atom, dc: DeviceColumns, stream=None, **opts) -> dict:

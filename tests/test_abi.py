@@ -124,3 +124,19 @@ def test_grid_defaults_and_empty_call(atom_dir):
     assert (o.w_z, o.w_T, o.w_v, o.w_tau) == (1.0, 2.0, 2.0e-4, 0.2)
     a = rh15d.Atom(atom_dir["h6"])
     assert _grid_call(a, [], []) == 0   # nothing to do, nothing launched
+
+
+def test_partial_magnetic_field_rejected(atom_dir):
+    a = rh15d.Atom(atom_dir["zeeman_tiny"])
+    dc = _fake_columns([5, 6])
+    dc.B = _FakeTensor(np.ones(11))
+    with pytest.raises(rh15d.RH15DError) as e:
+        rh15d.workspace_size(a, dc, rh15d.default_options())
+    assert e.value.code == -1 and "B_incl" in str(e.value)
+
+
+def test_zeeman_atoms_load_on_host(atom_dir):
+    for key in ("zeeman_tiny", "zeeman_tiny_prd", "ca2", "ca2_crd"):
+        a = rh15d.Atom(atom_dir[key])
+        o = O.Atom(atom_dir[key])
+        assert (a.n_levels, a.n_lines, a.n_continua, a.n_lambda) == (o.n_levels, o.n_lines, o.n_cont, o.n_lambda)
