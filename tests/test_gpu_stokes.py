@@ -97,15 +97,17 @@ def test_prd_line_uses_the_final_rho(atom_dir):
 
 
 def test_fp32_form_within_1e3(atom_dir):
+    """The precision error alone: the FP32 form and the oracle both run 80
+    iterations (no change test), and the Stokes vector of the FP32 form's
+    populations (computed in FP64) is within 1e-3 of the oracle's."""
     cols, fields = zeeman_columns()
-    # FP32 rates stop improving near 1e-6 relative: the change test at 1e-5
-    r = _solve(atom_dir["zeeman_tiny"], cols, _field_arrays(fields), precision=1, scheduler=1, n_mu=3, tol=1e-5,
-               max_iter=400)
-    assert np.all(r["status"] == 0)
+    kw = dict(n_mu=3, tol=0.0, max_iter=80)
+    r = _solve(atom_dir["zeeman_tiny"], cols, _field_arrays(fields), precision=1, scheduler=1, **kw)
+    assert np.all(r["status"] == 1) and np.all(r["n_iter"] == 80)
     a = O.Atom(atom_dir["zeeman_tiny"])
     for c in range(cols.n_columns):
         col = cols.column(c)
-        ref = O.solve_column(a, col, n_mu=3, tol=1e-10, max_iter=400)
+        ref = O.solve_column(a, col, **kw)
         st = O.stokes_column(a, col, ref["pops"], 3, *fields[c])
         _compare(r["stokes"][c], st, 1e-3, f"FP32 column {c}")
 
