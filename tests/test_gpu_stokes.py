@@ -99,8 +99,14 @@ def test_prd_line_uses_the_final_rho(atom_dir):
 def test_fp32_form_within_1e3(atom_dir):
     """The precision error alone: the FP32 form and the oracle both run 80
     iterations (no change test), and the Stokes vector of the FP32 form's
-    populations (computed in FP64) is within 1e-3 of the oracle's."""
+    populations (computed in FP64) is within 1e-3 of the oracle's.  The two
+    columns converge by then (the oracle's change is below 3e-6 and its
+    populations within 1e-5 of its 1e-10 answer); the third column of
+    zeeman_columns still changes by 3e-4 per iteration at 80 iterations and
+    is 0.8 % from its fixed point, where a comparison at a fixed count
+    measures the trajectory rather than the precision."""
     cols, fields = zeeman_columns()
+    cols, fields = cols.select([0, 1]), fields[:2]
     kw = dict(n_mu=3, tol=0.0, max_iter=80)
     r = _solve(atom_dir["zeeman_tiny"], cols, _field_arrays(fields), precision=1, scheduler=1, **kw)
     assert np.all(r["status"] == 1) and np.all(r["n_iter"] == 80)
