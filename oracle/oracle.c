@@ -819,7 +819,7 @@ static void transition_terms(const colstate *cs, const double *n, int t, int ja,
 /* One formal-solution sweep over all rays with populations n.
  * mode 0: preconditioned rates; mode 1: zero-radiation rates (I_eff = 0,
  * Psi* = 0); mode 2: Psi* averaged per transition into psi_out[T][N]. */
-static void sweep(const colstate *cs, const double *n, int mode, rates *R, double *psi_out) {
+static void sweep(const colstate *cs, const double *n, int mode, rates *R, double *psi_out, double *psi_ray) {
     const orc_atom *a = cs->a;
     int N = cs->N, L = a->L, T = a->T;
     double *chi = malloc(sizeof(double) * N), *eta = malloc(sizeof(double) * N), *S = malloc(sizeof(double) * N);
@@ -898,6 +898,8 @@ static void sweep(const colstate *cs, const double *n, int mode, rates *R, doubl
                         if (Is) Is[k] = I;
                     }
                 }
+                if (psi_ray)
+                    for (int k = 0; k < N; k++) psi_ray[(((size_t)k * a->NL + j) * cs->nmu + m) * 2 + s] = psi[k];
                 /* accumulation */
                 for (int q = 0; q < na; q++) {
                     int t = act[q];
@@ -1305,19 +1307,19 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
 
     memcpy(n, cs.nstar, sizeof(double) * NV);
     if (o->start == 1) {
-        sweep(&cs, n, 1, &R, NULL);
+        sweep(&cs, n, 1, &R, NULL, NULL);
         solve_se(&cs, &R, cs.nstar, n, 1.0);
     } else if (o->start == 2 && init_pops) {
         memcpy(n, init_pops, sizeof(double) * NV);
     } else if (o->start == 3) {
-        sweep(&cs, n, 1, &R, NULL);
+        sweep(&cs, n, 1, &R, NULL, NULL);
         escape_start(&cs, &R, o->esc_iter, n);
     }
     if (history) for (int i = 0; i < o->max_iter; i++) history[i] = NAN;
     int st = 1, it;
     double dprev = -1.0;   /* change of the previous iteration (none yet) */
     for (it = 1; it <= o->max_iter; it++) {
-        sweep(&cs, n, 0, &R, NULL);
+        sweep(&cs, n, 0, &R, NULL, NULL);
         /* while collisions are switched (cf > 1) the iterate solves another
          * problem: it may not end the iteration or enter Ng's history */
         const double cf = orc_crs_factor(o->crs_f0, it);
@@ -1362,7 +1364,7 @@ int orc_solve_column(const orc_atom *a, int N, const double *z, const double *T,
     *status = st;
     memcpy(pops, n, sizeof(double) * NV);
     if (spectrum) emergent(&cs, n, spectrum);
-    if (psi_star) sweep(&cs, n, 2, NULL, psi_star);
+    if (psi_star) sweep(&cs, n, 2, NULL, psi_star, NULL);
     if (prd_rho && prd)
         for (int t = 0; t < a->n_lines; t++)
             if (cs.rho[t]) {
@@ -1699,6 +1701,39 @@ int orc_stokes_coefficients(const orc_atom *a, int N, const double *z, const dou
     column_prepare(&cs, 1.0);
     double Bnu;
     stokes_point(&cs, pops, Bf, incl, azim, j, k, &out[0], &out[1], &out[7], &Bnu);
+    column_release(&cs);
+    free(cs.mu); free(cs.wmu);
+    return 0;
+}
+
+/* Psi* of every ray (Lambda* over chi, 0 at the ray's boundary point) of a
+ * column with populations pops [N][L] (and the final rho of its PRD lines
+ * as orc_solve_column returns it, or NULL), the diagonal that the
+ * per-transition Psi* of orc_solve_column averages; out: [N][NL][n_mu][2]
+ * (direction 0 down, 1 up) (tests only). */
+int orc_column_psi_ray(const orc_atom *a, int N, const double *z, const double *T, const double *ne, const double *nH,
+                       const double *vz, const double *vt, int n_mu, const double *pops, const double *prd_rho,
+                       double *out) {
+    if (!column_valid(N, z, T, ne, nH, vz, vt)) FAIL(-3, "column data cannot be used");
+    colstate cs = {0};
+    cs.a = a; cs.N = N; cs.nmu = n_mu; cs.z = z; cs.T = T; cs.ne = ne; cs.nH = nH; cs.vz = vz; cs.vt = vt;
+    cs.mu = malloc(sizeof(double) * n_mu); cs.wmu = malloc(sizeof(double) * n_mu);
+    orc_gauss_legendre(n_mu, cs.mu, cs.wmu);
+    column_prepare(&cs, 1.0);
+    if (prd_rho) {
+        cs.rho = calloc(a->n_lines ? a->n_lines : 1, sizeof(double *));
+        cs.gII = calloc(a->n_lines ? a->n_lines : 1, sizeof(double *));
+        for (int t = 0; t < a->n_lines; t++)
+            if (a->tr[t].prd) {
+                size_t m = (size_t)N * a->tr[t].n_act;
+                cs.rho[t] = malloc(sizeof(double) * m);
+                memcpy(cs.rho[t], prd_rho, sizeof(double) * m);
+                prd_rho += m;
+            }
+    }
+    double *tmp = malloc(sizeof(double) * (size_t)a->T * N);
+    sweep(&cs, pops, 2, NULL, tmp, out);
+    free(tmp);
     column_release(&cs);
     free(cs.mu); free(cs.wmu);
     return 0;

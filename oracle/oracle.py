@@ -74,6 +74,7 @@ def lib():
         L.orc_voigt_w.restype = None
         L.orc_stokes_formal.argtypes = [C.c_int] + [dp] * 6
         L.orc_stokes_column.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int] + [dp] * 6
+        L.orc_column_psi_ray.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int, dp, dp, dp]
         L.orc_stokes_coefficients.argtypes = [C.c_void_p, C.c_int] + [dp] * 6 + [C.c_int] + [dp] * 4 + \
             [C.c_int, C.c_int, dp]
         _lib = L
@@ -349,3 +350,19 @@ def stokes_coefficients(atom: Atom, col: dict, pops, n_mu: int, B, incl, azim, j
     if rc != 0:
         raise ValueError(lib().orc_last_error().decode())
     return dict(chi=out[0], K6=out[1:7], eps=out[7:11])
+
+
+def column_psi_ray(atom: Atom, col: dict, pops, n_mu: int, prd_rho=None) -> np.ndarray:
+    """Psi* of every ray [N][NL][n_mu][2] from given populations (see
+    orc_column_psi_ray)."""
+    N = len(col["z"])
+    cols = {k: np.ascontiguousarray(col[k], dtype=np.float64) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")}
+    n = np.ascontiguousarray(pops, dtype=np.float64).reshape(N, -1)
+    rho = None if prd_rho is None or len(prd_rho) == 0 else np.ascontiguousarray(
+        np.concatenate([np.asarray(r, dtype=np.float64).ravel() for r in prd_rho]))
+    out = np.empty((N, atom.n_lambda, n_mu, 2))
+    rc = lib().orc_column_psi_ray(atom._h, N, *(_p(cols[k]) for k in ("z", "T", "n_e", "n_H", "v_z", "v_turb")),
+                                  n_mu, _p(n), _p(rho), _p(out))
+    if rc != 0:
+        raise ValueError(lib().orc_last_error().decode())
+    return out

@@ -506,3 +506,19 @@ class Problem:
                     om = W * self.phi[ti][k, r] if d["kind"] == 0 else W / wsum[ti]
                     out[ti, k] += om * lst[k] / chi[k]
         return out
+
+
+def psi_ray(P: Problem, n):
+    """Psi* = Lambda*_kk / chi_k of every ray, [N][NL][n_mu][2] (0 where the
+    ray has no active transition)."""
+    NL, nmu = len(P.a.lam), len(P.mu)
+    out = np.zeros((P.N, NL, nmu, 2))
+    for r, (j, m, s) in enumerate(P.rays):
+        if not P.active(r):
+            continue
+        chi, _, _ = P.opacities(r, n)
+        order, M, _, _ = P.ray_operator(r, chi)
+        lst = np.zeros(P.N)
+        lst[order] = np.diag(M)
+        out[:, j, m, s] = lst / chi
+    return out

@@ -327,6 +327,21 @@ def test_bruteforce_emergent_and_psi_star(tiny):
     np.testing.assert_allclose(r["psi_star"], ps, rtol=1e-11, atol=1e-13 * np.abs(ps).max())
 
 
+def test_bruteforce_psi_of_every_ray(tiny):
+    """Psi* of every ray (the diagonal the per-transition Psi* averages)
+    against the diagonal of the exact Lambda matrix (40-digit mpmath) over
+    the ray's opacity, and its W phi average against the per-transition
+    output of the solve."""
+    import brute
+    a, b, col, P, cs = tiny
+    r = O.solve_column(a, col, n_mu=3, tol=1e-12, max_iter=500, ng_order=0, coll_scale=cs, want_psi=True)
+    pr = O.column_psi_ray(a, col, r["pops"], 3)
+    ref = brute.psi_ray(P, r["pops"])
+    np.testing.assert_allclose(pr, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+    # boundary points: 0 for the downward rays at the top, the upward ones at the bottom
+    assert np.all(pr[0, :, :, 0] == 0.0) and np.all(pr[-1, :, :, 1] == 0.0)
+
+
 def test_zero_radiation_start_two_level_closed_form(atom_dir):
     """Zero radiation start: with J = 0 the two-level balance is
     n_u / n_l = C_lu / (A_ul + C_ul)."""
