@@ -236,6 +236,14 @@ typedef struct {
                            source function (Rees, Durrant & Murphy 1989) on the
                            depth points; the bottom enters as (B_nu + dB_nu/dtau,
                            0, 0, 0).  With no field it equals (spectrum, 0, 0, 0). */
+    double *psi_ray;    /* DEVICE [total_depth][n_lambda][n_mu][2] Psi* = Lambda* / chi of every
+                           ray of the final formal solution (the diagonal of the local
+                           approximate operator, Sec. 2.1), per depth point, wavelength,
+                           angle and direction (0 downward, 1 upward), m; 0 at a ray's
+                           boundary point and where no transition is active at the
+                           wavelength; NaN for a column with status RH15D_BAD_INPUT.
+                           8 n_lambda n_mu 2 bytes per depth point: for small problems
+                           (tests, single columns); may be NULL */
 } rh15d_outputs;
 
 /* Fill *opt with the defaults: FP64, 5 angles, tol 1e-4, tol_fp 0, 200

@@ -229,6 +229,7 @@ struct RunArgs {
     // outputs (global depth / column index)
     double *pops, *history, *spectrum, *psi;
     double *stokes;           // [n_columns][NL][4] or NULL
+    double *psi_ray;          // [total_depth][NL][n_mu][2] or NULL
     int32_t *n_iter, *status;
     // per slot
     int *slot_col, *slot_state, *slot_it, *ng_count, *ng_head;
@@ -767,6 +768,23 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         // Psi* weights: W phi~ for lines, W / sum W for continua (W = w_nu w_mu / 2)
         wpsi[q] = sl.kind[q] == 1 ? R(0.5) * wj / sl.wsum[q] : R(0.5) * wj;
     }
+    // Psi* of every ray (final stage, when the caller asks for it): the
+    // lane's rays are (wavelength j, angles m0.., direction s_dir)
+    double *pray = nullptr;
+    int64_t pray_base = 0;
+    bool pray_nan = false;
+    if constexpr (MODE == MODE_PSI) {
+        if (a.psi_ray && lane < G.n_lanes) {
+            pray = a.psi_ray;
+            pray_base = ((int64_t)A.lanes.j[li] * A.n_mu + m0) * 2 + s_dir;
+            pray_nan = a.status[cg.col] == RH15D_BAD_INPUT;
+        }
+    }
+    const int64_t pray_row = (int64_t)A.NL * A.n_mu * 2;
+    auto store_psi = [&](int kk, int r, R v) {
+        if constexpr (MODE == MODE_PSI)
+            if (pray) pray[(g0 + kk) * pray_row + pray_base + 2 * r] = pray_nan ? NAN : static_cast<double>(v);
+    };
     R mu[MC], hinvmu[MC], wmu[MC];     // hinvmu = 1 / (2 mu)
 #pragma unroll
     for (int r = 0; r < MC; r++) {
@@ -841,6 +859,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
                 I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
             }
             store_I(k, r, I0);
+            store_psi(k, r, R(0));
             if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], I0, R(0), acc);
             else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], I0, R(0), acc);
             I[r] = I0;
@@ -870,6 +889,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
             const R Ieff = up + psi * sh.etabg;
             I[r] = up + wb * p.S;
             store_I(k, r, I[r]);
+            store_psi(k, r, psi);
             if (r == 0) contribute<R, NS, MODE, true>(p, wpsi, wmu[r], Ieff, psi, acc);
             else contribute<R, NS, MODE, false>(p, wpsi, wmu[r], Ieff, psi, acc);
             chi_p[r] = p.chi;
@@ -2779,8 +2799,10 @@ struct Launcher {
             if (fp32) launch_sweep<float, MODE_PSI>(a, st, side);
             else launch_sweep<double, MODE_PSI>(a, st, side);
             const unsigned gb = grid_for((int64_t)a.S * a.ND * a.A.T, 256, 16384);
-            if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3(gb), dim3(256), 0, st, a);
-            else hipLaunchKernelGGL(k_psi_gather<double>, dim3(gb), dim3(256), 0, st, a);
+            if (a.psi) {
+                if (fp32) hipLaunchKernelGGL(k_psi_gather<float>, dim3(gb), dim3(256), 0, st, a);
+                else hipLaunchKernelGGL(k_psi_gather<double>, dim3(gb), dim3(256), 0, st, a);
+            }
         }
         if (tm) tm->mark(6, st);
         refill_phase(tm);
@@ -2948,6 +2970,7 @@ int solve_columns_impl(const rh15d_atom *atom_c, const rh15d_columns *cols, cons
     a.init = cols->init_pops;
     a.Bf = cols->B; a.Bincl = cols->B_incl; a.Bazim = cols->B_azim;
     a.stokes = out->stokes;
+    a.psi_ray = out->psi_ray;
     a.pops = out->pops; a.history = out->history; a.spectrum = out->spectrum; a.psi = out->psi_star;
     a.n_iter = out->n_iter; a.status = out->status;
     int *slots = reinterpret_cast<int *>(ws + lay.off_slots);
@@ -2978,7 +3001,8 @@ int solve_columns_impl(const rh15d_atom *atom_c, const rh15d_columns *cols, cons
     a.emis = ws + lay.off_psi; a.ist = ws + lay.off_ist; a.gtab = ws + lay.off_gtab;
     a.rho = reinterpret_cast<double *>(ws + lay.off_rho);
 
-    Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr, out->stokes != nullptr, st};
+    Launcher run{a, fp32, o->start, out->spectrum != nullptr, out->psi_star != nullptr || out->psi_ray != nullptr,
+                 out->stokes != nullptr, st};
     Timer tm;
     if ((rc = tm.init(o->profile != 0)) != RH15D_OK) { free_host(); if (own) (void)hipFree(own); return rc; }
     // the sweep's classes run concurrently on side streams, or one after

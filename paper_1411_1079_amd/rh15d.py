@@ -76,7 +76,8 @@ class GridOutput(C.Structure):
 
 
 class Outputs(C.Structure):
-    _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes")]
+    _fields_ = [(n, C.c_void_p) for n in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes",
+                                          "psi_ray")]
 
 
 _lib = None
@@ -247,7 +248,7 @@ class Solver:
     """Reusable output and workspace buffers for repeated solves."""
 
     def __init__(self, atom: Atom, dc: DeviceColumns, opts: Options, want_spectrum=True, want_psi=False,
-                 want_history=True, workspace=None, want_stokes=False):
+                 want_history=True, workspace=None, want_stokes=False, want_psi_ray=False):
         import torch
         self.atom, self.dc, self.opts = atom, dc, opts
         dev = dc.z.device
@@ -260,6 +261,8 @@ class Solver:
         self.psi_star = (torch.empty((dc.total_depth, atom.n_transitions), dtype=torch.float64, device=dev)
                          if want_psi else None)
         self.stokes = torch.empty((n, atom.n_lambda, 4), dtype=torch.float64, device=dev) if want_stokes else None
+        self.psi_ray = (torch.empty((dc.total_depth, atom.n_lambda, opts.n_mu, 2), dtype=torch.float64, device=dev)
+                        if want_psi_ray else None)
         self.ws_bytes = workspace_size(atom, dc, opts)
         if workspace is None:
             workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
@@ -268,7 +271,7 @@ class Solver:
         self.workspace = workspace
         self._cols = _cols_struct(dc)
         self._out = Outputs()
-        for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes"):
+        for name in ("pops", "history", "n_iter", "status", "spectrum", "psi_star", "stokes", "psi_ray"):
             ten = getattr(self, name)
             setattr(self._out, name, ten.data_ptr() if ten is not None else None)
 
@@ -300,6 +303,8 @@ class Solver:
             out["psi_star"] = self.psi_star
         if self.stokes is not None:
             out["stokes"] = self.stokes
+        if self.psi_ray is not None:
+            out["psi_ray"] = self.psi_ray
         return out
 
 
@@ -340,7 +345,7 @@ def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stre
         sub = DeviceColumns(offset=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64), init_pops=init, **fields)
         r = Solver(atom, sub, opts, want_spectrum=out.get("spectrum") is not None,
                    want_psi=out.get("psi_star") is not None, want_history=out.get("history") is not None,
-                   want_stokes=out.get("stokes") is not None).run(st)
+                   want_stokes=out.get("stokes") is not None, want_psi_ray=out.get("psi_ray") is not None).run(st)
         cb = torch.as_tensor(bad, dtype=torch.int64, device=dev)
         out["pops"].index_copy_(0, it, r.pops)
         if out.get("psi_star") is not None:
@@ -349,6 +354,8 @@ def resolve_failed(atom: Atom, dc: DeviceColumns, out: dict, opts: Options, stre
             out["spectrum"].index_copy_(0, cb, r.spectrum)
         if out.get("stokes") is not None:
             out["stokes"].index_copy_(0, cb, r.stokes)
+        if out.get("psi_ray") is not None:
+            out["psi_ray"].index_copy_(0, it, r.psi_ray)
         n1 = out["n_iter"].index_select(0, cb)
         if out.get("history") is not None:
             # the first attempt's n1 entries, then the second attempt's
