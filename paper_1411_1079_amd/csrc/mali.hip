@@ -144,7 +144,7 @@ __device__ __forceinline__ float d_cos(float x) { return __cosf(x); }
 // approximation in four regions of s = |v| + a (relative accuracy ~1e-4),
 // evaluated in the precision F.
 template <typename F>
-__device__ __noinline__ F voigt_w4(F a, F v) {
+__device__ __forceinline__ F voigt_w4_body(F a, F v) {
     using C = cplx_t<F>;
     const C t = {a, -v};          // t = a - i v
     const F s = fabs(v) + a;
@@ -191,6 +191,10 @@ __device__ __noinline__ F voigt_w4(F a, F v) {
     const F frac = cdiv_re(cmul(t, p), q);
     return d_exp(u.r) * d_cos(u.i) - frac;
 }
+// The same as a call (for the FP64 callers, whose registers it would
+// otherwise crowd); the FP32 profile preparation inlines the body.
+template <typename F>
+__device__ __noinline__ F voigt_w4(F a, F v) { return voigt_w4_body<F>(a, v); }
 
 template <typename R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -373,23 +377,35 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
         const R H = tr.voigt ? voigt_w4<R>(adamp, static_cast<R>(v)) : d_exp(static_cast<R>(-v * v));
         return H * static_cast<R>(pre);
     };
+    // FP32: v = ((nu - nu0) - nu0 vz/c mu) / dnu_D from the FP32 ray table,
+    // the Voigt function inlined
+    const float *pdnu = A.prof_dnu + r0, *pmusf = A.prof_musf + r0;
+    const float nvz = static_cast<float>(tr.nu0 * vzc), rdndf = static_cast<float>(rdnd);
+    const float pref = static_cast<float>(pre), adf = static_cast<float>(adamp);
+    const bool voigt = tr.voigt != 0;
+    auto profile32 = [&](float dnu, float mus) -> float {
+        const float v = (dnu - nvz * mus) * rdndf;
+        const float H = voigt ? voigt_w4_body<float>(adf, v) : d_exp(-v * v);
+        return H * pref;
+    };
     double acc = 0.0, tot;
     if (kHeld > 0 && nr <= kHeld * kWave) {
         R val[kHeld > 0 ? kHeld : 1];
         int dst[kHeld > 0 ? kHeld : 1];
 #pragma unroll
         for (int h0 = 0; h0 < kHeld; h0 += U) {
-            double nu[U], mus[U], w[U];
+            float dnu[U], musf[U];
+            double w[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int r = lane + (h0 + u) * kWave;
-                if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[h0 + u] = pdst[r]; }
+                if (r < nr) { dnu[u] = pdnu[r]; musf[u] = pmusf[r]; w[u] = pw[r]; dst[h0 + u] = pdst[r]; }
             }
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int r = lane + (h0 + u) * kWave;
                 if (r < nr) {
-                    val[h0 + u] = profile(r, nu[u], mus[u]);
+                    val[h0 + u] = static_cast<R>(profile32(dnu[u], musf[u]));
                     acc += w[u] * static_cast<double>(val[h0 + u]);
                 }
             }
@@ -406,17 +422,25 @@ __device__ void prep_profile_item(const RunArgs &a, int slot, int k, int t, int 
     } else {
         for (int r0 = lane; r0 < nr; r0 += U * kWave) {
             double nu[U], mus[U], w[U];
+            float dnu[U], musf[U];
             int dst[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int r = r0 + u * kWave;
-                if (r < nr) { nu[u] = pnu[r]; mus[u] = pmus[r]; w[u] = pw[r]; dst[u] = pdst[r]; }
+                if (r < nr) {
+                    if constexpr (sizeof(R) == 4) { dnu[u] = pdnu[r]; musf[u] = pmusf[r]; }
+                    else { nu[u] = pnu[r]; mus[u] = pmus[r]; }
+                    w[u] = pw[r];
+                    dst[u] = pdst[r];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int r = r0 + u * kWave;
                 if (r < nr) {
-                    const R ph = profile(r, nu[u], mus[u]);
+                    R ph;
+                    if constexpr (sizeof(R) == 4) ph = profile32(dnu[u], musf[u]);
+                    else ph = profile(r, nu[u], mus[u]);
                     acc += w[u] * static_cast<double>(ph);
                     phi[dst[u]] = ph;
                 }
@@ -2394,6 +2418,7 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bo
     // the Voigt approximation.
     {
         std::vector<double> pnu, pmus, pw;
+        std::vector<float> pdnu, pmusf;
         std::vector<int> poff(1, 0), pdst;
         for (int t = 0; t < D.n_lines; t++) {
             const auto &h = atom->tr[t];
@@ -2427,11 +2452,18 @@ int get_dev_atom(rh15d_atom *atom, int n_mu, SweepShape shape, DevAtom **out, bo
                 for (int r = 0; r < nq + na; r++) v[first + r] = w[ord[r]];
             };
             permute(pnu); permute(pmus); permute(pw); permute(pdst);
+            for (size_t r = first; r < pnu.size(); r++) {
+                pdnu.push_back(static_cast<float>(pnu[r] - h.nu0));
+                pmusf.push_back(static_cast<float>(pmus[r]));
+            }
             poff.push_back(static_cast<int>(pnu.size()));
         }
-        if (pnu.empty()) { pnu.push_back(0.0); pmus.push_back(0.0); pw.push_back(0.0); pdst.push_back(0); }
+        if (pnu.empty()) {
+            pnu.push_back(0.0); pmus.push_back(0.0); pw.push_back(0.0); pdst.push_back(0);
+            pdnu.push_back(0.0f); pmusf.push_back(0.0f);
+        }
         UP(pnu, &D.prof_nu); UP(pmus, &D.prof_mus); UP(pw, &D.prof_w); UP(poff, &D.prof_off);
-        UP(pdst, &D.prof_dst);
+        UP(pdst, &D.prof_dst); UP(pdnu, &D.prof_dnu); UP(pmusf, &D.prof_musf);
     }
     UP(H.groups, &D.groups);
     UP(H.lane_j, &D.lanes.j); UP(H.lane_m0, &D.lanes.m0);

@@ -120,6 +120,8 @@ struct DevAtom {
     // lines): place in the profile table's row, frequency, signed direction
     // cosine, quadrature weight
     int *prof_off, *prof_dst; double *prof_nu, *prof_mus, *prof_w;
+    float *prof_dnu, *prof_musf;  // the same rays in FP32: nu - nu0 of the ray's line, mu
+                                  // (for the FP32 profile table, without FP64 arithmetic)
     DevGroup *groups;
     DevLanes lanes;
     // rate keys per transition and per ordered transition pair (CSR)
