@@ -258,7 +258,8 @@ struct RunArgs {
     // partial frequency redistribution (prd = 1), sweep precision
     void *emis;               // [gc][psi_cols] emission profiles psi = rho phi of the PRD lines' rays
     void *ist;                // [gc][ist_cols] intensities of the stored rays (last sweep)
-    void *gtab;               // [gc][g_cols] redistribution weights g(j, j') of the PRD lines
+    void *gtab;               // [gc][g_cols] redistribution weights of the PRD lines, per line
+                              // [j'][j] = g(j <- j') (input frequency major)
     double *rho;              // [gc][sum of PRD n_act] new rho (between the two update kernels)
     int max_iter, ng_order, ng_delay, ng_period, start, esc_iter, prd;
     double tol, tol_fp, coll_scale, crs_f0, prd_eps0;
@@ -1342,11 +1343,28 @@ __global__ __launch_bounds__(64) void k_prd_tables(RunArgs a) {
             G[j2 * na + j] = r;
         }
         __syncthreads();
-        for (int j = lane; j < na; j += 64) {
+        // row sums of output frequency j first (every lane reads the whole,
+        // still symmetric table), then the weights stored transposed,
+        // G[j2 * na + j] = g(j <- j2), so that the rho update's lanes (one
+        // output frequency each) read consecutive addresses; each lane
+        // rewrites only its own column
+        double sums[kMaxPrdFreq / 64];
+#pragma unroll
+        for (int c = 0; c < kMaxPrdFreq / 64; c++) {
+            const int j = lane + 64 * c;
             double sum = 0.0;
-            for (int j2 = 0; j2 < na; j2++) sum += A.act_w[tr.act_off + j2] * static_cast<double>(G[j * na + j2]);
-            for (int j2 = 0; j2 < na; j2++)
-                G[j * na + j2] = static_cast<R>(A.act_w[tr.act_off + j2] * static_cast<double>(G[j * na + j2]) / sum);
+            if (j < na)
+                for (int j2 = 0; j2 < na; j2++) sum += A.act_w[tr.act_off + j2] * static_cast<double>(G[j * na + j2]);
+            sums[c] = sum;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kMaxPrdFreq / 64; c++) {
+            const int j = lane + 64 * c;
+            if (j < na)
+                for (int j2 = 0; j2 < na; j2++)
+                    G[j2 * na + j] =
+                        static_cast<R>(A.act_w[tr.act_off + j2] * static_cast<double>(G[j2 * na + j]) / sums[c]);
         }
         __syncthreads();
     }
@@ -1479,7 +1497,7 @@ __global__ __launch_bounds__(256) void k_prd_rho(RunArgs a) {
             rloc[c] = 1.0;
             if (ja < na) {
                 double sJ = 0.0;
-                for (int j2 = 0; j2 < na; j2++) sJ += static_cast<double>(G[ja * na + j2]) * sh[wv][j2];
+                for (int j2 = 0; j2 < na; j2++) sJ += static_cast<double>(G[j2 * na + ja]) * sh[wv][j2];
                 double r = isfinite(fac) ? 1.0 + fac * (sJ - Jbar) : 1.0;
                 r = r * eps + (1.0 - eps);
                 rloc[c] = r > 0.0 ? r : 0.0;
