@@ -47,9 +47,9 @@ HBM_PEAK_GBS = 8000.0
 # taken on: the JSON line reports null once that source has changed.
 SWEEP_TRAFFIC = {
     "source": "paper_1411_1079_amd/csrc/mali.hip",
-    "sha256": "1232baf3d362d9b94d3a7db6f15bc348dee2d6ef9477945251d33cd7605b405d",
-    "read_bytes": 23.42e9,
-    "written_bytes": 4.62e9,
+    "sha256": "5a5dbcac2630cfa320bcc834af6d3d55d146526f8dbdcee7244594bf571ae0f7",
+    "read_bytes": 23.32e9,
+    "written_bytes": 4.63e9,
     "summary": "profiles/k_sweep_fp32_learned_start_cube256_counters.md",
 }
 
@@ -498,6 +498,8 @@ def main():
     ap.add_argument("--accuracy-columns", type=int, default=128,
                     help="seeded random columns of the cube also solved by the oracle to 1e-10")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip the grid-optimisation measurement (profiler runs of one form)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (a reference kernel of known traffic for "
                          "hardware byte counters) and exit")
@@ -669,8 +671,9 @@ def main():
             out["forms"][f]["mlp"] = r["mlp"]
     if train_info is not None:
         out["network_training"] = train_info
-    out["grid_optimisation"] = grid_measure(rh, torch, atom, cols, fields, args.tol_fp)
-    log(f"grid optimisation: {out['grid_optimisation']}")
+    if not args.no_grid:
+        out["grid_optimisation"] = grid_measure(rh, torch, atom, cols, fields, args.tol_fp)
+        log(f"grid optimisation: {out['grid_optimisation']}")
     if tune:
         out["autotune"] = tune
     if not args.no_cpu_baseline:
