@@ -352,8 +352,9 @@ typedef struct {
  * height range), w_tau = 0.2. */
 int rh15d_default_grid_options(rh15d_grid_options *opt);
 
-/* Re-grid the columns in (init_pops is ignored; input columns may have up
- * to RH15D_GRID_MAX_INPUT points) into out.  Output buffers are caller-owned
+/* Re-grid the columns in (init_pops and the magnetic field are ignored: a
+ * caller with a field interpolates it onto the new heights itself; input
+ * columns may have up to RH15D_GRID_MAX_INPUT points) into out.  Output buffers are caller-owned
  * and must not overlap the input.  The depth offsets are uploaded before
  * the call returns (the call waits for work queued earlier on hip_stream);
  * the re-gridding itself is asynchronous on hip_stream.  Errors:

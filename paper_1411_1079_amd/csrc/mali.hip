@@ -95,28 +95,29 @@ __device__ __forceinline__ double rcp(double x) {
 // relative at 0.1) is below the FP32 rounding of the rest of the step.
 template <typename R>
 __device__ __forceinline__ void sc_weights(R x, R &e, R &wa, R &wb) {
-    const R thr = sizeof(R) == 8 ? R(1.0e-2) : R(0.1);
-    if (x < thr) {
-        if constexpr (sizeof(R) == 8) {
-            wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * (R(-1.0 / 120.0) +
-                 x * (R(1.0 / 720.0) + x * R(-1.0 / 5040.0))))));
-            wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
-                 x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
-        } else {
+    if constexpr (sizeof(R) == 4) {
+        // e from one exponential for both branches (lanes of a wavefront
+        // often take both: thin and thick rays side by side)
+        e = d_exp(-x);
+        if (x < R(0.1)) {
             wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * R(-1.0 / 120.0))));
             wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) + x * R(1.0 / 144.0)))));
+        } else {
+            // x >= 0.1: 1 - e^-x carries at most a few ulp of relative error
+            const R q = (R(1) - e) * __builtin_amdgcn_rcpf(x);
+            wb = R(1) - q;
+            wa = q - e;
         }
+    } else if (x < R(1.0e-2)) {
+        wb = x * (R(0.5) + x * (R(-1.0 / 6.0) + x * (R(1.0 / 24.0) + x * (R(-1.0 / 120.0) +
+             x * (R(1.0 / 720.0) + x * R(-1.0 / 5040.0))))));
+        wa = x * (R(0.5) + x * (R(-1.0 / 3.0) + x * (R(1.0 / 8.0) + x * (R(-1.0 / 30.0) +
+             x * (R(1.0 / 144.0) + x * R(-1.0 / 840.0))))));
         e = d_exp(-x);
-    } else if constexpr (sizeof(R) == 8) {
+    } else {
         const R one_m_e = -d_expm1(-x);
         const R q = one_m_e * rcp(x);
         e = R(1) - one_m_e;
-        wb = R(1) - q;
-        wa = q - e;
-    } else {
-        // x >= 0.1: 1 - e^-x carries at most a few ulp of relative error
-        e = d_exp(-x);
-        const R q = (R(1) - e) * __builtin_amdgcn_rcpf(x);
         wb = R(1) - q;
         wa = q - e;
     }
