@@ -325,10 +325,13 @@ __device__ void prep_point(const RunArgs &a, int slot, int k) {
     const double kbg = A.bg_kind == 1 ? A.c_bg * nH * ne * pow(T, -1.5) * exp(kBgTheta / T) : 0.0;
     a.kbg[gc] = kbg;
     R *rec = reinterpret_cast<R *>(a.rec) + gc * a.rec_w;
+    // spacings to the points above (rec[0]) and below (rec[3]): a sweep
+    // reads the one towards the previous point along its direction from the
+    // point's own record
     rec[0] = static_cast<R>(k == 0 ? 0.0 : a.z[g - 1] - a.z[g]);
     rec[1] = static_cast<R>(1.0 / T);
     rec[2] = static_cast<R>(kbg);
-    rec[3] = R(0);
+    rec[3] = static_cast<R>(k == cg.N - 1 ? 0.0 : a.z[g] - a.z[g + 1]);
     for (int c = 0; c < A.n_cont; c++) {
         const DevTransition &tr = A.tr[A.n_lines + c];
         const double gr = exp(lr[tr.l] - lr[tr.u]);
@@ -546,31 +549,100 @@ struct PrdIO {
     int psi_cols, ist_cols;
 };
 
-template <typename R, int NS, int MC, bool PRD = false>
-__device__ __forceinline__ void load_point(const R *__restrict__ recb, const R *__restrict__ popsb,
-                                           const R *__restrict__ phi, int rec_w, int L, int ray_cols,
-                                           const Slots<R, NS> &sl, const int *pb, int64_t g, int64_t gc,
-                                           int64_t gc_dz, PointIn<R, NS, MC> &p, const PrdIO<R> *pio = nullptr,
-                                           const int *psb = nullptr) {
-    const R *rec = recb + gc * rec_w;
+// Where one depth point's inputs start, as byte offsets from the bases the
+// sweep kernel receives: its record, its populations, its profile row and
+// (PRD) its emission-profile row.  The loads index the restrict-qualified
+// bases directly, so the compiler still sees that the sweep's own stores
+// cannot change them (and keeps the uniform ones scalar).
+struct PointRows {
+    int64_t rec, pops, phi, psi;
+};
+
+template <typename R>
+__device__ __forceinline__ const R *at_bytes(const R *base, int64_t off) {
+    return reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// Records and populations are not written while a sweep kernel runs:
+// read through the constant address space, uniform loads of them are
+// scalar loads whatever stores the kernel makes elsewhere.
+template <typename R>
+using const_as = const __attribute__((address_space(4))) R;
+
+template <typename R>
+__device__ __forceinline__ const_as<R> *at_bytes_c(const R *base, int64_t off) {
+    return (const_as<R> *)(reinterpret_cast<const char *>(base) + off);
+}
+template <typename R>
+__device__ __forceinline__ const_as<R> *at_bytes_c(const_as<R> *base, uint32_t off) {
+    return (const_as<R> *)((const __attribute__((address_space(4))) char *)base + off);
+}
+
+// The point's wavefront-uniform inputs (record fields and populations).
+// dzi: the record field with the spacing to the previous point along the
+// sweep (0 going down, 3 going up).
+template <typename R, int NS, int MC>
+__device__ __forceinline__ void load_uniform(const R *__restrict__ recb, const R *__restrict__ popsb,
+                                             const PointRows &rw, int dzi, const Slots<R, NS> &sl,
+                                             PointIn<R, NS, MC> &p) {
+    const_as<R> *rec = at_bytes_c(recb, rw.rec);
     p.invT = rec[1];
     p.kbg = rec[2];
-    p.dz = recb[gc_dz * rec_w];
-    const R *n = popsb + (sizeof(R) == 8 ? g : gc) * L;
-    const R *phirow = phi + gc * ray_cols;
+    // level and continuum fields as 32-bit byte offsets: the loads then
+    // take them as the scalar load's register offset
+    constexpr uint32_t sz = sizeof(R);
+    p.dz = *at_bytes_c<R>(rec, (uint32_t)dzi * sz);
+    const_as<R> *n = at_bytes_c(popsb, rw.pops);
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        p.nl[q] = n[sl.l[q]];
-        p.nu[q] = n[sl.u[q]];
-        p.gfac[q] = sl.kind[q] == 1 ? rec[kRecHead + sl.c[q]] : R(0);
+        p.nl[q] = *at_bytes_c<R>(n, (uint32_t)sl.l[q] * sz);
+        p.nu[q] = *at_bytes_c<R>(n, (uint32_t)sl.u[q] * sz);
+        p.gfac[q] = sl.kind[q] == 1 ? *at_bytes_c<R>(rec, (uint32_t)(kRecHead + sl.c[q]) * sz) : R(0);
+    }
+}
+
+// The lane's profile values at the point (and, PRD, its emission-profile
+// values).  A lane without line slot q reads its row's first value (a
+// valid address in any group with a line); ray_terms replaces it by 0.
+// An unconditional load, selected at its use, instead of a branch around
+// the load.
+template <typename R, int NS, int MC, bool PRD = false>
+__device__ __forceinline__ void load_profiles(const R *__restrict__ phi, const PointRows &rw, const Slots<R, NS> &sl,
+                                              const int *pb, PointIn<R, NS, MC> &p, const PrdIO<R> *pio = nullptr,
+                                              const int *psb = nullptr) {
+    const R *phirow = at_bytes(phi, rw.phi);
 #pragma unroll
-        for (int r = 0; r < MC; r++) p.ph[q][r] = (sl.kind[q] == 0 && pb[q] >= 0) ? phirow[pb[q] + r] : R(0);
+    for (int q = 0; q < NS; q++) {
+#pragma unroll
+        for (int r = 0; r < MC; r++)
+            p.ph[q][r] = sl.kind[q] == 0 ? phirow[(pb[q] >= 0 ? pb[q] : 0) + r] : R(0);
         if constexpr (PRD) {
-            const R *psirow = pio->psi + gc * pio->psi_cols;
+            const R *psirow = at_bytes(pio->psi, rw.psi);
 #pragma unroll
             for (int r = 0; r < MC; r++) p.ps[q][r] = (sl.kind[q] == 0 && psb[q] >= 0) ? psirow[psb[q] + r] : p.ph[q][r];
         }
     }
+}
+
+template <typename R, int NS, int MC, bool PRD = false>
+__device__ __forceinline__ void load_rows(const R *__restrict__ recb, const R *__restrict__ popsb,
+                                          const R *__restrict__ phi, const PointRows &rw, int dzi,
+                                          const Slots<R, NS> &sl, const int *pb, PointIn<R, NS, MC> &p,
+                                          const PrdIO<R> *pio = nullptr, const int *psb = nullptr) {
+    load_uniform<R, NS, MC>(recb, popsb, rw, dzi, sl, p);
+    load_profiles<R, NS, MC, PRD>(phi, rw, sl, pb, p, pio, psb);
+}
+
+// The offsets of the point with global depth index g (slot-local gc).
+template <typename R, bool PRD = false>
+__device__ __forceinline__ PointRows point_rows(int rec_w, int L, int ray_cols, int64_t g, int64_t gc,
+                                                const PrdIO<R> *pio = nullptr) {
+    PointRows rw;
+    rw.rec = gc * rec_w * (int64_t)sizeof(R);
+    rw.pops = (sizeof(R) == 8 ? g : gc) * L * (int64_t)sizeof(R);
+    rw.phi = gc * ray_cols * (int64_t)sizeof(R);
+    rw.psi = PRD ? gc * pio->psi_cols * (int64_t)sizeof(R) : 0;
+    return rw;
 }
 
 template <typename R, int NS, int MC>
@@ -607,16 +679,18 @@ struct RayPt {
     R vlu[NS], vul[NS], U[NS], cht[NS], ph[NS];
 };
 
+// pon[q]: the lane's wavelength lies in line slot q's active set (its
+// loaded profile value counts; otherwise the value is 0)
 template <typename R, int NS, int MC, bool PRD = false>
 __device__ __forceinline__ void ray_terms(const Slots<R, NS> &sl, const Shared<R, NS> &sh, const PointIn<R, NS, MC> &in,
-                                          int r, RayPt<R, NS> &p) {
+                                          const bool *pon, int r, RayPt<R, NS> &p) {
     R chi = sh.chi0, eta = sh.eta0;
 #pragma unroll
     for (int q = 0; q < NS; q++) {
         if (sl.kind[q] == 0) {
-            const R ph = in.ph[q][r];
+            const R ph = pon[q] ? in.ph[q][r] : R(0);
             // emission (spontaneous and stimulated) with psi for PRD lines
-            const R ps = PRD ? in.ps[q][r] : ph;
+            const R ps = PRD ? (pon[q] ? in.ps[q][r] : R(0)) : ph;
             p.ph[q] = ph;
             p.vlu[q] = sl.cblu[q] * ph;
             p.vul[q] = sl.cbul[q] * ps;
@@ -774,6 +848,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     const R hnu_k = static_cast<R>(A.lanes.hnu_k[li]);
     const R two_hnu3 = static_cast<R>(A.lanes.two_hnu3c2[li]);
     int pb[NS], psb[NS];
+    bool pon[NS];
     R kapj[NS], alpha[NS], wpsi[NS];
     PrdIO<R> pio{};
     int ist_base = -1;
@@ -787,6 +862,7 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
 #pragma unroll
     for (int q = 0; q < NS; q++) {
         pb[q] = A.lanes.pbase[li * kMaxSlots + q];
+        pon[q] = pb[q] >= 0;
         psb[q] = PRD ? A.lanes.psb[li * kMaxSlots + q] : -1;
         kapj[q] = static_cast<R>(A.lanes.kapj[li * kMaxSlots + q]);
         alpha[q] = static_cast<R>(A.lanes.alpha[li * kMaxSlots + q]);
@@ -860,27 +936,27 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
     };
     {
         PointIn<R, NS, MC> in0;
-        load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + k, gc0 + k, gc0 + k, in0, &pio,
-                                   psb);
+        load_rows<R, NS, MC, PRD>(rec, popsb, phi, point_rows<R, PRD>(rec_w, L, ray_cols, g0 + k, gc0 + k, &pio), 0,
+                                  sl, pb, in0, &pio, psb);
         Shared<R, NS> sh;
         shared_terms<R, NS, MC>(in0, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
         PointIn<R, NS, MC> in2;
         Shared<R, NS> sh2;
         R dzb = R(0);
         if (s_dir != 0) {
-            load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + N - 2, gc0 + N - 2,
-                                       gc0 + N - 1, in2, &pio, psb);
+            load_rows<R, NS, MC, PRD>(rec, popsb, phi, point_rows<R, PRD>(rec_w, L, ray_cols, g0 + N - 2, gc0 + N - 2, &pio),
+                                      3, sl, pb, in2, &pio, psb);
             shared_terms<R, NS, MC>(in2, sl, alpha, hnu_k, two_hnu3, lamfac, sh2);
             dzb = in2.dz;
         }
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS, MC, PRD>(sl, sh, in0, r, p);
+            ray_terms<R, NS, MC, PRD>(sl, sh, in0, pon, r, p);
             R I0 = R(0);
             if (s_dir != 0) {
                 RayPt<R, NS> p2;
-                ray_terms<R, NS, MC, PRD>(sl, sh2, in2, r, p2);
+                ray_terms<R, NS, MC, PRD>(sl, sh2, in2, pon, r, p2);
                 const R dtv = R(0.5) * (p.chi + p2.chi) * dzb;
                 I0 = dtv > R(0) ? sh.B + mu[r] * (sh.B - sh2.B) * rcp(dtv) : sh.B;
             }
@@ -894,19 +970,29 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         }
         emit();
     }
-    // the spacing to the previous point along the sweep is stored with the
-    // lower of the two points
-    const int dz_shift = step > 0 ? 0 : 1;
-    // one depth step from the inputs `cur` of the new point k
-    auto advance = [&](const PointIn<R, NS, MC> &cur) {
+    // the rows of consecutive points along the sweep are these many bytes apart
+    const int64_t st_rec = (int64_t)step * rec_w * (int64_t)sizeof(R);
+    const int64_t st_pop = (int64_t)step * L * (int64_t)sizeof(R);
+    const int64_t st_phi = (int64_t)step * ray_cols * (int64_t)sizeof(R);
+    const int64_t st_psi = PRD ? (int64_t)step * pio.psi_cols * (int64_t)sizeof(R) : 0;
+    // One depth step to the new point k.  Its wavefront-uniform inputs are
+    // read at the start of the step (scalar loads, whose short latency the
+    // other wavefronts cover); its profile values were loaded into `cur`
+    // one step earlier.
+    PointRows urow = point_rows<R, PRD>(rec_w, L, ray_cols, g0 + k + step, gc0 + k + step, &pio);
+    const int dzi = step > 0 ? 0 : 3;   // the record field with the spacing to the previous point
+    auto advance = [&](PointIn<R, NS, MC> &cur) {
         k += step;
+        load_uniform<R, NS, MC>(rec, popsb, urow, dzi, sl, cur);
+        urow.rec += st_rec;
+        urow.pops += st_pop;
         Shared<R, NS> sh;
         shared_terms<R, NS, MC>(cur, sl, alpha, hnu_k, two_hnu3, lamfac, sh);
         const R dz = cur.dz;
 #pragma unroll
         for (int r = 0; r < MC; r++) {
             RayPt<R, NS> p;
-            ray_terms<R, NS, MC, PRD>(sl, sh, cur, r, p);
+            ray_terms<R, NS, MC, PRD>(sl, sh, cur, pon, r, p);
             const R x = (chi_p[r] + p.chi) * dz * hinvmu[r];
             R e, wa, wb;
             sc_weights<R>(x, e, wa, wb);
@@ -923,20 +1009,33 @@ __device__ __forceinline__ void sweep_group(const RunArgs &a, int grp, int slot,
         }
         emit();
     };
-    auto load = [&](int kk, PointIn<R, NS, MC> &dst) {
-        load_point<R, NS, MC, PRD>(rec, popsb, phi, rec_w, L, ray_cols, sl, pb, g0 + kk, gc0 + kk, gc0 + kk + dz_shift,
-                                   dst, &pio, psb);
+    // The profile values (vector loads) are read one step ahead of their
+    // use, in depth order along the sweep: the rows of the next point to
+    // load advance by one point per load.  Past the column's last point
+    // they stay on it (a repeated load whose values are not used), so the
+    // loads are unconditional and neither input buffer has to keep its old
+    // contents on some path.
+    const int k1 = N > 1 ? k + step : k;   // the first point to load (the only one of a 1-point column)
+    PointRows nxt = point_rows<R, PRD>(rec_w, L, ray_cols, g0 + k1, gc0 + k1, &pio);
+    int rows_left = N - 1;
+    auto load = [&](PointIn<R, NS, MC> &dst) {
+        load_profiles<R, NS, MC, PRD>(phi, nxt, sl, pb, dst, &pio, psb);
+        const bool more = --rows_left > 0;
+        nxt.rec += more ? st_rec : 0;
+        nxt.pops += more ? st_pop : 0;
+        nxt.phi += more ? st_phi : 0;
+        if constexpr (PRD) nxt.psi += more ? st_psi : 0;
     };
-    // two input buffers used alternately (the loop is unrolled by two), so
-    // the inputs of the next point load into the buffer not in use and no
+    // two profile buffers used alternately (the loop is unrolled by two), so
+    // the values of the next point load into the buffer not in use and no
     // registers are copied between steps
     PointIn<R, NS, MC> ba, bb;
-    if (N > 1) load(k + step, ba);
+    load(ba);
     for (int i = 1; i < N; i += 2) {
-        if (i + 1 < N) load(k + 2 * step, bb);
+        load(bb);
         advance(ba);
         if (i + 1 >= N) break;
-        if (i + 2 < N) load(k + 2 * step, ba);
+        load(ba);
         advance(bb);
     }
 }
