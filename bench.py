@@ -47,9 +47,9 @@ HBM_PEAK_GBS = 8000.0
 # taken on: the JSON line reports null once that source has changed.
 SWEEP_TRAFFIC = {
     "source": "paper_1411_1079_amd/csrc/mali.hip",
-    "sha256": "e0035fd8406b6ce1bb8410b22892ab0ff9ae06e7052974be6f3f2d00fef84a75",
-    "read_bytes": 23.33e9,
-    "written_bytes": 4.57e9,
+    "sha256": "39bd161138b3ce9e151b9d2b80b0922f2f7afe12726526d4a7596ae6b08200c1",
+    "read_bytes": 24.20e9,
+    "written_bytes": 5.52e9,
     "summary": "profiles/k_sweep_fp32_learned_start_cube256_counters.md",
 }
 
