@@ -6,8 +6,8 @@
 //
 // Network: 36 inputs (a 9-point depth stencil, offsets 0, +-2, +-8, +-32,
 // +-128, of ln T, ln n_e, ln n_H and v_z / 10 km/s, z-scored) -> n_layers x n_hidden (SiLU) -> n_out.
-// Dense layers run on CDNA matrix cores: v_mfma_f32_16x16x16 with BF16
-// operands and FP32 accumulation.  Weights are rounded to BF16 when staged
+// Dense layers run on CDNA matrix cores: gfx950's v_mfma_f32_16x16x32_bf16
+// (16 x 16 outputs, 32-deep K per instruction) with FP32 accumulation.  Weights are rounded to BF16 when staged
 // in LDS; forward activations enter as two BF16 terms (hi + lo), backward
 // products round both operands to BF16.  Master weights, gradients and Adam
 // moments are FP32.
@@ -37,8 +37,23 @@ constexpr int kFeat = 4 * kStencil;   // 36
 constexpr int64_t kChunk = 1 << 18;   // samples per forward pass of a long inference
 constexpr int kMaxSplit = 64;         // most sample chunks of a weight-gradient product
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Operands of v_mfma_f32_16x16x32_bf16: lane l holds row (A) or column (B)
+// l % 16 and the 8 consecutive K indices 8 (l / 16) .. 8 (l / 16) + 7 of the
+// 32-deep block; the 16 x 16 FP32 result sits in lane l as rows
+// 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 bf16x8_of(const unsigned short (&v)[8]) {
+    bf16x8 r;
+#pragma unroll
+    for (int t = 0; t < 8; t++) r[t] = __builtin_bit_cast(__bf16, v[t]);
+    return r;
+}
 
 __device__ __forceinline__ unsigned short to_bf16(float f) {
     unsigned int u = __builtin_bit_cast(unsigned int, f);
@@ -107,26 +122,30 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
             Bs[r][c] = to_bf16(v);
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kBK; kk += 16) {
-            const int kb = kk + 4 * (lane >> 4);
-            bf16x4 af[2], al[2], bfr[2];
+        static_assert(kBK == 32, "one 32-deep MFMA block per K tile");
+        {
+            const int kb = 8 * (lane >> 4);
+            bf16x8 af[2], al[2], bfr[2];
 #pragma unroll
             for (int i = 0; i < 2; i++) {
-                const int row = wm + i * 16 + (lane & 15);
-                af[i] = bf16x4{(short)As[row][kb], (short)As[row][kb + 1], (short)As[row][kb + 2], (short)As[row][kb + 3]};
-                if (SA)
-                    al[i] = bf16x4{(short)Al[row][kb], (short)Al[row][kb + 1], (short)Al[row][kb + 2],
-                                   (short)Al[row][kb + 3]};
-                const int col = wn + i * 16 + (lane & 15);
-                bfr[i] = bf16x4{(short)Bs[kb][col], (short)Bs[kb + 1][col], (short)Bs[kb + 2][col], (short)Bs[kb + 3][col]};
+                const int row = wm + i * 16 + (lane & 15), col = wn + i * 16 + (lane & 15);
+                unsigned short va[8], vl[8], vb[8];
+#pragma unroll
+                for (int t = 0; t < 8; t++) {
+                    va[t] = As[row][kb + t];
+                    vl[t] = SA ? Al[row][kb + t] : (unsigned short)0;
+                    vb[t] = Bs[kb + t][col];
+                }
+                af[i] = bf16x8_of(va);
+                al[i] = bf16x8_of(vl);
+                bfr[i] = bf16x8_of(vb);
             }
 #pragma unroll
             for (int i = 0; i < 2; i++)
 #pragma unroll
                 for (int j = 0; j < 2; j++) {
-                    if (SA) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bfr[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    if (SA) acc[i][j] = mfma32(al[i], bfr[j], acc[i][j]);
+                    acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
                 }
         }
         __syncthreads();
@@ -199,36 +218,38 @@ constexpr int kMaxDense = 10;
 // (written once when the network is created), so the kernel reads it with
 // scalar loads instead of indexing a by-value argument array.
 struct FusedLayer {
-    int kp, np, nout, pad;              // fan-in and fan-out padded to 16, fan-out
+    int kp, np, nout, pad;              // fan-in padded to 32, fan-out padded to 16, fan-out
     const unsigned short *w;            // weights packed as MFMA B fragments
     const float *b;                     // biases (FP32 master copy)
 };
 
-// B fragments of a [K][N] weight matrix for v_mfma_f32_16x16x16bf16: block
-// (kb, nb) holds, for lane l, W[16 kb + 4 (l / 16) + t][16 nb + l % 16],
-// t = 0..3, as 4 consecutive BF16 values; zero outside the matrix.
+// B fragments of a [K][N] weight matrix for v_mfma_f32_16x16x32_bf16:
+// block (kb, nb) holds, for lane l, W[32 kb + 8 (l / 16) + t][16 nb + l % 16],
+// t = 0..7, as 8 consecutive BF16 values; zero outside the matrix.
 __global__ void k_pack_b(const float *W, int K, int N, int KB, int NB, unsigned short *out) {
-    const int64_t total = (int64_t)KB * NB * 256;
+    const int64_t total = (int64_t)KB * NB * 512;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int t = (int)(e & 3), lane = (int)((e >> 2) & 63);
-        const int64_t f = e >> 8;
+        const int t = (int)(e & 7), lane = (int)((e >> 3) & 63);
+        const int64_t f = e >> 9;
         const int nb = (int)(f % NB), kb = (int)(f / NB);
-        const int k = kb * 16 + 4 * (lane >> 4) + t, c = nb * 16 + (lane & 15);
+        const int k = kb * 32 + 8 * (lane >> 4) + t, c = nb * 16 + (lane & 15);
         out[e] = (k < K && c < N) ? to_bf16(W[(size_t)k * N + c]) : (unsigned short)0;
     }
 }
 
 // The same arithmetic as the layer-by-layer path (normalised input; per
-// 16-wide K block the LO then the HI half of the activations times the BF16
+// 32-deep K block the LO then the HI half of the activations times the BF16
 // weights; bias, SiLU), so the outputs agree bit for bit.  Wavefront w owns
 // the output blocks of 16 columns w, w + 4, ...; the weight fragments of the
-// next K block are loaded while the current block's MFMAs run.
+// next K block are loaded while the current block's MFMAs run.  Activation
+// columns between a layer's width and the next layer's 32-padded fan-in are
+// written as zeros.
 __global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict__ layers, int n_layers,
                                                    const float *feat, const float *mean, const float *istd, int64_t n,
                                                    float *out) {
     constexpr int RB = kFuseRows / 16;  // row blocks of 16 samples
-    __shared__ unsigned short Hh[kFuseRows][kFuseLd];
-    __shared__ unsigned short Hl[kFuseRows][kFuseLd];
+    __shared__ __align__(16) unsigned short Hh[kFuseRows][kFuseLd];
+    __shared__ __align__(16) unsigned short Hl[kFuseRows][kFuseLd];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t row0 = (int64_t)blockIdx.x * kFuseRows;
     const int kp0 = layers[0].kp;
@@ -244,22 +265,25 @@ __global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict_
     const int nout_last = layers[n_layers - 1].nout;
     for (int l = 0; l < n_layers; l++) {
         const FusedLayer &ly = layers[l];
-        const int KB = ly.kp / 16, NB = ly.np / 16, nout = ly.nout;
+        const int KB = ly.kp / 32, NB = ly.np / 16, nout = ly.nout;
         const bool last = l == n_layers - 1;
-        const uint2 *wf = reinterpret_cast<const uint2 *>(ly.w);
+        // output blocks written: the layer's, and for a hidden layer up to
+        // the next layer's 32-padded fan-in (zeros past the width)
+        const int NBW = last ? NB : (NB + 1) / 2 * 2;
+        const uint4 *wf = reinterpret_cast<const uint4 *>(ly.w);
         f32x4 acc[RB][4];
 #pragma unroll
         for (int i = 0; i < RB; i++)
 #pragma unroll
             for (int j = 0; j < 4; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        uint2 bnext[4];
+        uint4 bnext[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int nb = wave + 4 * j;
-            bnext[j] = nb < NB ? wf[(int64_t)nb * 64 + lane] : uint2{0u, 0u};
+            bnext[j] = nb < NB ? wf[(int64_t)nb * 64 + lane] : uint4{0u, 0u, 0u, 0u};
         }
         for (int kb = 0; kb < KB; kb++) {
-            uint2 bcur[4];
+            uint4 bcur[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) bcur[j] = bnext[j];
             if (kb + 1 < KB) {
@@ -269,22 +293,22 @@ __global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict_
                     if (nb < NB) bnext[j] = wf[((int64_t)(kb + 1) * NB + nb) * 64 + lane];
                 }
             }
-            const int k = kb * 16 + 4 * (lane >> 4);
-            bf16x4 ah[RB], al[RB];
+            const int k = kb * 32 + 8 * (lane >> 4);
+            bf16x8 ah[RB], al[RB];
 #pragma unroll
             for (int i = 0; i < RB; i++) {
                 const int row = i * 16 + (lane & 15);
-                ah[i] = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(&Hh[row][k]));
-                al[i] = __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2 *>(&Hl[row][k]));
+                ah[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&Hh[row][k]));
+                al[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&Hl[row][k]));
             }
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 if (wave + 4 * j < NB) {
-                    const bf16x4 bv = __builtin_bit_cast(bf16x4, bcur[j]);
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, bcur[j]);
 #pragma unroll
                     for (int i = 0; i < RB; i++) {
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bv, acc[i][j], 0, 0, 0);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bv, acc[i][j], 0, 0, 0);
+                        acc[i][j] = mfma32(al[i], bv, acc[i][j]);
+                        acc[i][j] = mfma32(ah[i], bv, acc[i][j]);
                     }
                 }
             }
@@ -294,7 +318,7 @@ __global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict_
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int nb = wave + 4 * j;
-            if (nb >= NB) continue;
+            if (nb >= NBW) continue;
             const int col = nb * 16 + (lane & 15);
             const float bc = col < nout ? bias[col] : 0.f;
 #pragma unroll
@@ -629,14 +653,14 @@ int rh15d_mlp_create(int n_hidden, int n_layers, int n_out, uint64_t seed, rh15d
     size_t pk = 0;
     for (size_t l = 0; l + 1 < p->dims.size(); l++) {
         p->pk_off.push_back(pk);
-        pk += (size_t)((p->dims[l] + 15) / 16 * 16) * ((p->dims[l + 1] + 15) / 16 * 16);
+        pk += (size_t)((p->dims[l] + 31) / 32 * 32) * ((p->dims[l + 1] + 15) / 16 * 16);
     }
     if (e == hipSuccess) e = hipMalloc(&p->packed, pk * sizeof(unsigned short));
     if (e == hipSuccess) e = hipMalloc(&p->layers, (p->dims.size() - 1) * sizeof(FusedLayer));
     if (e == hipSuccess) {
         std::vector<FusedLayer> ly(p->dims.size() - 1);
         for (size_t l = 0; l + 1 < p->dims.size(); l++) {
-            ly[l].kp = (p->dims[l] + 15) / 16 * 16;
+            ly[l].kp = (p->dims[l] + 31) / 32 * 32;
             ly[l].np = (p->dims[l + 1] + 15) / 16 * 16;
             ly[l].nout = p->dims[l + 1];
             ly[l].w = p->packed + p->pk_off[l];
@@ -759,8 +783,8 @@ int rh15d_mlp_forward(rh15d_mlp *p, const float *feat, int64_t n, float *out, vo
         if (n == 0) return RH15D_OK;
         // the weights change with every Adam step or set_params: pack them for this call
         for (int l = 0; l < L; l++) {
-            const int K = p->dims[l], N = p->dims[l + 1], KB = (K + 15) / 16, NB = (N + 15) / 16;
-            hipLaunchKernelGGL(k_pack_b, dim3(blocks_for((int64_t)KB * NB * 256)), dim3(256), 0, st,
+            const int K = p->dims[l], N = p->dims[l + 1], KB = (K + 31) / 32, NB = (N + 15) / 16;
+            hipLaunchKernelGGL(k_pack_b, dim3(blocks_for((int64_t)KB * NB * 512)), dim3(256), 0, st,
                                p->params + p->w_off[l], K, N, KB, NB, p->packed + p->pk_off[l]);
         }
         hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)((n + kFuseRows - 1) / kFuseRows)), dim3(256), 0, st,
