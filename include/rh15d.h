@@ -457,6 +457,20 @@ int rh15d_mlp_gradients(rh15d_mlp *mlp, const float *features, const float *targ
 int rh15d_mlp_train_step(rh15d_mlp *mlp, const float *features, const float *target, int64_t n, float lr,
                          float *loss, void *hip_stream);
 
+/* n_batches Adam steps, the same as rh15d_mlp_train_step on rows
+ * [b batch, (b + 1) batch) of features (DEVICE float [n_batches batch][36])
+ * and target (DEVICE float [n_batches batch][n_out]) with learning rate
+ * lr[b] (HOST float [n_batches], >= 0), b = 0 .. n_batches - 1 in order,
+ * and bitwise the same parameters.  One step is captured as a HIP graph on
+ * a stream of the handle and replayed once per batch (one launch per step
+ * instead of one per kernel); the replays are ordered after the work on
+ * hip_stream and hip_stream after them.  losses (DEVICE float [n_batches],
+ * may be NULL) receives each step's loss.  The captured step is kept for
+ * the next call with the same features, target, batch and losses; the
+ * call waits for the previous call's replays.  1 <= batch <= 262144. */
+int rh15d_mlp_train_batches(rh15d_mlp *mlp, const float *features, const float *target, int64_t batch,
+                            int n_batches, const float *lr, float *losses, void *hip_stream);
+
 /* Text of the calling thread's last failure ("" if none). */
 const char *rh15d_last_error(void);
 

@@ -36,6 +36,7 @@ constexpr int kStencil = 9;
 constexpr int kFeat = 4 * kStencil;   // 36
 constexpr int64_t kChunk = 1 << 18;   // samples per forward pass of a long inference
 constexpr int kMaxSplit = 64;         // most sample chunks of a weight-gradient product
+constexpr int kMseBlocks = 256;       // workgroups (and loss partials) of the squared-error kernel
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -167,9 +168,13 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *
             }
 }
 
-// dY = 2 (Y - T) / (n N); per-block partial sums of the squared error
-__global__ void k_mse(const float *Y, const float *T, float *dY, int64_t n, int N, double *partial) {
+// dY = 2 (Y - T) / (n N); per-block partial sums of the squared error.
+// ctr (a replayed training step, else NULL): the target rows start at row
+// ctr[0] * n of T.
+__global__ void k_mse(const float *Y, const float *T, float *dY, int64_t n, int N, double *partial,
+                      const int *ctr) {
     __shared__ double sh[256];
+    if (ctr) T += (int64_t)ctr[0] * n * N;
     double s = 0.0;
     const double scale = 2.0 / ((double)n * N);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -345,8 +350,16 @@ __global__ __launch_bounds__(256) void k_mlp_fused(const FusedLayer *__restrict_
     }
 }
 
+// sched (a replayed training step, else NULL): the step's learning rate and
+// bias corrections are sched[3 ctr[0] + 0, 1, 2].
 __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float eps, float c1, float c2, const float *sched, const int *ctr) {
+    if (sched) {
+        const float *q = sched + 3 * (int64_t)ctr[0];
+        lr = q[0];
+        c1 = q[1];
+        c2 = q[2];
+    }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = g[i];
         const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -356,6 +369,19 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, 
         w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     }
 }
+
+// Loss of a replayed training step: the squared-error partials summed in
+// order (as the host does for a single step), into losses[ctr[0]].
+__global__ void k_step_loss(const double *partial, int nb, int64_t n, int N, const int *ctr, float *losses) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; b++) s += partial[b];
+    losses[ctr[0]] = (float)(s / ((double)n * N));
+}
+
+// The cursor of replayed training steps: set, then advanced after each step.
+__global__ void k_set_counter(int *ctr, int v) { ctr[0] = v; }
+__global__ void k_advance_counter(int *ctr) { ctr[0] += 1; }
 
 // Raw stencil features of sample points (global depth indices; NULL = all
 // points in order), columns ragged with offsets doff: ln T, ln n_e, ln n_H and
@@ -389,7 +415,10 @@ __global__ void k_features(const int64_t *doff, int64_t n_columns, const double 
 }
 
 // (x - mean) / std per feature
-__global__ void k_normalize(const float *x, const float *mean, const float *istd, float *y, int64_t n) {
+// ctr (a replayed training step, else NULL): the rows start at row ctr[0] * n of x.
+__global__ void k_normalize(const float *x, const float *mean, const float *istd, float *y, int64_t n,
+                            const int *ctr) {
+    if (ctr) x += (int64_t)ctr[0] * n * kFeat;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * kFeat; i += (int64_t)gridDim.x * blockDim.x) {
         const int f = (int)(i % kFeat);
         y[i] = (x[i] - mean[f]) * istd[f];
@@ -465,6 +494,19 @@ struct rh15d_mlp {
     FusedLayer *layers = nullptr;              // device descriptors of the fused kernel
     double *partial = nullptr;              // reductions
     int dev = 0;
+    // rh15d_mlp_train_batches: one training step captured as a HIP graph on
+    // the handle's own stream and replayed once per batch; a device cursor
+    // selects the batch and the step's Adam scalars (sched).
+    hipStream_t tstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t texec = nullptr;
+    const float *g_feat = nullptr, *g_target = nullptr;  // what the captured step reads and writes
+    float *g_losses = nullptr;
+    int64_t g_batch = 0;
+    int *ctr = nullptr;
+    float *sched = nullptr;                 // device [sched_cap][3]: lr, c1, c2
+    int64_t sched_cap = 0;
+    std::vector<float> h_sched;
 };
 
 namespace {
@@ -547,8 +589,10 @@ void split_for(int64_t n, int M, int N, int *nsplit, int *chunk) {
 // layer's pre-activation Z and activation H for the backward pass and leaves
 // the output in p->Z.back(); inference keeps only H (the bias and SiLU are
 // applied in the GEMM epilogue) and writes the output layer to `out`.
-void forward(rh15d_mlp *p, const float *feat, int64_t n, bool training, float *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n * kFeat)), dim3(256), 0, st, feat, p->mean, p->istd, p->x, n);
+void forward(rh15d_mlp *p, const float *feat, int64_t n, bool training, float *out, hipStream_t st,
+             const int *ctr = nullptr) {
+    hipLaunchKernelGGL(k_normalize, dim3(blocks_for(n * kFeat)), dim3(256), 0, st, feat, p->mean, p->istd, p->x, n,
+                       ctr);
     const int L = (int)p->dims.size() - 1;
     const float *in = p->x;
     for (int l = 0; l < L; l++) {
@@ -567,11 +611,12 @@ void forward(rh15d_mlp *p, const float *feat, int64_t n, bool training, float *o
     }
 }
 
-int backward(rh15d_mlp *p, const float *target, int64_t n, float *loss, hipStream_t st) {
+int backward(rh15d_mlp *p, const float *target, int64_t n, float *loss, hipStream_t st, const int *ctr = nullptr) {
     const int L = (int)p->dims.size() - 1;
     const int nout = p->dims[L];
-    const int nb = 256;
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, p->Z[L - 1], target, p->dH[L - 1], n, nout, p->partial);
+    const int nb = kMseBlocks;
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, p->Z[L - 1], target, p->dH[L - 1], n, nout, p->partial,
+                       ctr);
     for (int l = L - 1; l >= 0; l--) {
         const int K = p->dims[l], N = p->dims[l + 1];
         const float *dZ = p->dH[l];  // includes silu'(Z[l]) for hidden layers (epilogue below)
@@ -689,6 +734,13 @@ void rh15d_mlp_free(rh15d_mlp *p) {
     (void)hipFree(p->params); (void)hipFree(p->grads); (void)hipFree(p->m); (void)hipFree(p->v);
     (void)hipFree(p->mean); (void)hipFree(p->istd); (void)hipFree(p->partial); (void)hipFree(p->packed);
     (void)hipFree(p->layers);
+    if (p->tstream) (void)hipStreamSynchronize(p->tstream);
+    if (p->texec) (void)hipGraphExecDestroy(p->texec);
+    if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+    if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+    if (p->tstream) (void)hipStreamDestroy(p->tstream);
+    (void)hipFree(p->ctr);
+    (void)hipFree(p->sched);
     delete p;
 }
 
@@ -822,7 +874,93 @@ int rh15d_mlp_train_step(rh15d_mlp *p, const float *feat, const float *target, i
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)p->step), c2 = 1.f - std::pow(b2, (float)p->step);
     hipLaunchKernelGGL(k_adam, dim3(blocks_for((int64_t)p->n_params)), dim3(256), 0, st, p->params, p->grads, p->m, p->v,
-                       (int64_t)p->n_params, lr, b1, b2, 1e-8f, c1, c2);
+                       (int64_t)p->n_params, lr, b1, b2, 1e-8f, c1, c2, nullptr, nullptr);
+    HIP_TRY(hipGetLastError());
+    return RH15D_OK;
+}
+
+int rh15d_mlp_train_batches(rh15d_mlp *p, const float *feat, const float *target, int64_t batch, int n_batches,
+                            const float *lr, float *losses, void *stream) {
+    if (!p || !feat || !target || !lr || batch < 1 || batch > kChunk || n_batches < 0) {
+        set_error("bad argument (1 <= batch <= %lld, n_batches >= 0)", (long long)kChunk);
+        return RH15D_EINVAL;
+    }
+    for (int b = 0; b < n_batches; b++)
+        if (!(lr[b] >= 0.f)) { set_error("learning rate %d must be >= 0", b); return RH15D_EINVAL; }
+    if (n_batches == 0) return RH15D_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t cap0 = p->cap;
+    int rc = ensure_cap(p, batch);
+    if (rc != RH15D_OK) return rc;
+    auto drop_graph = [&]() {
+        if (p->texec) (void)hipGraphExecDestroy(p->texec);
+        p->texec = nullptr;
+    };
+    if (!p->tstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&p->tstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+        HIP_TRY(hipMalloc(&p->ctr, sizeof(int)));
+    }
+    // the previous call's replays read h_sched (copied) and sched: let them finish
+    HIP_TRY(hipStreamSynchronize(p->tstream));
+    if (p->cap != cap0) drop_graph();   // activation buffers moved
+    if (p->sched_cap < n_batches) {
+        drop_graph();
+        (void)hipFree(p->sched);
+        p->sched = nullptr;
+        p->sched_cap = 0;
+        HIP_TRY(hipMalloc(&p->sched, (size_t)n_batches * 3 * sizeof(float)));
+        p->sched_cap = n_batches;
+    }
+    if (p->texec && (p->g_feat != feat || p->g_target != target || p->g_batch != batch || p->g_losses != losses))
+        drop_graph();
+    // the Adam scalars of every step, as rh15d_mlp_train_step computes them
+    const float b1 = 0.9f, b2 = 0.999f;
+    p->h_sched.resize((size_t)n_batches * 3);
+    for (int b = 0; b < n_batches; b++) {
+        const float step = (float)(p->step + 1 + b);
+        p->h_sched[3 * b] = lr[b];
+        p->h_sched[3 * b + 1] = 1.f - std::pow(b1, step);
+        p->h_sched[3 * b + 2] = 1.f - std::pow(b2, step);
+    }
+    // after the caller's work on its stream
+    HIP_TRY(hipEventRecord(p->ev_in, st));
+    HIP_TRY(hipStreamWaitEvent(p->tstream, p->ev_in, 0));
+    HIP_TRY(hipMemcpyAsync(p->sched, p->h_sched.data(), (size_t)n_batches * 3 * sizeof(float), hipMemcpyHostToDevice,
+                           p->tstream));
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, p->tstream, p->ctr, 0);
+    if (!p->texec) {
+        const int L = (int)p->dims.size() - 1;
+        HIP_TRY(hipStreamBeginCapture(p->tstream, hipStreamCaptureModeThreadLocal));
+        forward(p, feat, batch, true, nullptr, p->tstream, p->ctr);
+        rc = backward(p, target, batch, nullptr, p->tstream, p->ctr);
+        if (losses)
+            hipLaunchKernelGGL(k_step_loss, dim3(1), dim3(64), 0, p->tstream, p->partial, kMseBlocks, batch, p->dims[L],
+                               p->ctr, losses);
+        hipLaunchKernelGGL(k_adam, dim3(blocks_for((int64_t)p->n_params)), dim3(256), 0, p->tstream, p->params,
+                           p->grads, p->m, p->v, (int64_t)p->n_params, 0.f, b1, b2, 1e-8f, 1.f, 1.f, p->sched, p->ctr);
+        hipLaunchKernelGGL(k_advance_counter, dim3(1), dim3(1), 0, p->tstream, p->ctr);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(p->tstream, &graph);
+        if (rc != RH15D_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (ec != hipSuccess) { set_error("training step capture failed: %s", hipGetErrorString(ec)); return RH15D_EDEVICE; }
+        const hipError_t ei = hipGraphInstantiate(&p->texec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            p->texec = nullptr;
+            set_error("training step graph: %s", hipGetErrorString(ei));
+            return RH15D_EDEVICE;
+        }
+        p->g_feat = feat;
+        p->g_target = target;
+        p->g_batch = batch;
+        p->g_losses = losses;
+    }
+    for (int b = 0; b < n_batches; b++) HIP_TRY(hipGraphLaunch(p->texec, p->tstream));
+    p->step += n_batches;
+    HIP_TRY(hipEventRecord(p->ev_out, p->tstream));
+    HIP_TRY(hipStreamWaitEvent(st, p->ev_out, 0));
     HIP_TRY(hipGetLastError());
     return RH15D_OK;
 }

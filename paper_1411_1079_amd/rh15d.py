@@ -27,7 +27,7 @@ EXPORTS = (
     "rh15d_autotune", "rh15d_departures", "rh15d_pops_from_departures", "rh15d_mlp_create", "rh15d_mlp_free", "rh15d_mlp_n_params",
     "rh15d_mlp_get_params", "rh15d_mlp_set_params", "rh15d_mlp_get_grads", "rh15d_mlp_get_normalization",
     "rh15d_mlp_set_normalization", "rh15d_mlp_fit_normalization", "rh15d_mlp_features", "rh15d_mlp_forward",
-    "rh15d_mlp_gradients", "rh15d_mlp_train_step", "rh15d_solve_columns_static", "rh15d_static_workspace_bytes",
+    "rh15d_mlp_gradients", "rh15d_mlp_train_step", "rh15d_mlp_train_batches", "rh15d_solve_columns_static", "rh15d_static_workspace_bytes",
     "rh15d_default_grid_options", "rh15d_optimize_grid",
 )
 
@@ -127,6 +127,7 @@ def lib():
         L.rh15d_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.rh15d_mlp_gradients.argtypes = [vp, vp, vp, C.c_int64, fp, vp]
         L.rh15d_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, fp, vp]
+        L.rh15d_mlp_train_batches.argtypes = [vp, vp, vp, C.c_int64, C.c_int, fp, vp, vp]
         _lib = L
     return _lib
 
@@ -552,3 +553,20 @@ class MLP:
                                           feats.shape[0], float(lr), C.byref(loss) if want_loss else None,
                                           _stream(stream)))
         return loss.value if want_loss else None
+
+    def train_batches(self, feats, target, batch, lrs, losses=None, stream=None):
+        """Adam steps on consecutive batches of `batch` rows of feats/target,
+        step b with learning rate lrs[b]: the same as one train_step per
+        batch, replayed from one captured step.  losses (CUDA float32
+        [len(lrs)], optional) receives every step's loss."""
+        import torch
+        n = len(lrs)
+        assert feats.dtype == torch.float32 and feats.is_contiguous() and feats.shape[-1] == N_FEATURES
+        assert target.dtype == torch.float32 and target.is_contiguous()
+        assert feats.shape[0] >= n * batch and target.numel() >= n * batch * self.n_out
+        assert losses is None or (losses.dtype == torch.float32 and losses.is_cuda and losses.numel() >= n)
+        lr = (C.c_float * max(n, 1))(*[float(x) for x in lrs])
+        _check(lib().rh15d_mlp_train_batches(self._h, C.c_void_p(feats.data_ptr()), C.c_void_p(target.data_ptr()),
+                                             int(batch), n, lr,
+                                             C.c_void_p(losses.data_ptr()) if losses is not None else None,
+                                             _stream(stream)))

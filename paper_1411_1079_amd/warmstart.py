@@ -44,7 +44,8 @@ def train(atom: rh.Atom, dc: rh.DeviceColumns, pops, n_hidden=256, n_layers=3, s
 
     Adam with a cosine learning-rate decay from lr to 0; mini-batches are
     consecutive slices of a seeded permutation of the depth points,
-    reshuffled every epoch."""
+    reshuffled every epoch.  The steps of an epoch run as replays of one
+    captured training step (MLP.train_batches)."""
     import torch
     dev = dc.z.device
     P = dc.total_depth
@@ -64,18 +65,22 @@ def train(atom: rh.Atom, dc: rh.DeviceColumns, pops, n_hidden=256, n_layers=3, s
     batch = min(batch, P)
     per_epoch = max(1, P // batch)
     losses = []
+    loss_buf = torch.empty(per_epoch, dtype=torch.float32, device=dev)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    for s in range(steps):
+    s = 0
+    while s < steps:
         e, b = divmod(s, per_epoch)
         if b == 0 and e > 0:
             shuffle()
-        lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
-        want = s == 0 or s == steps - 1 or (log_every and s % log_every == 0)
-        loss = net.train_step(feats[b * batch:(b + 1) * batch], target[b * batch:(b + 1) * batch], lr_s,
-                              want_loss=bool(want), stream=stream)
+        n = min(per_epoch - b, steps - s)
+        lrs = [lr * 0.5 * (1.0 + math.cos(math.pi * (s + i) / steps)) for i in range(n)]
+        net.train_batches(feats[b * batch:], target[b * batch:], batch, lrs, losses=loss_buf, stream=stream)
+        want = [i for i in range(n) if s + i == 0 or s + i == steps - 1 or (log_every and (s + i) % log_every == 0)]
         if want:
-            losses.append((s, loss))
+            lv = loss_buf[:n].cpu().numpy()
+            losses += [(s + i, float(lv[i])) for i in want]
+        s += n
     torch.cuda.synchronize(dev)
     rep = TrainReport(points=P, steps=steps, batch=batch, seconds=time.perf_counter() - t0,
                       loss_first=losses[0][1], loss_last=losses[-1][1], losses=losses)

@@ -162,6 +162,38 @@ def test_training_tracks_fp64_adam():
     assert 0.5 * lo - 1e-4 <= lg <= 2.0 * lo + 1e-4
 
 
+@pytest.mark.parametrize("dims", [OM.dims_of(256, 3, 6), OM.dims_of(40, 2, 6)])
+def test_replayed_training_steps_match_single_steps(dims):
+    """train_batches (one captured step replayed per batch) gives bitwise the
+    parameters and losses of one train_step per batch: three calls, the
+    second on other rows (a new capture), the third on the first call's
+    rows and loss buffer again (the kept capture), with eager work between."""
+    batch, nb = 300, 5
+    x = synth.mlp_features(31, 4 * nb * batch)
+    mean, std = OM.normalization(x.astype(np.float64))
+    t = np.random.default_rng(4).normal(size=(x.shape[0], dims[-1])).astype(np.float32)
+    xt, tt = torch.as_tensor(x).cuda(), torch.as_tensor(t).cuda()
+    nets = []
+    for _ in range(2):
+        net, _ = _net(dims, seed=41)
+        net.set_normalization(mean.astype(np.float32), std.astype(np.float32))
+        nets.append(net)
+    ref, rep = nets
+    calls = [(0, 0.003), (2 * nb * batch, 0.002), (0, 0.001)]   # (first row, lr scale)
+    got_losses, want_losses = [], []
+    buf = torch.full((nb,), np.nan, dtype=torch.float32, device="cuda")
+    for c, (r0, lr) in enumerate(calls):
+        lrs = [lr * (1.0 - 0.1 * b) for b in range(nb)]
+        for b in range(nb):
+            rows = slice(r0 + b * batch, r0 + (b + 1) * batch)
+            want_losses.append(ref.train_step(xt[rows], tt[rows], lrs[b], want_loss=True))
+        rep.train_batches(xt[r0:], tt[r0:], batch, lrs, losses=buf)
+        got_losses += buf.cpu().numpy().tolist()
+        _ = (xt[:1000] * 2.0).sum().item()   # eager work between the calls
+        np.testing.assert_array_equal(rep.get_params(), ref.get_params(), err_msg=f"call {c}")
+    np.testing.assert_array_equal(np.float32(got_losses), np.float32(want_losses))
+
+
 def test_features_and_normalization():
     rh = _rh()
     cube = synth.cube_columns(1, 64, 64)
