@@ -140,3 +140,18 @@ def test_zeeman_atoms_load_on_host(atom_dir):
         a = rh15d.Atom(atom_dir[key])
         o = O.Atom(atom_dir[key])
         assert (a.n_levels, a.n_lines, a.n_continua, a.n_lambda) == (o.n_levels, o.n_lines, o.n_cont, o.n_lambda)
+
+
+def test_network_training_entries_reject_bad_arguments():
+    """The training entry points check their arguments before any HIP call:
+    a missing handle or buffer, a batch outside 1..262144, a negative batch
+    count."""
+    lib = rh15d.lib()
+    buf = np.zeros(64, dtype=np.float32)
+    p = buf.ctypes.data
+    lr = (C.c_float * 2)(1e-3, 1e-3)
+    assert lib.rh15d_mlp_train_batches(None, p, p, 4, 2, lr, None, None) == -1
+    assert lib.rh15d_mlp_train_step(None, p, p, 4, C.c_float(1e-3), None, None) == -1
+    assert lib.rh15d_mlp_gradients(None, p, p, 4, None, None) == -1
+    assert lib.rh15d_mlp_forward(None, p, 4, p, None) == -1
+    assert "argument" in lib.rh15d_last_error().decode()
