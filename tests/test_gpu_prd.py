@@ -100,3 +100,42 @@ def test_prd_fp32_form(atom_dir):
         lo, hi = int(cols.offset[c]), int(cols.offset[c + 1])
         np.testing.assert_allclose(g["pops"][lo:hi], r["pops"], rtol=1e-3)
         np.testing.assert_allclose(g["spectrum"][c], r["spectrum"], rtol=1e-3)
+
+
+def test_breakdown_and_switching_on_a_cube_column(atom_dir):
+    """A column of the full-stack workload (64 x 64 cube, column 1959, the
+    Ca II-like atom with both resonance lines in PRD, 5 angles) whose plain
+    PRD iteration breaks down in the oracle too: non-finite at iteration 41,
+    with the oracle's per-iteration changes up to there.  With the PRD
+    switching of Eq. 1 (eps0 = 0.01) the column converges, in the same
+    number of iterations as the oracle's, and within the stopping rule of
+    the oracle's answer; rh15d.resolve_failed with the switching option set
+    repairs the plain solve's result.  Expected values: the oracle's, in
+    tests/golden/prd_switching_column.json (written by the script beside
+    it)."""
+    import json
+    import os
+    from paper_1411_1079_amd import rh15d as rh
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "prd_switching_column.json")))
+    col = synth.cube_columns(1, 64, 64).column(gold["column"])
+    cols = synth.Columns.from_list([col])
+    kw = dict(n_mu=5, tol=1e-4, tol_fp=1e-4, prd=1)
+    g = _solve(atom_dir["ca2"], cols, max_iter=60, **kw)
+    assert g["status"][0] == gold["plain"]["status"] == rh.NONFINITE
+    assert g["n_iter"][0] == gold["plain"]["n_iter"]
+    h = np.array(gold["plain"]["history"])
+    np.testing.assert_allclose(g["history"][0, :len(h)], h, rtol=1e-6)
+    s = _solve(atom_dir["ca2"], cols, max_iter=400, prd_eps0=gold["eps0"], **kw)
+    sw = gold["switching"]
+    assert s["status"][0] == sw["status"] == rh.CONVERGED and s["n_iter"][0] == sw["n_iter"]
+    # both stop within about tol_fp of the same fixed point
+    np.testing.assert_allclose(s["pops"], np.array(sw["pops"]), rtol=3e-4)
+    np.testing.assert_allclose(s["spectrum"][0], np.array(sw["spectrum"]), rtol=3e-4)
+    # the failed plain result, solved again with switching
+    atom = rh.Atom(atom_dir["ca2"])
+    dc = rh.DeviceColumns.from_host(cols)
+    out = rh.solve(atom, dc, max_iter=60, **kw)
+    n = rh.resolve_failed(atom, dc, out, rh.default_options(max_iter=400, prd_eps0=gold["eps0"], **kw))
+    torch.cuda.synchronize()
+    assert n == 1 and int(out["status"][0]) == rh.CONVERGED
+    np.testing.assert_allclose(out["pops"].cpu().numpy(), s["pops"], rtol=0, atol=0)
